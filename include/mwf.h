@@ -1,0 +1,167 @@
+/*
+ * mwf.h -- messenger-field Wiener filtering of HEALPix maps on AMD MI355X (gfx950).
+ *
+ * Method: Elsner & Wandelt, "Fast Wiener filtering of CMB maps", Sect. 2.
+ * Data d = s + n (Eq. 1); the Wiener filter solves (S^-1 + N^-1) s = N^-1 d (Eq. 2).
+ * With a messenger field t of covariance T = tau * 1, tau = min(diag N), and
+ * Nbar = N - T, each sweep solves
+ *     Eq. (3)  (Nbar^-1 + (lambda T)^-1) t = Nbar^-1 d + (lambda T)^-1 s   in pixel space,
+ *     Eq. (4)  (S^-1 + (lambda T)^-1) s = (lambda T)^-1 t                  in harmonic space,
+ * with a spherical-harmonic transform pair in between; lambda is lowered to 1
+ * (Sect. 3), where the pair reduces to Eq. (2).
+ *
+ * Conventions used by every call below:
+ *   - Maps: HEALPix RING order, npix = 12 nside^2 values per map, maps of a
+ *     batch stored back to back (stride npix).
+ *   - alm: complex, interleaved (re, im), packed m-major: entry (l, m), 0 <= m <= l <= lmax,
+ *     sits at index m (2 lmax + 1 - m) / 2 + l; N_lm = (lmax+1)(lmax+2)/2 entries
+ *     per map, maps back to back (stride 2 N_lm reals). Y_lm carries the
+ *     Condon-Shortley phase. Only m >= 0 is stored (real fields).
+ *   - The forward transform is the pixel-area-weighted adjoint of the synthesis:
+ *     a_lm = Omega sum_p conj(Y_lm(p)) f_p, Omega = 4 pi / npix.
+ *   - Pixel noise: N is diagonal with inverse variance ninv[p] >= 0; ninv = 0
+ *     (or mask[p] = 0) marks an unobserved pixel. tau = 1 / max_p ninv[p].
+ *   - Harmonic filter of Eq. (4): s_lm = C_l / (C_l + lambda tau Omega) a_lm
+ *     (0 where C_l = 0); pixel step of Eq. (3): t = s + w (d - s) with
+ *     w_p = lambda tau ninv_p / (1 + (lambda - 1) tau ninv_p).
+ *   - Element type: double for WF_F64; float for WF_F32 and WF_BF16X3 (whose
+ *     Legendre contraction runs on bf16 matrix cores with a three-product
+ *     hi/lo split and fp32 accumulation). The Legendre recurrence is fp64 on
+ *     every path.
+ *   - Device pointers are HIP device memory owned by the caller; host pointers
+ *     are ordinary host memory, copied before the call returns.
+ *   - Calls that take a hip_stream (a hipStream_t, NULL = default stream) only
+ *     enqueue work and return; kernel faults surface at wf_sync().
+ *   - A plan is not thread-safe: drive each plan from one host thread.
+ *   - Every int-returning call returns WF_OK (0) or a negative WF_E* code;
+ *     wf_last_error() then holds a message (per host thread).
+ */
+#ifndef MWF_H
+#define MWF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  WF_OK = 0,
+  WF_EINVAL = -1,       /* invalid argument (message in wf_last_error)          */
+  WF_ENOMEM = -2,       /* device or host allocation failed / over budget        */
+  WF_EDEVICE = -3,      /* HIP runtime error                                      */
+  WF_EUNSUPPORTED = -4, /* valid request this build does not handle               */
+  WF_EBUSY = -5,        /* no free slot (serving)                                 */
+  WF_ENOTREADY = -6     /* result not finished yet (serving)                      */
+};
+
+enum { WF_F64 = 0, WF_F32 = 1, WF_BF16X3 = 2 };
+
+typedef struct wf_plan_s* wf_plan_t;
+
+typedef struct {
+  int32_t dtype;      /* WF_F64 (default), WF_F32 or WF_BF16X3                         */
+  int32_t max_batch;  /* largest nmaps accepted by the batched calls (>= 1; 0 -> 1)    */
+  int32_t flags;      /* reserved, must be 0                                           */
+  const char* tune_cache; /* reserved (may be NULL)                                    */
+} wf_plan_opts;
+
+typedef struct {
+  int32_t sweeps_done; /* sweeps enqueued by the last solve                            */
+  double chi2_last;    /* reserved (0)                                                  */
+  float ms_phaseA;     /* reserved (0)                                                  */
+  float ms_phaseB;     /* reserved (0)                                                  */
+} wf_stats;
+
+/*
+ * wf_plan -- build the geometry, coefficient tables and device work buffers for
+ * one (nside, lmax, C_l, N^-1, mask) problem (Sect. 2: T = min(diag N) fixes tau).
+ *   out      receives the plan handle (set to NULL on failure)
+ *   nside    HEALPix resolution, a power of two in [1, 1024]
+ *   lmax     band limit, 0 <= lmax <= 4 nside - 1 (and <= 2048)
+ *   cl       host, lmax+1 doubles, finite and >= 0 (signal power C_l; 0 filters the mode out)
+ *   ninv     host, npix doubles, finite and >= 0 (inverse noise variance per pixel)
+ *   mask     host, npix bytes, 1 = observed, 0 = unobserved (forces ninv = 0); NULL = all observed
+ *   opts     NULL for defaults
+ *   hip_stream stream used for the table uploads (the call synchronises it)
+ * Errors: WF_EINVAL (bad nside/lmax, non-finite or negative input, no observed
+ * pixel), WF_EUNSUPPORTED (dtype not built), WF_ENOMEM, WF_EDEVICE.
+ * The plan owns copies of everything; the caller keeps its arrays.
+ */
+int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl,
+            const double* ninv, const uint8_t* mask, const wf_plan_opts* opts,
+            void* hip_stream);
+
+/*
+ * wf_solve -- run the messenger iteration (Sect. 2) from s = t = 0, one sweep
+ * per entry of the lambda schedule (Sect. 3: lambda is lowered to 1).
+ *   d        device, npix elements of the plan dtype: the data map
+ *   s_wf     device, npix elements: receives the final signal map
+ *   s_alm    device, 2 N_lm elements, or NULL: receives the final filtered alm
+ *   lambda   host, nsweeps doubles, finite and > 0
+ *   nsweeps  >= 1
+ *   stats    NULL or receives counters
+ * Errors: WF_EINVAL (NULL pointers, bad schedule), WF_EDEVICE.
+ */
+int wf_solve(wf_plan_t plan, const void* d, void* s_wf, void* s_alm,
+             const double* lambda, int32_t nsweeps, void* hip_stream,
+             wf_stats* stats);
+
+/*
+ * wf_solve_batch -- wf_solve for nmaps independent data maps that share the
+ * plan's C_l, N^-1 and mask (d, s_wf: nmaps * npix; s_alm: nmaps * 2 N_lm).
+ * 1 <= nmaps <= max_batch.
+ */
+int wf_solve_batch(wf_plan_t plan, int32_t nmaps, const void* d, void* s_wf,
+                   void* s_alm, const double* lambda, int32_t nsweeps,
+                   void* hip_stream, wf_stats* stats);
+
+/*
+ * sht_map2alm -- forward transform of nmaps maps: a_lm = Omega sum_p conj(Y_lm(p)) f_p
+ * (the basis change of Sect. 2 from pixels to harmonics).
+ *   map  device, nmaps * npix elements; alm device, nmaps * 2 N_lm elements.
+ */
+int sht_map2alm(wf_plan_t plan, int32_t nmaps, const void* map, void* alm,
+                void* hip_stream);
+
+/*
+ * sht_alm2map -- synthesis f_p = sum_lm a_lm Y_lm(p) of nmaps real fields
+ * (the basis change back to pixels). a_l0 must be real; its imaginary part is ignored.
+ */
+int sht_alm2map(wf_plan_t plan, int32_t nmaps, const void* alm, void* map,
+                void* hip_stream);
+
+/*
+ * wf_footprint -- device bytes a plan of this shape with max_batch = nmaps would
+ * hold (tables + work buffers), for admission control. Host-only.
+ */
+int wf_footprint(int32_t nside, int32_t lmax, int32_t dtype, int32_t nmaps,
+                 size_t* bytes);
+
+/* wf_plan_info -- npix, N_lm and tau of a plan (any pointer may be NULL). */
+int wf_plan_info(wf_plan_t plan, int64_t* npix, int64_t* nalm, double* tau);
+
+/*
+ * wf_pixel_angles -- colatitude theta and longitude phi of every pixel centre of
+ * HEALPix RING order at this nside (host arrays of npix doubles).
+ */
+int wf_pixel_angles(int32_t nside, double* theta, double* phi);
+
+/* wf_sync -- wait for the plan's stream work; reports asynchronous device errors. */
+int wf_sync(wf_plan_t plan);
+
+/* wf_destroy -- free a plan and its device memory (NULL is accepted). */
+void wf_destroy(wf_plan_t plan);
+
+/* wf_strerror -- static text for a status code. */
+const char* wf_strerror(int status);
+
+/* wf_last_error -- detail of the last failure on this host thread ("" if none). */
+const char* wf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MWF_H */

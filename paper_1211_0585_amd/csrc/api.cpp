@@ -1,0 +1,610 @@
+// Host runtime and C ABI of libmwf: plan construction (geometry, coefficient
+// tables, polar-skip work lists, device buffers) and the sweep driver of the
+// messenger iteration (Elsner & Wandelt, Sect. 2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mwf_internal.hpp"
+
+namespace mwf {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+}  // namespace mwf
+
+using namespace mwf;
+
+struct wf_plan_s {
+  int nside = 0, lmax = 0, dtype = WF_F64, max_batch = 1;
+  int64_t npix = 0, nalm = 0;
+  int nrings = 0, npairs = 0;
+  double tau = 0.0, omega = 0.0;
+  hipStream_t stream = nullptr;       // plan-time uploads
+  hipStream_t last_stream = nullptr;  // stream of the last enqueued call
+  size_t lds_phase_b = 0;
+  int nitems = 0, nitems_m = 0;
+  std::vector<int32_t> n_active;
+  // device allocations
+  std::vector<void*> allocs;
+  RingPair* d_pairs = nullptr;
+  double* d_q = nullptr;
+  double* d_cl = nullptr;
+  double* d_A = nullptr;
+  double* d_C = nullptr;
+  int64_t* d_row_off = nullptr;
+  double* d_norm = nullptr;
+  int32_t* d_nact = nullptr;
+  int32_t* d_nblk = nullptr;
+  double2* d_tw = nullptr;
+  double2* d_blue = nullptr;
+  WorkItem* d_items = nullptr;     // all (m, blk), longest first
+  WorkItem* d_items_m = nullptr;   // (m, 0), one per m
+  double* d_G = nullptr;           // [batch][pair][m][4]
+  double* d_F = nullptr;
+  double2* d_partial = nullptr;    // [batch][blk][nalm]
+  PlanDev dev{};
+};
+
+namespace {
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+// In-place iterative radix-2 FFT in long double (host, plan time only).
+void host_fft(std::vector<std::complex<long double>>& a, int sign) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t k = 0; k < len / 2; ++k) {
+      const long double ang = sign * 2.0L * pi * (long double)k / (long double)len;
+      const std::complex<long double> w(cosl(ang), sinl(ang));
+      for (size_t i = k; i < n; i += len) {
+        const auto u = a[i], v = a[i + len / 2] * w;
+        a[i] = u + v;
+        a[i + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+// Ring geometry of the HEALPix RING scheme (Gorski et al. 2005), ring i = 1..4n-1.
+struct RingGeo {
+  double z;
+  int64_t start;
+  int32_t nphi, ph_num, ph_den;
+};
+
+RingGeo ring_geo(int n, int i) {
+  RingGeo g{};
+  const int64_t npix = 12LL * n * n;
+  if (i < n) {
+    g.z = 1.0 - (double)((int64_t)i * i) / (3.0 * n * n);
+    g.nphi = 4 * i;
+    g.ph_num = 1;
+    g.ph_den = 4 * i;
+    g.start = 2LL * i * (i - 1);
+  } else if (i <= 3 * n) {
+    g.z = 2.0 * (2 * n - i) / (3.0 * n);
+    g.nphi = 4 * n;
+    g.ph_num = (i - n + 1) % 2;
+    g.ph_den = 4 * n;
+    g.start = 2LL * n * (n - 1) + 4LL * n * (i - n);
+  } else {
+    const int ip = 4 * n - i;
+    g.z = -(1.0 - (double)((int64_t)ip * ip) / (3.0 * n * n));
+    g.nphi = 4 * ip;
+    g.ph_num = 1;
+    g.ph_den = 4 * ip;
+    g.start = npix - 2LL * ip * (ip + 1);
+  }
+  return g;
+}
+
+template <class T>
+int dev_alloc(wf_plan_s* p, T** ptr, size_t count) {
+  void* v = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(&v, count * sizeof(T));
+  if (e != hipSuccess)
+    return fail(e == hipErrorOutOfMemory ? WF_ENOMEM : WF_EDEVICE,
+                std::string("hipMalloc: ") + hipGetErrorString(e));
+  p->allocs.push_back(v);
+  *ptr = static_cast<T*>(v);
+  return WF_OK;
+}
+
+template <class T>
+int upload(wf_plan_s* p, T** ptr, const std::vector<T>& host) {
+  int rc = dev_alloc(p, ptr, host.size());
+  if (rc) return rc;
+  MWF_HIP(hipMemcpyAsync(*ptr, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice,
+                         p->stream));
+  return WF_OK;
+}
+
+size_t buffer_bytes(int nside, int lmax, int nmaps, int* ring_block_out, int* nblk_out) {
+  const int npairs = 2 * nside;
+  const int rb = npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256);
+  const int nblk = (npairs + rb - 1) / rb;
+  if (ring_block_out) *ring_block_out = rb;
+  if (nblk_out) *nblk_out = nblk;
+  const size_t nalm = (size_t)(lmax + 1) * (lmax + 2) / 2;
+  const size_t gf = (size_t)nmaps * npairs * (lmax + 1) * 4 * sizeof(double);
+  const size_t part = (size_t)nmaps * nblk * nalm * sizeof(double2);
+  return 2 * gf + part;
+}
+
+size_t table_bytes(int nside, int lmax) {
+  const size_t npix = 12ULL * nside * nside;
+  const size_t nalm = (size_t)(lmax + 1) * (lmax + 2) / 2;
+  const size_t rows = nalm + (size_t)(lmax + 1) * CHUNK;
+  // q, A, C, Bluestein (upper bound 16 n per cap ring pair), reach scratch
+  size_t blue = 0;
+  for (int i = 1; i < nside; ++i)
+    if (!is_pow2(4 * i)) blue += (size_t)1 << ilog2(8 * i - 1);
+  return npix * 8 + 2 * rows * 8 + blue * 16 + (size_t)(lmax + 1) * 2 * nside +
+         (size_t)(8 * nside + 64) * 16 + 64 * 1024;
+}
+
+int validate_plan_args(int nside, int lmax, const double* cl, const double* ninv, const wf_plan_opts* o) {
+  if (nside < 1 || nside > 1024 || !is_pow2(nside))
+    return fail(WF_EINVAL, "nside must be a power of two in [1, 1024]");
+  if (lmax < 0 || lmax > 4 * nside - 1 || lmax > 2048)
+    return fail(WF_EINVAL, "lmax must satisfy 0 <= lmax <= min(4 nside - 1, 2048)");
+  if (!cl || !ninv) return fail(WF_EINVAL, "cl and ninv must not be NULL");
+  if (o) {
+    if (o->dtype != WF_F64 && o->dtype != WF_F32 && o->dtype != WF_BF16X3)
+      return fail(WF_EINVAL, "unknown dtype");
+    if (o->max_batch < 0) return fail(WF_EINVAL, "max_batch must be >= 0");
+    if (o->flags != 0) return fail(WF_EINVAL, "flags must be 0");
+  }
+  return WF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wf_strerror(int status) {
+  switch (status) {
+    case WF_OK: return "ok";
+    case WF_EINVAL: return "invalid argument";
+    case WF_ENOMEM: return "out of memory";
+    case WF_EDEVICE: return "device error";
+    case WF_EUNSUPPORTED: return "unsupported";
+    case WF_EBUSY: return "busy";
+    case WF_ENOTREADY: return "not ready";
+    default: return "unknown status";
+  }
+}
+
+const char* wf_last_error(void) { return g_last_error.c_str(); }
+
+int wf_footprint(int32_t nside, int32_t lmax, int32_t dtype, int32_t nmaps, size_t* bytes) {
+  if (!bytes) return fail(WF_EINVAL, "bytes must not be NULL");
+  if (nmaps < 1) return fail(WF_EINVAL, "nmaps must be >= 1");
+  if (dtype != WF_F64 && dtype != WF_F32 && dtype != WF_BF16X3) return fail(WF_EINVAL, "unknown dtype");
+  if (nside < 1 || nside > 1024 || !is_pow2(nside) || lmax < 0 || lmax > 4 * nside - 1 || lmax > 2048)
+    return fail(WF_EINVAL, "bad nside / lmax");
+  *bytes = table_bytes(nside, lmax) + buffer_bytes(nside, lmax, nmaps, nullptr, nullptr);
+  return WF_OK;
+}
+
+int wf_pixel_angles(int32_t nside, double* theta, double* phi) {
+  if (nside < 1 || nside > 8192 || !is_pow2(nside)) return fail(WF_EINVAL, "nside must be a power of two in [1, 8192]");
+  if (!theta || !phi) return fail(WF_EINVAL, "theta and phi must not be NULL");
+  const double pi = 3.141592653589793238462643383279502884;
+  for (int i = 1; i <= 4 * nside - 1; ++i) {
+    const RingGeo g = ring_geo(nside, i);
+    const double th = std::acos(g.z);
+    const double ph0 = pi * g.ph_num / g.ph_den;
+    for (int j = 0; j < g.nphi; ++j) {
+      theta[g.start + j] = th;
+      phi[g.start + j] = ph0 + 2.0 * pi * j / g.nphi;
+    }
+  }
+  return WF_OK;
+}
+
+void wf_destroy(wf_plan_t p) {
+  if (!p) return;
+  hipStreamSynchronize(p->stream);
+  if (p->last_stream != p->stream) hipStreamSynchronize(p->last_stream);
+  for (void* v : p->allocs) hipFree(v);
+  delete p;
+}
+
+int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const double* ninv,
+            const uint8_t* mask, const wf_plan_opts* opts, void* hip_stream) {
+  if (!out) return fail(WF_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  int rc = validate_plan_args(nside, lmax, cl, ninv, opts);
+  if (rc) return rc;
+  const int dtype = opts ? opts->dtype : WF_F64;
+  if (dtype != WF_F64) return fail(WF_EUNSUPPORTED, "only WF_F64 plans are available in this build");
+  const int64_t npix = 12LL * nside * nside;
+  for (int l = 0; l <= lmax; ++l)
+    if (!std::isfinite(cl[l]) || cl[l] < 0) return fail(WF_EINVAL, "cl must be finite and >= 0");
+  double nmax = 0.0;
+  for (int64_t p = 0; p < npix; ++p) {
+    if (!std::isfinite(ninv[p]) || ninv[p] < 0) return fail(WF_EINVAL, "ninv must be finite and >= 0");
+    if ((!mask || mask[p]) && ninv[p] > nmax) nmax = ninv[p];
+  }
+  if (!(nmax > 0)) return fail(WF_EINVAL, "no observed pixel (all ninv == 0 or masked)");
+
+  wf_plan_s* p = new wf_plan_s();
+  p->nside = nside;
+  p->lmax = lmax;
+  p->dtype = dtype;
+  p->max_batch = (opts && opts->max_batch > 0) ? opts->max_batch : 1;
+  p->npix = npix;
+  p->nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
+  p->nrings = 4 * nside - 1;
+  p->npairs = 2 * nside;
+  p->tau = 1.0 / nmax;
+  p->omega = 4.0 * 3.141592653589793238462643383279502884 / (double)npix;
+  p->stream = static_cast<hipStream_t>(hip_stream);
+  auto bail = [&](int code) {
+    wf_destroy(p);
+    return code;
+  };
+
+  // ---- ring pairs, equator first
+  std::vector<RingPair> pairs(p->npairs);
+  std::vector<int> blue_len;        // distinct non-power-of-two ring lengths
+  int tw_len = 4;
+  size_t lds = 0;
+  for (int q = 0; q < p->npairs; ++q) {
+    const int i = 2 * nside - q;
+    const RingGeo gn = ring_geo(nside, i);
+    RingPair rp{};
+    rp.z = gn.z;
+    rp.sin_t = std::sqrt((1.0 - gn.z) * (1.0 + gn.z));
+    rp.start_n = gn.start;
+    rp.start_s = (q == 0) ? -1 : ring_geo(nside, 4 * nside - i).start;
+    rp.nphi = gn.nphi;
+    rp.ph_num = gn.ph_num;
+    rp.ph_den = gn.ph_den;
+    if (is_pow2(gn.nphi)) {
+      rp.log2n = ilog2(gn.nphi);
+      rp.bl_M = 0;
+      tw_len = std::max(tw_len, gn.nphi);
+      lds = std::max(lds, (size_t)gn.nphi * 16);
+    } else {
+      rp.log2n = -1;
+      rp.bl_M = 1 << ilog2(2 * gn.nphi - 1);
+      tw_len = std::max(tw_len, rp.bl_M);
+      lds = std::max(lds, (size_t)rp.bl_M * 16);
+      blue_len.push_back(gn.nphi);
+    }
+    pairs[q] = rp;
+  }
+  p->lds_phase_b = lds;
+
+  // Bluestein filter spectra: H = FFT_M(h), h_j = exp(+i pi j^2 / n) for |j| < n
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<double2> blue;
+  {
+    std::vector<int64_t> off_of(4 * nside + 1, -1);
+    for (int n : blue_len) {
+      if (off_of[n] >= 0) continue;
+      const int M = 1 << ilog2(2 * n - 1);
+      std::vector<std::complex<long double>> h(M, 0.0L);
+      for (int j = 0; j < n; ++j) {
+        const long double ang = pi * (long double)(((int64_t)j * j) % (2LL * n)) / (long double)n;
+        const std::complex<long double> w(cosl(ang), sinl(ang));
+        h[j] = w;
+        if (j) h[M - j] = w;
+      }
+      host_fft(h, -1);
+      off_of[n] = (int64_t)blue.size();
+      for (int k = 0; k < M; ++k) blue.push_back(make_double2((double)h[k].real(), (double)h[k].imag()));
+    }
+    for (auto& rp : pairs)
+      if (rp.log2n < 0) rp.bl_off = off_of[rp.nphi];
+    if (blue.empty()) blue.push_back(make_double2(0.0, 0.0));
+  }
+  std::vector<double2> tw(tw_len / 2);
+  for (int k = 0; k < tw_len / 2; ++k) {
+    const long double ang = -2.0L * pi * (long double)k / (long double)tw_len;
+    tw[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+  }
+
+  // ---- per-pixel tau * ninv (0 where unobserved)
+  std::vector<double> q(npix);
+  for (int64_t i = 0; i < npix; ++i) q[i] = (mask && !mask[i]) ? 0.0 : p->tau * ninv[i];
+
+  // ---- recurrence tables: rows per m, padded with CHUNK zeros
+  std::vector<int64_t> row_off(lmax + 1);
+  std::vector<double> A, C, norm(lmax + 1);
+  {
+    int64_t off = 0;
+    for (int m = 0; m <= lmax; ++m) {
+      row_off[m] = off;
+      off += (lmax - m + 1) + CHUNK;
+    }
+    A.assign(off, 0.0);
+    C.assign(off, 0.0);
+    long double nm = 1.0L / sqrtl(4.0L * pi);
+    for (int m = 0; m <= lmax; ++m) {
+      if (m > 0) nm *= -sqrtl((2.0L * m + 1.0L) / (2.0L * m));
+      norm[m] = (double)nm;
+      auto alpha = [&](int l) {
+        return sqrtl((4.0L * l * l - 1.0L) / ((long double)(l - m) * (long double)(l + m)));
+      };
+      const int64_t r = row_off[m];
+      long double c_lm2 = 1.0L, c_lm1 = 1.0L;   // C_{l-2}, C_{l-1}
+      A[r] = 0.0;
+      C[r] = 1.0;
+      if (m + 1 <= lmax) {
+        A[r + 1] = (double)alpha(m + 1);
+        C[r + 1] = 1.0;
+      }
+      for (int l = m + 2; l <= lmax; ++l) {
+        const long double al = alpha(l), alm1 = alpha(l - 1);
+        const long double cl_ = c_lm2 * al / alm1;
+        A[r + (l - m)] = (double)(al * c_lm1 / cl_);
+        C[r + (l - m)] = (double)cl_;
+        c_lm2 = c_lm1;
+        c_lm1 = cl_;
+      }
+    }
+  }
+
+  // ---- uploads
+  if ((rc = upload(p, &p->d_pairs, pairs))) return bail(rc);
+  if ((rc = upload(p, &p->d_q, q))) return bail(rc);
+  const std::vector<double> cl_host(cl, cl + lmax + 1);
+  if ((rc = upload(p, &p->d_cl, cl_host))) return bail(rc);
+  if ((rc = upload(p, &p->d_A, A))) return bail(rc);
+  if ((rc = upload(p, &p->d_C, C))) return bail(rc);
+  if ((rc = upload(p, &p->d_row_off, row_off))) return bail(rc);
+  if ((rc = upload(p, &p->d_norm, norm))) return bail(rc);
+  if ((rc = upload(p, &p->d_tw, tw))) return bail(rc);
+  if ((rc = upload(p, &p->d_blue, blue))) return bail(rc);
+
+  int ring_block = 0, nblk_max = 0;
+  buffer_bytes(nside, lmax, p->max_batch, &ring_block, &nblk_max);
+
+  PlanDev& D = p->dev;
+  D.nside = nside;
+  D.lmax = lmax;
+  D.npairs = p->npairs;
+  D.nrings = p->nrings;
+  D.npix = npix;
+  D.nalm = p->nalm;
+  D.tau = p->tau;
+  D.omega = p->omega;
+  D.ring_block = ring_block;
+  D.nblk_max = nblk_max;
+  D.pairs = p->d_pairs;
+  D.q = p->d_q;
+  D.cl = p->d_cl;
+  D.A = p->d_A;
+  D.C = p->d_C;
+  D.row_off = p->d_row_off;
+  D.norm_m = p->d_norm;
+  D.twiddle = p->d_tw;
+  D.tw_len = tw_len;
+  D.bluestein = p->d_blue;
+
+  // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range
+  {
+    uint8_t* d_reach = nullptr;
+    void* raw = nullptr;
+    MWF_HIP(hipMalloc(&raw, (size_t)(lmax + 1) * p->npairs));
+    d_reach = static_cast<uint8_t*>(raw);
+    hipError_t e = launch_reach(D, d_reach, p->stream);
+    std::vector<uint8_t> reach((size_t)(lmax + 1) * p->npairs);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(reach.data(), d_reach, reach.size(), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    hipFree(raw);
+    if (e != hipSuccess) {
+      set_error(std::string("plan reach kernel: ") + hipGetErrorString(e));
+      return bail(WF_EDEVICE);
+    }
+    p->n_active.assign(lmax + 1, 0);
+    for (int m = 0; m <= lmax; ++m) {
+      int na = 0;
+      for (int qq = 0; qq < p->npairs; ++qq)
+        if (reach[(size_t)m * p->npairs + qq]) na = qq + 1;
+      p->n_active[m] = na;
+    }
+  }
+  std::vector<int32_t> nblk(lmax + 1);
+  std::vector<WorkItem> items, items_m;
+  std::vector<double> cost;
+  for (int m = 0; m <= lmax; ++m) {
+    nblk[m] = (p->n_active[m] + ring_block - 1) / ring_block;
+    items_m.push_back({m, 0});
+    for (int b = 0; b < nblk[m]; ++b) items.push_back({m, b});
+  }
+  // longest items first so that the hardware dispatcher balances the tail
+  std::stable_sort(items.begin(), items.end(), [&](const WorkItem& a, const WorkItem& b) {
+    auto c = [&](const WorkItem& w) {
+      const int rings = std::min(ring_block, p->n_active[w.m] - w.blk * ring_block);
+      return (double)(lmax - w.m + 1) * (double)std::max(rings, 1);
+    };
+    return c(a) > c(b);
+  });
+  if (items.empty()) items.push_back({0, 0});
+  p->nitems = (int)items.size();
+  p->nitems_m = (int)items_m.size();
+  if ((rc = upload(p, &p->d_nact, p->n_active))) return bail(rc);
+  if ((rc = upload(p, &p->d_nblk, nblk))) return bail(rc);
+  if ((rc = upload(p, &p->d_items, items))) return bail(rc);
+  if ((rc = upload(p, &p->d_items_m, items_m))) return bail(rc);
+  D.n_active = p->d_nact;
+  D.nblk = p->d_nblk;
+
+  // ---- work buffers
+  const size_t gf = (size_t)p->max_batch * p->npairs * (lmax + 1) * 4;
+  if ((rc = dev_alloc(p, &p->d_G, gf))) return bail(rc);
+  if ((rc = dev_alloc(p, &p->d_F, gf))) return bail(rc);
+  if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->max_batch * nblk_max * p->nalm))) return bail(rc);
+  // F entries of skipped (m, ring pair) combinations are never written: keep them zero
+  if (hipMemsetAsync(p->d_F, 0, gf * sizeof(double), p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess) {
+    set_error("initialising work buffers failed");
+    return bail(WF_EDEVICE);
+  }
+  *out = p;
+  return WF_OK;
+}
+
+int wf_plan_info(wf_plan_t p, int64_t* npix, int64_t* nalm, double* tau) {
+  if (!p) return fail(WF_EINVAL, "plan must not be NULL");
+  if (npix) *npix = p->npix;
+  if (nalm) *nalm = p->nalm;
+  if (tau) *tau = p->tau;
+  return WF_OK;
+}
+
+int wf_sync(wf_plan_t p) {
+  if (!p) return fail(WF_EINVAL, "plan must not be NULL");
+  MWF_HIP(hipStreamSynchronize(p->stream));
+  if (p->last_stream != p->stream) MWF_HIP(hipStreamSynchronize(p->last_stream));
+  MWF_HIP(hipGetLastError());
+  return WF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, const double* d,
+                const double* map_in, double* map_out) {
+  PhaseBArgs a{};
+  a.mode = mode;
+  a.nmaps = nmaps;
+  a.lambda = lam;
+  a.F = p->d_F;
+  a.G = p->d_G;
+  a.d = d;
+  a.map_in = map_in;
+  a.map_out = map_out;
+  MWF_HIP(launch_phase_b_f64(p->dev, a, p->lds_phase_b, s));
+  return WF_OK;
+}
+
+int run_analysis(wf_plan_s* p, hipStream_t s, int nmaps) {
+  MWF_HIP(launch_legendre_analysis_f64(p->dev, p->d_items, p->nitems, nmaps, p->d_G, p->d_partial, s));
+  return WF_OK;
+}
+
+int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam,
+                  const double2* alm_in, double2* alm_out) {
+  SynthArgs a{};
+  a.mode = mode;
+  a.nmaps = nmaps;
+  a.lambda = lam;
+  a.partial = p->d_partial;
+  a.alm_in = alm_in;
+  a.alm_out = alm_out;
+  a.F = p->d_F;
+  const bool alm_only = (mode == SY_ALM_ONLY);
+  MWF_HIP(launch_legendre_synthesis_f64(p->dev, alm_only ? p->d_items_m : p->d_items,
+                                        alm_only ? p->nitems_m : p->nitems, a, s));
+  return WF_OK;
+}
+
+int check_batch(wf_plan_s* p, int nmaps) {
+  if (!p) return fail(WF_EINVAL, "plan must not be NULL");
+  if (nmaps < 1 || nmaps > p->max_batch)
+    return fail(WF_EINVAL, "nmaps must be in [1, max_batch] (max_batch = " +
+                               std::to_string(p->max_batch) + ")");
+  return WF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* s_alm,
+                   const double* lambda, int32_t nsweeps, void* hip_stream, wf_stats* stats) {
+  int rc = check_batch(p, nmaps);
+  if (rc) return rc;
+  if (!d || !s_wf) return fail(WF_EINVAL, "d and s_wf must not be NULL");
+  if (!lambda || nsweeps < 1) return fail(WF_EINVAL, "need a schedule of at least one lambda");
+  for (int k = 0; k < nsweeps; ++k)
+    if (!std::isfinite(lambda[k]) || !(lambda[k] > 0))
+      return fail(WF_EINVAL, "every lambda must be finite and > 0");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  p->last_stream = s;
+  const double* dd = static_cast<const double*>(d);
+  for (int k = 0; k < nsweeps; ++k) {
+    const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
+    if ((rc = run_phase_b(p, s, mode, nmaps, lambda[k], dd, nullptr, nullptr))) return rc;
+    if ((rc = run_analysis(p, s, nmaps))) return rc;
+    double2* alm_out = (k == nsweeps - 1) ? static_cast<double2*>(s_alm) : nullptr;
+    if ((rc = run_synthesis(p, s, SY_FROM_PARTIAL, nmaps, lambda[k], nullptr, alm_out))) return rc;
+  }
+  if ((rc = run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr,
+                        static_cast<double*>(s_wf))))
+    return rc;
+  if (stats) {
+    stats->sweeps_done = nsweeps;
+    stats->chi2_last = 0.0;
+    stats->ms_phaseA = stats->ms_phaseB = 0.0f;
+  }
+  return WF_OK;
+}
+
+int wf_solve(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const double* lambda,
+             int32_t nsweeps, void* hip_stream, wf_stats* stats) {
+  return wf_solve_batch(p, 1, d, s_wf, s_alm, lambda, nsweeps, hip_stream, stats);
+}
+
+int sht_map2alm(wf_plan_t p, int32_t nmaps, const void* map, void* alm, void* hip_stream) {
+  int rc = check_batch(p, nmaps);
+  if (rc) return rc;
+  if (!map || !alm) return fail(WF_EINVAL, "map and alm must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  p->last_stream = s;
+  if ((rc = run_phase_b(p, s, PB_READ_MAP | PB_ANALYSIS, nmaps, 1.0, nullptr,
+                        static_cast<const double*>(map), nullptr)))
+    return rc;
+  if ((rc = run_analysis(p, s, nmaps))) return rc;
+  return run_synthesis(p, s, SY_ALM_ONLY, nmaps, 1.0, nullptr, static_cast<double2*>(alm));
+}
+
+int sht_alm2map(wf_plan_t p, int32_t nmaps, const void* alm, void* map, void* hip_stream) {
+  int rc = check_batch(p, nmaps);
+  if (rc) return rc;
+  if (!map || !alm) return fail(WF_EINVAL, "map and alm must not be NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  p->last_stream = s;
+  if ((rc = run_synthesis(p, s, SY_FROM_ALM, nmaps, 1.0, static_cast<const double2*>(alm), nullptr)))
+    return rc;
+  return run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr,
+                     static_cast<double*>(map));
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// Internal definitions shared by the host runtime and the HIP kernels of libmwf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mwf.h"
+
+namespace mwf {
+
+// ---------------------------------------------------------------- error handling
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+
+#define MWF_HIP(expr)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (expr);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      return ::mwf::fail(WF_EDEVICE, std::string(#expr) + ": " +             \
+                                         hipGetErrorString(e_));              \
+  } while (0)
+
+// ---------------------------------------------------------------- geometry
+// One iso-latitude ring pair: north ring i (1-based, i <= 2 nside) and its
+// mirror 4 nside - i in the south. Pair index q counts from the equator
+// (q = 0 is the equator ring, which has no partner) towards the north pole
+// (q = 2 nside - 1 is ring 1), so that rings near the poles, where the
+// Legendre functions of high m vanish, form a contiguous tail.
+struct RingPair {
+  double z;          // cos(theta) of the north ring
+  double sin_t;      // sin(theta)
+  int64_t start_n;   // first pixel of the north ring (RING order)
+  int64_t start_s;   // first pixel of the south ring, -1 for the equator
+  int32_t nphi;      // pixels per ring (same for both rings)
+  int32_t log2n;     // log2(nphi) if nphi is a power of two, else -1
+  int32_t ph_num;    // longitude of pixel 0 = pi * ph_num / ph_den
+  int32_t ph_den;
+  int32_t bl_M;      // Bluestein convolution length (0 for power-of-two rings)
+  int32_t pad_;
+  int64_t bl_off;    // offset (complex entries) of this length's filter in the Bluestein table
+};
+
+// Scaling of the Legendre recurrence: a value is carried as v * 2^(-SCALE_BITS * s)
+// with an integer s >= 0. While s > 0 the value is below 2^(64 - SCALE_BITS)
+// and contributes nothing; it is rescaled (s -= 1) when |v| exceeds 2^64.
+constexpr int SCALE_BITS = 512;
+constexpr int CHUNK = 16;            // l-steps per reduction chunk in phase A
+constexpr int LANES = 64;            // wavefront width on CDNA
+
+// Work item of the m-parallel phase: one m and one block of ring pairs.
+struct WorkItem {
+  int32_t m;
+  int32_t blk;
+};
+
+// Everything the kernels need, passed by value.
+struct PlanDev {
+  int32_t nside, lmax, npairs, nrings;
+  int64_t npix, nalm;
+  double tau, omega;
+  int32_t ring_block;        // ring pairs per phase-A work item (64 * R)
+  int32_t nblk_max;          // max work-item blocks per m
+  const RingPair* pairs;     // [npairs]
+  const double* q;           // [npix] tau * ninv (observed) or 0
+  const double* cl;          // [lmax+1]
+  const double* A;           // recurrence coefficients, padded rows (see row_off)
+  const double* C;           // lambda = C * mu
+  const int64_t* row_off;    // [lmax+1] start of row m in A / C (row length lmax-m+1+CHUNK)
+  const double* norm_m;      // [lmax+1] signed sectoral normalisation
+  const int32_t* n_active;   // [lmax+1] ring pairs with non-negligible lambda_lm
+  const int32_t* nblk;       // [lmax+1] work-item blocks of m
+  const double2* twiddle;    // exp(-2 pi i k / tw_len), k < tw_len / 2
+  int32_t tw_len;
+  int32_t pad_;
+  const double2* bluestein;  // FFT_M of the Bluestein chirp filter per distinct length
+};
+
+__host__ __device__ inline int64_t alm_index(int lmax, int l, int m) {
+  return (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
+}
+
+// ---------------------------------------------------------------- kernel launchers
+// Phase B (ring-parallel): synthesis ring FFTs, messenger update (Eq. 3), analysis FFTs.
+enum PhaseBMode : int32_t {
+  PB_SYNTH = 1,       // read F (E/O per m), inverse ring DFT
+  PB_UPDATE = 2,      // t = s + w (d - s)
+  PB_ANALYSIS = 4,    // forward ring DFT, write G (S/D per m)
+  PB_WRITE_MAP = 8,   // write the synthesised map (before the update)
+  PB_READ_MAP = 16    // take the ring values from `map_in` instead of a synthesis
+};
+
+struct PhaseBArgs {
+  int32_t mode;
+  int32_t nmaps;
+  double lambda;
+  const double* F;        // [map][pair][m][4]
+  double* G;              // [map][pair][m][4]
+  const double* d;        // [map][npix]
+  const double* map_in;   // [map][npix]
+  double* map_out;        // [map][npix]
+};
+
+hipError_t launch_phase_b_f64(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes,
+                              hipStream_t s);
+
+// Phase A (m-parallel): Legendre analysis into per-block partial sums.
+hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,
+                                        int nmaps, const double* G, double2* partial,
+                                        hipStream_t s);
+
+enum SynthMode : int32_t {
+  SY_FROM_PARTIAL = 0,   // a = C sum(partials); s = f(lambda) a; synthesise s
+  SY_FROM_ALM = 1,       // synthesise the caller's alm
+  SY_ALM_ONLY = 2        // a = C sum(partials) -> alm output, no synthesis
+};
+
+struct SynthArgs {
+  int32_t mode;
+  int32_t nmaps;
+  double lambda;
+  const double2* partial;   // [map][blk][nalm]
+  const double2* alm_in;    // [map][nalm]
+  double2* alm_out;         // [map][nalm] or null
+  double* F;                // [map][pair][m][4]
+};
+
+hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
+                                         const SynthArgs& a, hipStream_t s);
+
+// Plan-time: which ring pairs ever reach a non-negligible lambda_lm (polar skip).
+hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s);
+
+}  // namespace mwf

@@ -1,0 +1,412 @@
+// Phase A of a messenger sweep: m-parallel work in harmonic space (FP64 VALU path).
+//
+// For each m the Legendre functions lambda_lm(z) of every ring pair are generated
+// on the fly, l = m..lmax, by the three-term recurrence in FP64 and contracted
+// against the ring Fourier coefficients:
+//
+//   analysis   a_lm = sum_pairs lambda_lm(z) (S if l-m even else D),  S/D = G_N +/- G_S
+//   filter     s_lm = f_l(lambda) a_lm, f_l = C_l / (C_l + lambda tau Omega)     (Eq. 4)
+//   synthesis  E = sum_{l-m even} lambda_lm s_lm, O = sum_{l-m odd} lambda_lm s_lm,
+//              F_N = E + O, F_S = E - O
+//
+// using lambda_lm(-z) = (-1)^(l+m) lambda_lm(z) for the mirror rings.
+//
+// The recurrence runs on rescaled values mu_l = lambda_lm / C_lm that obey
+//   mu_l = (A_lm z) mu_{l-1} - mu_{l-2}
+// (A and C are plan-time FP64 tables derived from
+//  a_lm = sqrt((4 l^2 - 1)/(l^2 - m^2)) with C_l = C_{l-2} a_l / a_{l-1}, A_l = a_l C_{l-1} / C_l),
+// i.e. one multiply and one FMA per value; C is applied once per (l, m) after the
+// ring sum (analysis) or folded into s_lm (synthesis).
+//
+// The sectoral seed lambda_mm = norm_m sin^m(theta) underflows FP64 near the
+// poles: every value carries an integer scale s (value = v 2^(-512 s)); while
+// s > 0 the value is negligible (< 2^-448) and is left out of the sums. A wave
+// runs a cheaper loop without scale checks once none of its rings is scaled.
+//
+// Each work item is (m, block of 64 R ring pairs) handled by one wavefront; a
+// lane owns R ring pairs. The analysis reduces over lanes through LDS once per
+// chunk of 16 values of l and writes one partial sum per block; the synthesis
+// kernel sums the partials of its m, applies the filter and synthesises.
+#include "mwf_internal.hpp"
+
+namespace mwf {
+namespace {
+
+constexpr double BIG_THRESH = 0x1p64;
+constexpr double RESCALE = 0x1p-512;
+
+// lambda_mm(z) = norm_m sin^m(theta) as v * 2^(-512 s) with |v| >= 2^-449 when s = 0.
+__device__ __forceinline__ void sectoral_seed(int m, double sin_t, double norm, double* v, int* s) {
+  int eb;
+  double b = frexp(sin_t, &eb);
+  double r = 1.0;
+  int er = 0;
+  int k = m;
+  while (k) {
+    if (k & 1) {
+      int t;
+      r = frexp(r * b, &t);
+      er += eb + t;
+    }
+    k >>= 1;
+    if (k) {
+      int t;
+      b = frexp(b * b, &t);
+      eb = 2 * eb + t;
+    }
+  }
+  int t;
+  double x = frexp(norm * r, &t);
+  const int e = er + t;                 // value = x * 2^e, 0.5 <= |x| < 1
+  int sc = 0;
+  if (e < 64 - SCALE_BITS) sc = (64 - SCALE_BITS - e + SCALE_BITS - 1) / SCALE_BITS;
+  *v = ldexp(x, e + SCALE_BITS * sc);
+  *s = sc;
+}
+
+__device__ __forceinline__ int wave_any(int pred) { return __any(pred); }
+
+template <int R>
+struct RingState {
+  double z[R], mu1[R], mu2[R];
+  int sc[R];
+};
+
+template <int R>
+__device__ __forceinline__ void init_rings(const PlanDev& P, int m, int blk, int lane, int nact,
+                                           RingState<R>& st) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = blk * (LANES * R) + r * LANES + lane;
+    if (q < nact) {
+      const RingPair rp = P.pairs[q];
+      double v;
+      int s;
+      sectoral_seed(m, rp.sin_t, P.norm_m[m], &v, &s);
+      st.z[r] = rp.z;
+      st.mu1[r] = 0.0;    // mu_{m-1}
+      st.mu2[r] = -v;     // with A_mm = 0 the first step yields mu_m = v
+      st.sc[r] = s;
+    } else {
+      st.z[r] = 0.0;
+      st.mu1[r] = 0.0;
+      st.mu2[r] = 0.0;
+      st.sc[r] = 0;
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void rescale_check(RingState<R>& st) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (st.sc[r] > 0 && fabs(st.mu1[r]) > BIG_THRESH) {
+      st.mu1[r] *= RESCALE;
+      st.mu2[r] *= RESCALE;
+      st.sc[r] -= 1;
+    }
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
+    PlanDev P, const WorkItem* __restrict__ items, const double* __restrict__ G,
+    double2* __restrict__ partial) {
+  __shared__ double red[2 * CHUNK][LANES + 1];
+  const WorkItem it = items[blockIdx.x];
+  const int m = it.m, blk = it.blk, map = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int lmax = P.lmax;
+  const int nact = P.n_active[m];
+  const double* __restrict__ Arow = P.A + P.row_off[m];
+  const size_t pstride = (size_t)(lmax + 1) * 4;
+  const double* Gm = G + (size_t)map * P.npairs * pstride + (size_t)m * 4;
+
+  RingState<R> st;
+  init_rings<R>(P, m, blk, lane, nact, st);
+  double Sre[R], Sim[R], Dre[R], Dim[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = blk * (LANES * R) + r * LANES + lane;
+    if (q < nact) {
+      const double4 sd = *reinterpret_cast<const double4*>(Gm + (size_t)q * pstride);
+      Sre[r] = sd.x;
+      Sim[r] = sd.y;
+      Dre[r] = sd.z;
+      Dim[r] = sd.w;
+    } else {
+      Sre[r] = Sim[r] = Dre[r] = Dim[r] = 0.0;
+    }
+  }
+
+  double* out = reinterpret_cast<double*>(partial + ((size_t)map * P.nblk_max + blk) * P.nalm);
+  const int64_t row = alm_index(lmax, m, m);
+
+  for (int l0 = m; l0 <= lmax; l0 += CHUNK) {
+    double are[CHUNK], aim[CHUNK];
+#pragma unroll
+    for (int j = 0; j < CHUNK; ++j) are[j] = aim[j] = 0.0;
+    int anysc = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) anysc |= st.sc[r];
+    const double* Ac = Arow + (l0 - m);
+    if (!wave_any(anysc)) {
+#pragma unroll
+      for (int j = 0; j < CHUNK; ++j) {
+        const double A = Ac[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
+          st.mu2[r] = st.mu1[r];
+          st.mu1[r] = mu;
+          if (j & 1) {
+            are[j] = fma(mu, Dre[r], are[j]);
+            aim[j] = fma(mu, Dim[r], aim[j]);
+          } else {
+            are[j] = fma(mu, Sre[r], are[j]);
+            aim[j] = fma(mu, Sim[r], aim[j]);
+          }
+        }
+      }
+    } else {
+      double cf[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) cf[r] = st.sc[r] == 0 ? 1.0 : 0.0;
+#pragma unroll
+      for (int j = 0; j < CHUNK; ++j) {
+        const double A = Ac[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
+          st.mu2[r] = st.mu1[r];
+          st.mu1[r] = mu;
+          const double me = mu * cf[r];
+          if (j & 1) {
+            are[j] = fma(me, Dre[r], are[j]);
+            aim[j] = fma(me, Dim[r], aim[j]);
+          } else {
+            are[j] = fma(me, Sre[r], are[j]);
+            aim[j] = fma(me, Sim[r], aim[j]);
+          }
+        }
+        if ((j & 3) == 3) rescale_check<R>(st);
+      }
+    }
+    // reduce the 32 values over the 64 lanes through LDS
+#pragma unroll
+    for (int j = 0; j < CHUNK; ++j) {
+      red[2 * j][lane] = are[j];
+      red[2 * j + 1][lane] = aim[j];
+    }
+    __syncthreads();
+    const int v = lane & 31;
+    const int h = (lane >> 5) * 32;
+    double sum = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < 32; ++k) sum += red[v][h + k];
+    sum += __shfl_xor(sum, 32);
+    if (lane < 32) {
+      const int l = l0 + (v >> 1);
+      if (l <= lmax) out[2 * (row + (l - m)) + (v & 1)] = sum;
+    }
+    __syncthreads();
+  }
+}
+
+template <int R>
+__global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
+    PlanDev P, const WorkItem* __restrict__ items, SynthArgs a) {
+  extern __shared__ double2 bsh[];
+  const WorkItem it = items[blockIdx.x];
+  const int m = it.m, blk = it.blk, map = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int lmax = P.lmax;
+  const int nl = lmax - m + 1;
+  const int nl_pad = ((nl + CHUNK - 1) / CHUNK) * CHUNK;
+  const int64_t row = alm_index(lmax, m, m);
+  const double* __restrict__ Crow = P.C + P.row_off[m];
+  const double lam_t_o = a.lambda * P.tau * P.omega;
+
+  // ---- coefficients: s_lm (alm) and b_l = C_l s_lm for the recurrence in mu
+  for (int i = lane; i < nl_pad; i += LANES) {
+    double2 b = make_double2(0.0, 0.0);
+    if (i < nl) {
+      const int l = m + i;
+      double2 alm;
+      if (a.mode == SY_FROM_ALM) {
+        alm = a.alm_in[(size_t)map * P.nalm + row + i];
+        if (m == 0) alm.y = 0.0;
+      } else {
+        double sr = 0.0, si = 0.0;
+        const int nb = P.nblk[m];
+        for (int k = 0; k < nb; ++k) {
+          const double2 p = a.partial[((size_t)map * P.nblk_max + k) * P.nalm + row + i];
+          sr += p.x;
+          si += p.y;
+        }
+        // the ring phase already applied Omega to G
+        const double sc = Crow[i];
+        alm = make_double2(sr * sc, si * sc);
+        if (a.mode == SY_FROM_PARTIAL) {
+          const double cl = P.cl[l];
+          const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
+          alm.x *= f;
+          alm.y *= f;
+        }
+      }
+      if (blk == 0 && a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = alm;
+      b = make_double2(alm.x * Crow[i], alm.y * Crow[i]);
+    }
+    bsh[i] = b;
+  }
+  __syncthreads();
+  if (a.mode == SY_ALM_ONLY) return;
+
+  const int nact = P.n_active[m];
+  const double* __restrict__ Arow = P.A + P.row_off[m];
+  RingState<R> st;
+  init_rings<R>(P, m, blk, lane, nact, st);
+  double Ere[R], Eim[R], Ore[R], Oim[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
+
+  for (int l0 = m; l0 <= lmax; l0 += CHUNK) {
+    int anysc = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) anysc |= st.sc[r];
+    const double* Ac = Arow + (l0 - m);
+    const double2* bc = bsh + (l0 - m);
+    if (!wave_any(anysc)) {
+#pragma unroll
+      for (int j = 0; j < CHUNK; ++j) {
+        const double A = Ac[j];
+        const double2 b = bc[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
+          st.mu2[r] = st.mu1[r];
+          st.mu1[r] = mu;
+          if (j & 1) {
+            Ore[r] = fma(mu, b.x, Ore[r]);
+            Oim[r] = fma(mu, b.y, Oim[r]);
+          } else {
+            Ere[r] = fma(mu, b.x, Ere[r]);
+            Eim[r] = fma(mu, b.y, Eim[r]);
+          }
+        }
+      }
+    } else {
+      double cf[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) cf[r] = st.sc[r] == 0 ? 1.0 : 0.0;
+#pragma unroll
+      for (int j = 0; j < CHUNK; ++j) {
+        const double A = Ac[j];
+        const double2 b = bc[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
+          st.mu2[r] = st.mu1[r];
+          st.mu1[r] = mu;
+          const double me = mu * cf[r];
+          if (j & 1) {
+            Ore[r] = fma(me, b.x, Ore[r]);
+            Oim[r] = fma(me, b.y, Oim[r]);
+          } else {
+            Ere[r] = fma(me, b.x, Ere[r]);
+            Eim[r] = fma(me, b.y, Eim[r]);
+          }
+        }
+        if ((j & 3) == 3) rescale_check<R>(st);
+      }
+    }
+  }
+
+  const size_t pstride = (size_t)(lmax + 1) * 4;
+  double* Fm = a.F + (size_t)map * P.npairs * pstride + (size_t)m * 4;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = blk * (LANES * R) + r * LANES + lane;
+    if (q < nact)
+      *reinterpret_cast<double4*>(Fm + (size_t)q * pstride) =
+          make_double4(Ere[r], Eim[r], Ore[r], Oim[r]);
+  }
+}
+
+// Plan time: does lambda_lm(z_q) rise above the negligible threshold for some l <= lmax?
+__global__ void reach_kernel(PlanDev P, uint8_t* __restrict__ reach) {
+  const int m = blockIdx.y;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.npairs) return;
+  const RingPair rp = P.pairs[q];
+  double v;
+  int s;
+  sectoral_seed(m, rp.sin_t, P.norm_m[m], &v, &s);
+  uint8_t ok = (s == 0);
+  if (!ok) {
+    const double* Arow = P.A + P.row_off[m];
+    double mu1 = 0.0, mu2 = -v;
+    for (int l = m; l <= P.lmax; ++l) {
+      const double mu = fma(Arow[l - m] * rp.z, mu1, -mu2);
+      mu2 = mu1;
+      mu1 = mu;
+      if (fabs(mu1) > BIG_THRESH) {
+        mu1 *= RESCALE;
+        mu2 *= RESCALE;
+        if (--s == 0) {
+          ok = 1;
+          break;
+        }
+      }
+    }
+  }
+  reach[(size_t)m * P.npairs + q] = ok;
+}
+
+template <int R>
+hipError_t launch_ana_r(const PlanDev& P, const WorkItem* items, int nitems, int nmaps,
+                        const double* G, double2* partial, hipStream_t s) {
+  hipLaunchKernelGGL(legendre_analysis_f64_kernel<R>, dim3(nitems, nmaps), dim3(64), 0, s, P,
+                     items, G, partial);
+  return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_syn_r(const PlanDev& P, const WorkItem* items, int nitems, const SynthArgs& a,
+                        hipStream_t s) {
+  const size_t lds = (size_t)(P.lmax + 1 + CHUNK) * sizeof(double2);
+  hipLaunchKernelGGL(legendre_synthesis_f64_kernel<R>, dim3(nitems, a.nmaps), dim3(64), lds, s,
+                     P, items, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,
+                                        int nmaps, const double* G, double2* partial,
+                                        hipStream_t s) {
+  switch (P.ring_block / LANES) {
+    case 1: return launch_ana_r<1>(P, items, nitems, nmaps, G, partial, s);
+    case 2: return launch_ana_r<2>(P, items, nitems, nmaps, G, partial, s);
+    case 4: return launch_ana_r<4>(P, items, nitems, nmaps, G, partial, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
+                                         const SynthArgs& a, hipStream_t s) {
+  switch (P.ring_block / LANES) {
+    case 1: return launch_syn_r<1>(P, items, nitems, a, s);
+    case 2: return launch_syn_r<2>(P, items, nitems, a, s);
+    case 4: return launch_syn_r<4>(P, items, nitems, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s) {
+  dim3 grid((P.npairs + 127) / 128, P.lmax + 1);
+  hipLaunchKernelGGL(reach_kernel, grid, dim3(128), 0, s, P, reach);
+  return hipGetLastError();
+}
+
+}  // namespace mwf

@@ -1,0 +1,215 @@
+"""Python binding of libmwf (ctypes): argument marshalling only.
+
+Every step of the filter runs in the HIP kernels of libmwf.so; PyTorch provides
+device memory and streams. There is no fallback: if the library is missing or
+cannot be loaded, every entry point raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+WF_OK, WF_EINVAL, WF_ENOMEM, WF_EDEVICE, WF_EUNSUPPORTED, WF_EBUSY, WF_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
+WF_F64, WF_F32, WF_BF16X3 = 0, 1, 2
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmwf.so")
+
+# (name, restype, argtypes) of every function declared in include/mwf.h
+_c = ctypes
+_SIGS = [
+    ("wf_plan", _c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                           _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    ("wf_solve", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
+                            _c.c_void_p, _c.c_void_p]),
+    ("wf_solve_batch", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                  _c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("sht_map2alm", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    ("sht_alm2map", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    ("wf_footprint", _c.c_int, [_c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
+    ("wf_plan_info", _c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
+                                _c.POINTER(_c.c_double)]),
+    ("wf_pixel_angles", _c.c_int, [_c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("wf_sync", _c.c_int, [_c.c_void_p]),
+    ("wf_destroy", None, [_c.c_void_p]),
+    ("wf_strerror", _c.c_char_p, [_c.c_int]),
+    ("wf_last_error", _c.c_char_p, []),
+]
+
+_lib = None
+
+
+class WFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+def lib():
+    """Load libmwf.so (once). Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libmwf.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != WF_OK:
+        L = lib()
+        raise WFError(rc, f"{L.wf_strerror(rc).decode()}: {L.wf_last_error().decode()}")
+
+
+class wf_plan_opts(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("tune_cache", ctypes.c_char_p)]
+
+
+class wf_stats(ctypes.Structure):
+    _fields_ = [("sweeps_done", ctypes.c_int32), ("chi2_last", ctypes.c_double),
+                ("ms_phaseA", ctypes.c_float), ("ms_phaseB", ctypes.c_float)]
+
+
+def footprint(nside, lmax, dtype=WF_F64, nmaps=1):
+    out = ctypes.c_size_t(0)
+    _check(lib().wf_footprint(nside, lmax, dtype, nmaps, ctypes.byref(out)))
+    return out.value
+
+
+def pixel_angles(nside):
+    """(theta, phi) of every pixel centre in RING order, from the library's geometry."""
+    npix = 12 * nside * nside
+    th = np.empty(npix)
+    ph = np.empty(npix)
+    _check(lib().wf_pixel_angles(nside, th.ctypes.data, ph.ctypes.data))
+    return th, ph
+
+
+def n_alm(lmax):
+    return (lmax + 1) * (lmax + 2) // 2
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A planned (nside, lmax, C_l, N^-1, mask) problem; owns device tables and buffers."""
+
+    def __init__(self, nside, lmax, cl, ninv, mask=None, dtype=WF_F64, max_batch=1, stream=None):
+        L = lib()
+        cl = np.ascontiguousarray(cl, dtype=np.float64)
+        ninv = np.ascontiguousarray(ninv, dtype=np.float64)
+        npix = 12 * nside * nside
+        if cl.size != lmax + 1:
+            raise ValueError("cl must have lmax+1 entries")
+        if ninv.size != npix:
+            raise ValueError("ninv must have npix entries")
+        mptr = None
+        if mask is not None:
+            mask = np.ascontiguousarray(np.asarray(mask).astype(np.uint8))
+            if mask.size != npix:
+                raise ValueError("mask must have npix entries")
+            mptr = mask.ctypes.data
+        opts = wf_plan_opts(dtype, max_batch, 0, None)
+        h = ctypes.c_void_p()
+        sh = _stream_handle(stream)
+        _check(L.wf_plan(ctypes.byref(h), nside, lmax, cl.ctypes.data, ninv.ctypes.data, mptr,
+                         ctypes.byref(opts), sh))
+        self._h = h
+        self.nside, self.lmax, self.dtype, self.max_batch = nside, lmax, dtype, max_batch
+        a, b, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(L.wf_plan_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)))
+        self.npix, self.nalm, self.tau = a.value, b.value, t.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan has been closed")
+        return self._h
+
+    def _types(self):
+        import torch
+        if self.dtype == WF_F64:
+            return torch.float64, torch.complex128
+        return torch.float32, torch.complex64
+
+    def solve(self, d, lambdas, s_wf=None, s_alm=None, stream=None, want_alm=True):
+        """Run the messenger iteration; d is [npix] or [nmaps, npix]. Returns (s_wf, s_alm)."""
+        import torch
+        rt, ct = self._types()
+        nmaps = 1 if d.dim() == 1 else d.shape[0]
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        if s_wf is None:
+            s_wf = torch.empty_like(d)
+        if s_alm is None and want_alm:
+            shape = (self.nalm,) if d.dim() == 1 else (nmaps, self.nalm)
+            s_alm = torch.empty(shape, dtype=ct, device=d.device)
+        aptr = _dev_ptr(s_alm, ct, nmaps * self.nalm, "s_alm") if s_alm is not None else None
+        _check(lib().wf_solve_batch(self.handle, nmaps, _dev_ptr(d, rt, nmaps * self.npix, "d"),
+                                    _dev_ptr(s_wf, rt, nmaps * self.npix, "s_wf"), aptr,
+                                    lam.ctypes.data, lam.size, _stream_handle(stream), None))
+        return s_wf, s_alm
+
+    def map2alm(self, maps, alm=None, stream=None):
+        import torch
+        rt, ct = self._types()
+        nmaps = 1 if maps.dim() == 1 else maps.shape[0]
+        if alm is None:
+            shape = (self.nalm,) if maps.dim() == 1 else (nmaps, self.nalm)
+            alm = torch.empty(shape, dtype=ct, device=maps.device)
+        _check(lib().sht_map2alm(self.handle, nmaps, _dev_ptr(maps, rt, nmaps * self.npix, "map"),
+                                 _dev_ptr(alm, ct, nmaps * self.nalm, "alm"), _stream_handle(stream)))
+        return alm
+
+    def alm2map(self, alm, maps=None, stream=None):
+        import torch
+        rt, ct = self._types()
+        nmaps = 1 if alm.dim() == 1 else alm.shape[0]
+        if maps is None:
+            shape = (self.npix,) if alm.dim() == 1 else (nmaps, self.npix)
+            maps = torch.empty(shape, dtype=rt, device=alm.device)
+        _check(lib().sht_alm2map(self.handle, nmaps, _dev_ptr(alm, ct, nmaps * self.nalm, "alm"),
+                                 _dev_ptr(maps, rt, nmaps * self.npix, "map"), _stream_handle(stream)))
+        return maps
+
+    def sync(self):
+        _check(lib().wf_sync(self.handle))
+
+    def close(self):
+        if self._h is not None:
+            lib().wf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

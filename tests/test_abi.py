@@ -1,0 +1,102 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+symbol include/mwf.h declares, validates arguments before touching the device,
+and its host-only calls agree with the oracle's geometry."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import healpix
+from paper_1211_0585_amd import mwf
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mwf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:wf|sht)_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = mwf.lib()
+    names = _declared()
+    assert "wf_plan" in names and "sht_map2alm" in names and "wf_solve" in names
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(n for n, _, _ in mwf._SIGS) == names
+
+
+def test_strerror_and_last_error():
+    L = mwf.lib()
+    assert L.wf_strerror(0) == b"ok"
+    assert L.wf_strerror(-1) == b"invalid argument"
+    assert L.wf_strerror(-999) == b"unknown status"
+
+
+def _plan_rc(nside, lmax, cl, ninv, mask=None, opts=None):
+    L = mwf.lib()
+    h = ctypes.c_void_p()
+    cl = np.ascontiguousarray(cl, dtype=np.float64)
+    ninv = np.ascontiguousarray(ninv, dtype=np.float64)
+    mp = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).ctypes.data
+    o = None if opts is None else ctypes.byref(opts)
+    rc = L.wf_plan(ctypes.byref(h), nside, lmax, cl.ctypes.data, ninv.ctypes.data, mp, o, None)
+    return rc, h.value, L.wf_last_error().decode()
+
+
+@pytest.mark.parametrize("nside,lmax,why", [
+    (3, 4, "power of two"), (0, 0, "power of two"), (2048, 8, "power of two"),
+    (4, 16, "lmax"), (4, -1, "lmax")])
+def test_plan_rejects_bad_shape(nside, lmax, why):
+    npix = 12 * max(nside, 1) ** 2
+    rc, h, msg = _plan_rc(nside, lmax, np.ones(max(lmax, 0) + 1), np.ones(npix))
+    assert rc == mwf.WF_EINVAL and h is None and why in msg
+
+
+def test_plan_rejects_bad_values():
+    nside, lmax = 4, 8
+    npix = 192
+    cl = np.ones(lmax + 1)
+    ninv = np.ones(npix)
+    bad = cl.copy()
+    bad[3] = np.nan
+    assert _plan_rc(nside, lmax, bad, ninv)[0] == mwf.WF_EINVAL
+    bad = ninv.copy()
+    bad[7] = -1.0
+    assert _plan_rc(nside, lmax, cl, bad)[0] == mwf.WF_EINVAL
+    assert _plan_rc(nside, lmax, cl, np.zeros(npix))[0] == mwf.WF_EINVAL          # no observed pixel
+    assert _plan_rc(nside, lmax, cl, ninv, mask=np.zeros(npix))[0] == mwf.WF_EINVAL  # all masked
+    opts = mwf.wf_plan_opts(7, 1, 0, None)
+    assert _plan_rc(nside, lmax, cl, ninv, opts=opts)[0] == mwf.WF_EINVAL
+    opts = mwf.wf_plan_opts(0, 1, 3, None)
+    assert _plan_rc(nside, lmax, cl, ninv, opts=opts)[0] == mwf.WF_EINVAL
+
+
+def test_null_arguments():
+    L = mwf.lib()
+    assert L.wf_plan(None, 4, 8, None, None, None, None, None) == mwf.WF_EINVAL
+    assert L.wf_solve(None, None, None, None, None, 1, None, None) == mwf.WF_EINVAL
+    assert L.sht_map2alm(None, 1, None, None, None) == mwf.WF_EINVAL
+    assert L.sht_alm2map(None, 1, None, None, None) == mwf.WF_EINVAL
+    assert L.wf_sync(None) == mwf.WF_EINVAL
+    L.wf_destroy(None)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 8, 64])
+def test_pixel_angles_match_oracle_geometry(nside):
+    th, ph = mwf.pixel_angles(nside)
+    oth, oph = healpix.pixel_angles(nside)
+    assert np.allclose(th, oth, rtol=0, atol=1e-15)
+    assert np.allclose(ph, oph, rtol=0, atol=1e-13)
+
+
+def test_footprint_monotone():
+    a = mwf.footprint(64, 128, mwf.WF_F64, 1)
+    b = mwf.footprint(64, 128, mwf.WF_F64, 4)
+    c = mwf.footprint(128, 256, mwf.WF_F64, 1)
+    assert 0 < a < b and a < c
+    with pytest.raises(mwf.WFError):
+        mwf.footprint(64, 128, mwf.WF_F64, 0)
