@@ -58,20 +58,28 @@ enum {
 
 enum { WF_F64 = 0, WF_F32 = 1, WF_BF16X3 = 2 };
 
+/* Plan flags. WF_FLAG_TIMING: record HIP events around every kernel launch of a
+ * solve on the caller's stream and report the summed durations in wf_stats; the
+ * solve then waits for its own completion before returning. */
+enum { WF_FLAG_TIMING = 1 };
+
 typedef struct wf_plan_s* wf_plan_t;
 
 typedef struct {
   int32_t dtype;      /* WF_F64 (default), WF_F32 or WF_BF16X3                         */
   int32_t max_batch;  /* largest nmaps accepted by the batched calls (>= 1; 0 -> 1)    */
-  int32_t flags;      /* reserved, must be 0                                           */
+  int32_t flags;      /* 0 or WF_FLAG_TIMING                                           */
   const char* tune_cache; /* reserved (may be NULL)                                    */
 } wf_plan_opts;
 
 typedef struct {
-  int32_t sweeps_done; /* sweeps enqueued by the last solve                            */
-  double chi2_last;    /* reserved (0)                                                  */
-  float ms_phaseA;     /* reserved (0)                                                  */
-  float ms_phaseB;     /* reserved (0)                                                  */
+  int32_t sweeps_done;   /* sweeps run by the last solve                                */
+  int32_t timed;         /* 1 when the kernel times below were measured (WF_FLAG_TIMING) */
+  double ms_ring;        /* summed duration of the ring-FFT / pixel-update launches      */
+  double ms_analysis;    /* summed duration of the Legendre analysis launches           */
+  double ms_synthesis;   /* summed duration of the filter + Legendre synthesis launches */
+  int32_t n_ring, n_analysis, n_synthesis;   /* number of launches of each kind        */
+  int32_t pad_;
 } wf_stats;
 
 /*
@@ -139,8 +147,17 @@ int sht_alm2map(wf_plan_t plan, int32_t nmaps, const void* alm, void* map,
 int wf_footprint(int32_t nside, int32_t lmax, int32_t dtype, int32_t nmaps,
                  size_t* bytes);
 
-/* wf_plan_info -- npix, N_lm and tau of a plan (any pointer may be NULL). */
-int wf_plan_info(wf_plan_t plan, int64_t* npix, int64_t* nalm, double* tau);
+/*
+ * wf_plan_info -- shape of a plan (any pointer may be NULL):
+ *   npix, nalm   pixels and packed alm per map
+ *   tau          min(diag N) = 1 / max ninv
+ *   units_all    (l, m, ring pair) triples of one Legendre transform of one map,
+ *                2 nside N_lm
+ *   units_active the triples actually visited after dropping ring pairs whose
+ *                lambda_lm stays below 2^-448 for every l <= lmax
+ */
+int wf_plan_info(wf_plan_t plan, int64_t* npix, int64_t* nalm, double* tau,
+                 int64_t* units_all, int64_t* units_active);
 
 /*
  * wf_pixel_angles -- colatitude theta and longitude phi of every pixel centre of

@@ -38,6 +38,8 @@ struct wf_plan_s {
   hipStream_t last_stream = nullptr;  // stream of the last enqueued call
   size_t lds_phase_b = 0;
   int nitems = 0, nitems_m = 0;
+  int flags = 0;
+  int64_t units_active = 0;
   std::vector<int32_t> n_active;
   // device allocations
   std::vector<void*> allocs;
@@ -182,7 +184,7 @@ int validate_plan_args(int nside, int lmax, const double* cl, const double* ninv
     if (o->dtype != WF_F64 && o->dtype != WF_F32 && o->dtype != WF_BF16X3)
       return fail(WF_EINVAL, "unknown dtype");
     if (o->max_batch < 0) return fail(WF_EINVAL, "max_batch must be >= 0");
-    if (o->flags != 0) return fail(WF_EINVAL, "flags must be 0");
+    if (o->flags & ~WF_FLAG_TIMING) return fail(WF_EINVAL, "unknown flags");
   }
   return WF_OK;
 }
@@ -263,6 +265,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   p->lmax = lmax;
   p->dtype = dtype;
   p->max_batch = (opts && opts->max_batch > 0) ? opts->max_batch : 1;
+  p->flags = opts ? opts->flags : 0;
   p->npix = npix;
   p->nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
   p->nrings = 4 * nside - 1;
@@ -431,11 +434,13 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
       return bail(WF_EDEVICE);
     }
     p->n_active.assign(lmax + 1, 0);
+    p->units_active = 0;
     for (int m = 0; m <= lmax; ++m) {
       int na = 0;
       for (int qq = 0; qq < p->npairs; ++qq)
         if (reach[(size_t)m * p->npairs + qq]) na = qq + 1;
       p->n_active[m] = na;
+      p->units_active += (int64_t)na * (lmax - m + 1);
     }
   }
   std::vector<int32_t> nblk(lmax + 1);
@@ -479,11 +484,14 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   return WF_OK;
 }
 
-int wf_plan_info(wf_plan_t p, int64_t* npix, int64_t* nalm, double* tau) {
+int wf_plan_info(wf_plan_t p, int64_t* npix, int64_t* nalm, double* tau, int64_t* units_all,
+                 int64_t* units_active) {
   if (!p) return fail(WF_EINVAL, "plan must not be NULL");
   if (npix) *npix = p->npix;
   if (nalm) *nalm = p->nalm;
   if (tau) *tau = p->tau;
+  if (units_all) *units_all = (int64_t)p->npairs * p->nalm;
+  if (units_active) *units_active = p->units_active;
   return WF_OK;
 }
 
@@ -499,6 +507,56 @@ int wf_sync(wf_plan_t p) {
 
 namespace {
 
+// Per-solve kernel timing (WF_FLAG_TIMING): an event before and after every launch.
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kind;   // 0 ring, 1 analysis, 2 synthesis
+  hipStream_t s = nullptr;
+  ~Timer() {
+    for (auto e : ev) hipEventDestroy(e);
+  }
+  int begin() {
+    if (!on) return WF_OK;
+    hipEvent_t e;
+    MWF_HIP(hipEventCreate(&e));
+    MWF_HIP(hipEventRecord(e, s));
+    ev.push_back(e);
+    return WF_OK;
+  }
+  int end(int k) {
+    if (!on) return WF_OK;
+    hipEvent_t e;
+    MWF_HIP(hipEventCreate(&e));
+    MWF_HIP(hipEventRecord(e, s));
+    ev.push_back(e);
+    kind.push_back(k);
+    return WF_OK;
+  }
+  int collect(wf_stats* st) {
+    if (!on || !st) return WF_OK;
+    MWF_HIP(hipEventSynchronize(ev.back()));
+    double ms[3] = {0, 0, 0};
+    int cnt[3] = {0, 0, 0};
+    for (size_t i = 0; i < kind.size(); ++i) {
+      float t = 0.f;
+      MWF_HIP(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+      ms[kind[i]] += t;
+      cnt[kind[i]] += 1;
+    }
+    st->timed = 1;
+    st->ms_ring = ms[0];
+    st->ms_analysis = ms[1];
+    st->ms_synthesis = ms[2];
+    st->n_ring = cnt[0];
+    st->n_analysis = cnt[1];
+    st->n_synthesis = cnt[2];
+    return WF_OK;
+  }
+};
+
+thread_local Timer* g_timer = nullptr;
+
 int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, const double* d,
                 const double* map_in, double* map_out) {
   PhaseBArgs a{};
@@ -510,12 +568,16 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   a.d = d;
   a.map_in = map_in;
   a.map_out = map_out;
+  if (g_timer && g_timer->begin()) return WF_EDEVICE;
   MWF_HIP(launch_phase_b_f64(p->dev, a, p->lds_phase_b, s));
+  if (g_timer && g_timer->end(0)) return WF_EDEVICE;
   return WF_OK;
 }
 
 int run_analysis(wf_plan_s* p, hipStream_t s, int nmaps) {
+  if (g_timer && g_timer->begin()) return WF_EDEVICE;
   MWF_HIP(launch_legendre_analysis_f64(p->dev, p->d_items, p->nitems, nmaps, p->d_G, p->d_partial, s));
+  if (g_timer && g_timer->end(1)) return WF_EDEVICE;
   return WF_OK;
 }
 
@@ -530,8 +592,10 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam,
   a.alm_out = alm_out;
   a.F = p->d_F;
   const bool alm_only = (mode == SY_ALM_ONLY);
+  if (g_timer && g_timer->begin()) return WF_EDEVICE;
   MWF_HIP(launch_legendre_synthesis_f64(p->dev, alm_only ? p->d_items_m : p->d_items,
                                         alm_only ? p->nitems_m : p->nitems, a, s));
+  if (g_timer && g_timer->end(2)) return WF_EDEVICE;
   return WF_OK;
 }
 
@@ -559,6 +623,14 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   p->last_stream = s;
   const double* dd = static_cast<const double*>(d);
+  Timer timer;
+  timer.on = (p->flags & WF_FLAG_TIMING) != 0;
+  timer.s = s;
+  struct Guard {
+    Timer* t;
+    Guard(Timer* x) : t(x) { g_timer = x->on ? x : nullptr; }
+    ~Guard() { g_timer = nullptr; }
+  } guard(&timer);
   for (int k = 0; k < nsweeps; ++k) {
     const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
     if ((rc = run_phase_b(p, s, mode, nmaps, lambda[k], dd, nullptr, nullptr))) return rc;
@@ -570,9 +642,9 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
                         static_cast<double*>(s_wf))))
     return rc;
   if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
     stats->sweeps_done = nsweeps;
-    stats->chi2_last = 0.0;
-    stats->ms_phaseA = stats->ms_phaseB = 0.0f;
+    if ((rc = timer.collect(stats))) return rc;
   }
   return WF_OK;
 }

@@ -11,6 +11,7 @@ import numpy as np
 
 WF_OK, WF_EINVAL, WF_ENOMEM, WF_EDEVICE, WF_EUNSUPPORTED, WF_EBUSY, WF_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
 WF_F64, WF_F32, WF_BF16X3 = 0, 1, 2
+WF_FLAG_TIMING = 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmwf.so")
 
@@ -27,7 +28,7 @@ _SIGS = [
     ("sht_alm2map", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     ("wf_footprint", _c.c_int, [_c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
     ("wf_plan_info", _c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
-                                _c.POINTER(_c.c_double)]),
+                                _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64)]),
     ("wf_pixel_angles", _c.c_int, [_c.c_int32, _c.c_void_p, _c.c_void_p]),
     ("wf_sync", _c.c_int, [_c.c_void_p]),
     ("wf_destroy", None, [_c.c_void_p]),
@@ -71,8 +72,11 @@ class wf_plan_opts(ctypes.Structure):
 
 
 class wf_stats(ctypes.Structure):
-    _fields_ = [("sweeps_done", ctypes.c_int32), ("chi2_last", ctypes.c_double),
-                ("ms_phaseA", ctypes.c_float), ("ms_phaseB", ctypes.c_float)]
+    _fields_ = [("sweeps_done", ctypes.c_int32), ("timed", ctypes.c_int32),
+                ("ms_ring", ctypes.c_double), ("ms_analysis", ctypes.c_double),
+                ("ms_synthesis", ctypes.c_double), ("n_ring", ctypes.c_int32),
+                ("n_analysis", ctypes.c_int32), ("n_synthesis", ctypes.c_int32),
+                ("pad_", ctypes.c_int32)]
 
 
 def footprint(nside, lmax, dtype=WF_F64, nmaps=1):
@@ -117,7 +121,8 @@ def _dev_ptr(t, dtype, numel, name):
 class Plan:
     """A planned (nside, lmax, C_l, N^-1, mask) problem; owns device tables and buffers."""
 
-    def __init__(self, nside, lmax, cl, ninv, mask=None, dtype=WF_F64, max_batch=1, stream=None):
+    def __init__(self, nside, lmax, cl, ninv, mask=None, dtype=WF_F64, max_batch=1, stream=None,
+                 flags=0):
         L = lib()
         cl = np.ascontiguousarray(cl, dtype=np.float64)
         ninv = np.ascontiguousarray(ninv, dtype=np.float64)
@@ -132,7 +137,7 @@ class Plan:
             if mask.size != npix:
                 raise ValueError("mask must have npix entries")
             mptr = mask.ctypes.data
-        opts = wf_plan_opts(dtype, max_batch, 0, None)
+        opts = wf_plan_opts(dtype, max_batch, flags, None)
         h = ctypes.c_void_p()
         sh = _stream_handle(stream)
         _check(L.wf_plan(ctypes.byref(h), nside, lmax, cl.ctypes.data, ninv.ctypes.data, mptr,
@@ -140,8 +145,12 @@ class Plan:
         self._h = h
         self.nside, self.lmax, self.dtype, self.max_batch = nside, lmax, dtype, max_batch
         a, b, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
-        _check(L.wf_plan_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t)))
+        u1, u2 = ctypes.c_int64(), ctypes.c_int64()
+        _check(L.wf_plan_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t), ctypes.byref(u1),
+                              ctypes.byref(u2)))
         self.npix, self.nalm, self.tau = a.value, b.value, t.value
+        self.units_all, self.units_active = u1.value, u2.value
+        self.last_stats = None
 
     @property
     def handle(self):
@@ -167,9 +176,11 @@ class Plan:
             shape = (self.nalm,) if d.dim() == 1 else (nmaps, self.nalm)
             s_alm = torch.empty(shape, dtype=ct, device=d.device)
         aptr = _dev_ptr(s_alm, ct, nmaps * self.nalm, "s_alm") if s_alm is not None else None
+        st = wf_stats()
         _check(lib().wf_solve_batch(self.handle, nmaps, _dev_ptr(d, rt, nmaps * self.npix, "d"),
                                     _dev_ptr(s_wf, rt, nmaps * self.npix, "s_wf"), aptr,
-                                    lam.ctypes.data, lam.size, _stream_handle(stream), None))
+                                    lam.ctypes.data, lam.size, _stream_handle(stream), ctypes.byref(st)))
+        self.last_stats = st
         return s_wf, s_alm
 
     def map2alm(self, maps, alm=None, stream=None):
