@@ -37,14 +37,14 @@ struct wf_plan_s {
   hipStream_t stream = nullptr;       // plan-time uploads
   hipStream_t last_stream = nullptr;  // stream of the last enqueued call
   size_t lds_phase_b = 0;
-  int nitems = 0, nitems_m = 0;
+  int nitems_ana = 0, nitems_syn = 0, nitems_m = 0;
   int flags = 0;
   int64_t units_active = 0;
   std::vector<int32_t> n_active;
   // device allocations
   std::vector<void*> allocs;
   RingPair* d_pairs = nullptr;
-  double* d_q = nullptr;
+  void* d_q = nullptr;
   double* d_cl = nullptr;
   double* d_A = nullptr;
   double* d_C = nullptr;
@@ -54,10 +54,13 @@ struct wf_plan_s {
   int32_t* d_nblk = nullptr;
   double2* d_tw = nullptr;
   double2* d_blue = nullptr;
-  WorkItem* d_items = nullptr;     // all (m, blk), longest first
+  double2* d_chirp = nullptr;
+  WorkItem* d_items_ana = nullptr; // (m, analysis block), longest first
+  WorkItem* d_items_syn = nullptr; // (m, synthesis block), longest first
   WorkItem* d_items_m = nullptr;   // (m, 0), one per m
-  double* d_G = nullptr;           // [batch][pair][m][4]
-  double* d_F = nullptr;
+  void* d_G = nullptr;             // [batch][pair][m][4] in the storage type
+  void* d_F = nullptr;
+  size_t elem = 8;                 // bytes per stored real (8 for WF_F64, 4 otherwise)
   double2* d_partial = nullptr;    // [batch][blk][nalm]
   PlanDev dev{};
 };
@@ -150,9 +153,15 @@ int upload(wf_plan_s* p, T** ptr, const std::vector<T>& host) {
   return WF_OK;
 }
 
+// Ring pairs per analysis work item: two per lane once there are enough rings
+// (the cross-lane reduction is then shared by two rings); synthesis uses one per
+// lane so that long recurrences are spread over as many waves as possible.
+int ana_ring_block(int npairs) { return npairs <= 64 ? 64 : 128; }
+constexpr int SYN_RING_BLOCK = 64;
+
 size_t buffer_bytes(int nside, int lmax, int nmaps, int* ring_block_out, int* nblk_out) {
   const int npairs = 2 * nside;
-  const int rb = npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256);
+  const int rb = ana_ring_block(npairs);
   const int nblk = (npairs + rb - 1) / rb;
   if (ring_block_out) *ring_block_out = rb;
   if (nblk_out) *nblk_out = nblk;
@@ -312,11 +321,16 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
 
   // Bluestein filter spectra: H = FFT_M(h), h_j = exp(+i pi j^2 / n) for |j| < n
   const long double pi = 3.141592653589793238462643383279502884L;
-  std::vector<double2> blue;
+  std::vector<double2> blue, chirp;
   {
-    std::vector<int64_t> off_of(4 * nside + 1, -1);
+    std::vector<int64_t> off_of(4 * nside + 1, -1), coff_of(4 * nside + 1, -1);
     for (int n : blue_len) {
       if (off_of[n] >= 0) continue;
+      coff_of[n] = (int64_t)chirp.size();
+      for (int j = 0; j < n; ++j) {
+        const long double ang = -pi * (long double)(((int64_t)j * j) % (2LL * n)) / (long double)n;
+        chirp.push_back(make_double2((double)cosl(ang), (double)sinl(ang)));
+      }
       const int M = 1 << ilog2(2 * n - 1);
       std::vector<std::complex<long double>> h(M, 0.0L);
       for (int j = 0; j < n; ++j) {
@@ -330,8 +344,12 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
       for (int k = 0; k < M; ++k) blue.push_back(make_double2((double)h[k].real(), (double)h[k].imag()));
     }
     for (auto& rp : pairs)
-      if (rp.log2n < 0) rp.bl_off = off_of[rp.nphi];
+      if (rp.log2n < 0) {
+        rp.bl_off = off_of[rp.nphi];
+        rp.chirp_off = coff_of[rp.nphi];
+      }
     if (blue.empty()) blue.push_back(make_double2(0.0, 0.0));
+    if (chirp.empty()) chirp.push_back(make_double2(0.0, 0.0));
   }
   std::vector<double2> tw(tw_len / 2);
   for (int k = 0; k < tw_len / 2; ++k) {
@@ -340,6 +358,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   }
 
   // ---- per-pixel tau * ninv (0 where unobserved)
+  std::vector<float> q32;
   std::vector<double> q(npix);
   for (int64_t i = 0; i < npix; ++i) q[i] = (mask && !mask[i]) ? 0.0 : p->tau * ninv[i];
 
@@ -382,7 +401,16 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
 
   // ---- uploads
   if ((rc = upload(p, &p->d_pairs, pairs))) return bail(rc);
-  if ((rc = upload(p, &p->d_q, q))) return bail(rc);
+  if (dtype == WF_F64) {
+    double* dq = nullptr;
+    if ((rc = upload(p, &dq, q))) return bail(rc);
+    p->d_q = dq;
+  } else {
+    q32.assign(q.begin(), q.end());
+    float* dq = nullptr;
+    if ((rc = upload(p, &dq, q32))) return bail(rc);
+    p->d_q = dq;
+  }
   const std::vector<double> cl_host(cl, cl + lmax + 1);
   if ((rc = upload(p, &p->d_cl, cl_host))) return bail(rc);
   if ((rc = upload(p, &p->d_A, A))) return bail(rc);
@@ -391,6 +419,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   if ((rc = upload(p, &p->d_norm, norm))) return bail(rc);
   if ((rc = upload(p, &p->d_tw, tw))) return bail(rc);
   if ((rc = upload(p, &p->d_blue, blue))) return bail(rc);
+  if ((rc = upload(p, &p->d_chirp, chirp))) return bail(rc);
 
   int ring_block = 0, nblk_max = 0;
   buffer_bytes(nside, lmax, p->max_batch, &ring_block, &nblk_max);
@@ -404,7 +433,8 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   D.nalm = p->nalm;
   D.tau = p->tau;
   D.omega = p->omega;
-  D.ring_block = ring_block;
+  D.ring_block_ana = ring_block;
+  D.ring_block_syn = SYN_RING_BLOCK;
   D.nblk_max = nblk_max;
   D.pairs = p->d_pairs;
   D.q = p->d_q;
@@ -416,6 +446,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   D.twiddle = p->d_tw;
   D.tw_len = tw_len;
   D.bluestein = p->d_blue;
+  D.chirp = p->d_chirp;
 
   // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range
   {
@@ -444,38 +475,55 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
     }
   }
   std::vector<int32_t> nblk(lmax + 1);
-  std::vector<WorkItem> items, items_m;
-  std::vector<double> cost;
+  std::vector<WorkItem> items_m;
+  // (m, ring block) items, longest first so that the hardware dispatcher balances the tail
+  auto make_items = [&](int rb) {
+    std::vector<WorkItem> items;
+    for (int m = 0; m <= lmax; ++m) {
+      const int nb = (p->n_active[m] + rb - 1) / rb;
+      for (int b = 0; b < nb; ++b) items.push_back({m, b});
+    }
+    std::stable_sort(items.begin(), items.end(), [&](const WorkItem& a, const WorkItem& b) {
+      auto c = [&](const WorkItem& w) {
+        const int rings = std::min(rb, p->n_active[w.m] - w.blk * rb);
+        return (double)(lmax - w.m + 1) * (double)std::max(rings, 1);
+      };
+      return c(a) > c(b);
+    });
+    if (items.empty()) items.push_back({0, 0});
+    return items;
+  };
   for (int m = 0; m <= lmax; ++m) {
     nblk[m] = (p->n_active[m] + ring_block - 1) / ring_block;
     items_m.push_back({m, 0});
-    for (int b = 0; b < nblk[m]; ++b) items.push_back({m, b});
   }
-  // longest items first so that the hardware dispatcher balances the tail
-  std::stable_sort(items.begin(), items.end(), [&](const WorkItem& a, const WorkItem& b) {
-    auto c = [&](const WorkItem& w) {
-      const int rings = std::min(ring_block, p->n_active[w.m] - w.blk * ring_block);
-      return (double)(lmax - w.m + 1) * (double)std::max(rings, 1);
-    };
-    return c(a) > c(b);
-  });
-  if (items.empty()) items.push_back({0, 0});
-  p->nitems = (int)items.size();
+  const std::vector<WorkItem> items_ana = make_items(ring_block);
+  const std::vector<WorkItem> items_syn = make_items(SYN_RING_BLOCK);
+  p->nitems_ana = (int)items_ana.size();
+  p->nitems_syn = (int)items_syn.size();
   p->nitems_m = (int)items_m.size();
   if ((rc = upload(p, &p->d_nact, p->n_active))) return bail(rc);
   if ((rc = upload(p, &p->d_nblk, nblk))) return bail(rc);
-  if ((rc = upload(p, &p->d_items, items))) return bail(rc);
+  if ((rc = upload(p, &p->d_items_ana, items_ana))) return bail(rc);
+  if ((rc = upload(p, &p->d_items_syn, items_syn))) return bail(rc);
   if ((rc = upload(p, &p->d_items_m, items_m))) return bail(rc);
   D.n_active = p->d_nact;
   D.nblk = p->d_nblk;
 
   // ---- work buffers
-  const size_t gf = (size_t)p->max_batch * p->npairs * (lmax + 1) * 4;
-  if ((rc = dev_alloc(p, &p->d_G, gf))) return bail(rc);
-  if ((rc = dev_alloc(p, &p->d_F, gf))) return bail(rc);
+  p->elem = (dtype == WF_F64) ? 8 : 4;
+  const size_t gf = (size_t)p->max_batch * p->npairs * (lmax + 1) * 4 * p->elem;
+  {
+    uint8_t* g = nullptr;
+    uint8_t* f = nullptr;
+    if ((rc = dev_alloc(p, &g, gf))) return bail(rc);
+    if ((rc = dev_alloc(p, &f, gf))) return bail(rc);
+    p->d_G = g;
+    p->d_F = f;
+  }
   if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->max_batch * nblk_max * p->nalm))) return bail(rc);
   // F entries of skipped (m, ring pair) combinations are never written: keep them zero
-  if (hipMemsetAsync(p->d_F, 0, gf * sizeof(double), p->stream) != hipSuccess ||
+  if (hipMemsetAsync(p->d_F, 0, gf, p->stream) != hipSuccess ||
       hipStreamSynchronize(p->stream) != hipSuccess) {
     set_error("initialising work buffers failed");
     return bail(WF_EDEVICE);
@@ -557,8 +605,8 @@ struct Timer {
 
 thread_local Timer* g_timer = nullptr;
 
-int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, const double* d,
-                const double* map_in, double* map_out) {
+int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, const void* d,
+                const void* map_in, void* map_out) {
   PhaseBArgs a{};
   a.mode = mode;
   a.nmaps = nmaps;
@@ -569,14 +617,15 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   a.map_in = map_in;
   a.map_out = map_out;
   if (g_timer && g_timer->begin()) return WF_EDEVICE;
-  MWF_HIP(launch_phase_b_f64(p->dev, a, p->lds_phase_b, s));
+  MWF_HIP(launch_phase_b(p->dev, a, p->lds_phase_b, p->dtype != WF_F64, s));
   if (g_timer && g_timer->end(0)) return WF_EDEVICE;
   return WF_OK;
 }
 
 int run_analysis(wf_plan_s* p, hipStream_t s, int nmaps) {
   if (g_timer && g_timer->begin()) return WF_EDEVICE;
-  MWF_HIP(launch_legendre_analysis_f64(p->dev, p->d_items, p->nitems, nmaps, p->d_G, p->d_partial, s));
+  MWF_HIP(launch_legendre_analysis_f64(p->dev, p->d_items_ana, p->nitems_ana, nmaps,
+                                       static_cast<const double*>(p->d_G), p->d_partial, s));
   if (g_timer && g_timer->end(1)) return WF_EDEVICE;
   return WF_OK;
 }
@@ -590,11 +639,11 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam,
   a.partial = p->d_partial;
   a.alm_in = alm_in;
   a.alm_out = alm_out;
-  a.F = p->d_F;
+  a.F = static_cast<double*>(p->d_F);
   const bool alm_only = (mode == SY_ALM_ONLY);
   if (g_timer && g_timer->begin()) return WF_EDEVICE;
-  MWF_HIP(launch_legendre_synthesis_f64(p->dev, alm_only ? p->d_items_m : p->d_items,
-                                        alm_only ? p->nitems_m : p->nitems, a, s));
+  MWF_HIP(launch_legendre_synthesis_f64(p->dev, alm_only ? p->d_items_m : p->d_items_syn,
+                                        alm_only ? p->nitems_m : p->nitems_syn, a, s));
   if (g_timer && g_timer->end(2)) return WF_EDEVICE;
   return WF_OK;
 }
@@ -622,7 +671,7 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
       return fail(WF_EINVAL, "every lambda must be finite and > 0");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   p->last_stream = s;
-  const double* dd = static_cast<const double*>(d);
+  const void* dd = d;
   Timer timer;
   timer.on = (p->flags & WF_FLAG_TIMING) != 0;
   timer.s = s;
@@ -638,8 +687,7 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
     double2* alm_out = (k == nsweeps - 1) ? static_cast<double2*>(s_alm) : nullptr;
     if ((rc = run_synthesis(p, s, SY_FROM_PARTIAL, nmaps, lambda[k], nullptr, alm_out))) return rc;
   }
-  if ((rc = run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr,
-                        static_cast<double*>(s_wf))))
+  if ((rc = run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr, s_wf)))
     return rc;
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
@@ -660,8 +708,7 @@ int sht_map2alm(wf_plan_t p, int32_t nmaps, const void* map, void* alm, void* hi
   if (!map || !alm) return fail(WF_EINVAL, "map and alm must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   p->last_stream = s;
-  if ((rc = run_phase_b(p, s, PB_READ_MAP | PB_ANALYSIS, nmaps, 1.0, nullptr,
-                        static_cast<const double*>(map), nullptr)))
+  if ((rc = run_phase_b(p, s, PB_READ_MAP | PB_ANALYSIS, nmaps, 1.0, nullptr, map, nullptr)))
     return rc;
   if ((rc = run_analysis(p, s, nmaps))) return rc;
   return run_synthesis(p, s, SY_ALM_ONLY, nmaps, 1.0, nullptr, static_cast<double2*>(alm));
@@ -675,8 +722,7 @@ int sht_alm2map(wf_plan_t p, int32_t nmaps, const void* alm, void* map, void* hi
   p->last_stream = s;
   if ((rc = run_synthesis(p, s, SY_FROM_ALM, nmaps, 1.0, static_cast<const double2*>(alm), nullptr)))
     return rc;
-  return run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr,
-                     static_cast<double*>(map));
+  return run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr, map);
 }
 
 }  // extern "C"

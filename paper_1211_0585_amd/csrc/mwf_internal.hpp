@@ -41,6 +41,7 @@ struct RingPair {
   int32_t bl_M;      // Bluestein convolution length (0 for power-of-two rings)
   int32_t pad_;
   int64_t bl_off;    // offset (complex entries) of this length's filter in the Bluestein table
+  int64_t chirp_off; // offset (complex entries) of this length's chirp exp(-i pi j^2 / n)
 };
 
 // Scaling of the Legendre recurrence: a value is carried as v * 2^(-SCALE_BITS * s)
@@ -61,21 +62,24 @@ struct PlanDev {
   int32_t nside, lmax, npairs, nrings;
   int64_t npix, nalm;
   double tau, omega;
-  int32_t ring_block;        // ring pairs per phase-A work item (64 * R)
-  int32_t nblk_max;          // max work-item blocks per m
+  int32_t ring_block_ana;    // ring pairs per Legendre-analysis work item (64 * R)
+  int32_t ring_block_syn;    // ring pairs per Legendre-synthesis work item (64 * R)
+  int32_t nblk_max;          // max analysis blocks per m (partial sums per m)
+  int32_t pad0_;
   const RingPair* pairs;     // [npairs]
-  const double* q;           // [npix] tau * ninv (observed) or 0
+  const void* q;             // [npix] tau * ninv (observed) or 0, in the storage type
   const double* cl;          // [lmax+1]
   const double* A;           // recurrence coefficients, padded rows (see row_off)
   const double* C;           // lambda = C * mu
   const int64_t* row_off;    // [lmax+1] start of row m in A / C (row length lmax-m+1+CHUNK)
   const double* norm_m;      // [lmax+1] signed sectoral normalisation
   const int32_t* n_active;   // [lmax+1] ring pairs with non-negligible lambda_lm
-  const int32_t* nblk;       // [lmax+1] work-item blocks of m
+  const int32_t* nblk;       // [lmax+1] analysis blocks of m
   const double2* twiddle;    // exp(-2 pi i k / tw_len), k < tw_len / 2
   int32_t tw_len;
   int32_t pad_;
   const double2* bluestein;  // FFT_M of the Bluestein chirp filter per distinct length
+  const double2* chirp;      // exp(-i pi j^2 / n) per distinct Bluestein length
 };
 
 __host__ __device__ inline int64_t alm_index(int lmax, int l, int m) {
@@ -92,19 +96,20 @@ enum PhaseBMode : int32_t {
   PB_READ_MAP = 16    // take the ring values from `map_in` instead of a synthesis
 };
 
+// Pointers are in the plan's storage type (double, or float for the FP32 / BF16x3 paths).
 struct PhaseBArgs {
   int32_t mode;
   int32_t nmaps;
   double lambda;
-  const double* F;        // [map][pair][m][4]
-  double* G;              // [map][pair][m][4]
-  const double* d;        // [map][npix]
-  const double* map_in;   // [map][npix]
-  double* map_out;        // [map][npix]
+  const void* F;          // [map][pair][m][4]
+  void* G;                // [map][pair][m][4]
+  const void* d;          // [map][npix]
+  const void* map_in;     // [map][npix]
+  void* map_out;          // [map][npix]
 };
 
-hipError_t launch_phase_b_f64(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes,
-                              hipStream_t s);
+hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes, bool fp32,
+                          hipStream_t s);
 
 // Phase A (m-parallel): Legendre analysis into per-block partial sums.
 hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,

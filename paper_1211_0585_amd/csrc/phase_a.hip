@@ -277,47 +277,45 @@ __global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
     const double* Ac = Arow + (l0 - m);
     const double2* bc = bsh + (l0 - m);
     if (!wave_any(anysc)) {
-#pragma unroll
-      for (int j = 0; j < CHUNK; ++j) {
-        const double A = Ac[j];
-        const double2 b = bc[j];
+      // steps in pairs (l - m even, then odd); only two steps are unrolled at a
+      // time so that the coefficient loads are not all hoisted into registers
+#pragma unroll 1
+      for (int j = 0; j < CHUNK; j += 2) {
+        const double A0 = Ac[j], A1 = Ac[j + 1];
+        const double2 b0 = bc[j], b1 = bc[j + 1];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
-          st.mu2[r] = st.mu1[r];
-          st.mu1[r] = mu;
-          if (j & 1) {
-            Ore[r] = fma(mu, b.x, Ore[r]);
-            Oim[r] = fma(mu, b.y, Oim[r]);
-          } else {
-            Ere[r] = fma(mu, b.x, Ere[r]);
-            Eim[r] = fma(mu, b.y, Eim[r]);
-          }
+          const double mu0 = fma(A0 * st.z[r], st.mu1[r], -st.mu2[r]);
+          const double mu1 = fma(A1 * st.z[r], mu0, -st.mu1[r]);
+          st.mu2[r] = mu0;
+          st.mu1[r] = mu1;
+          Ere[r] = fma(mu0, b0.x, Ere[r]);
+          Eim[r] = fma(mu0, b0.y, Eim[r]);
+          Ore[r] = fma(mu1, b1.x, Ore[r]);
+          Oim[r] = fma(mu1, b1.y, Oim[r]);
         }
       }
     } else {
       double cf[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) cf[r] = st.sc[r] == 0 ? 1.0 : 0.0;
-#pragma unroll
-      for (int j = 0; j < CHUNK; ++j) {
-        const double A = Ac[j];
-        const double2 b = bc[j];
+#pragma unroll 1
+      for (int j = 0; j < CHUNK; j += 2) {
+        const double A0 = Ac[j], A1 = Ac[j + 1];
+        const double2 b0 = bc[j], b1 = bc[j + 1];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
-          st.mu2[r] = st.mu1[r];
-          st.mu1[r] = mu;
-          const double me = mu * cf[r];
-          if (j & 1) {
-            Ore[r] = fma(me, b.x, Ore[r]);
-            Oim[r] = fma(me, b.y, Oim[r]);
-          } else {
-            Ere[r] = fma(me, b.x, Ere[r]);
-            Eim[r] = fma(me, b.y, Eim[r]);
-          }
+          const double mu0 = fma(A0 * st.z[r], st.mu1[r], -st.mu2[r]);
+          const double mu1 = fma(A1 * st.z[r], mu0, -st.mu1[r]);
+          st.mu2[r] = mu0;
+          st.mu1[r] = mu1;
+          const double e0 = mu0 * cf[r], e1 = mu1 * cf[r];
+          Ere[r] = fma(e0, b0.x, Ere[r]);
+          Eim[r] = fma(e0, b0.y, Eim[r]);
+          Ore[r] = fma(e1, b1.x, Ore[r]);
+          Oim[r] = fma(e1, b1.y, Oim[r]);
         }
-        if ((j & 3) == 3) rescale_check<R>(st);
+        if (j & 2) rescale_check<R>(st);    // after every fourth step
       }
     }
   }
@@ -385,7 +383,7 @@ hipError_t launch_syn_r(const PlanDev& P, const WorkItem* items, int nitems, con
 hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,
                                         int nmaps, const double* G, double2* partial,
                                         hipStream_t s) {
-  switch (P.ring_block / LANES) {
+  switch (P.ring_block_ana / LANES) {
     case 1: return launch_ana_r<1>(P, items, nitems, nmaps, G, partial, s);
     case 2: return launch_ana_r<2>(P, items, nitems, nmaps, G, partial, s);
     case 4: return launch_ana_r<4>(P, items, nitems, nmaps, G, partial, s);
@@ -395,7 +393,7 @@ hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items,
 
 hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
                                          const SynthArgs& a, hipStream_t s) {
-  switch (P.ring_block / LANES) {
+  switch (P.ring_block_syn / LANES) {
     case 1: return launch_syn_r<1>(P, items, nitems, a, s);
     case 2: return launch_syn_r<2>(P, items, nitems, a, s);
     case 4: return launch_syn_r<4>(P, items, nitems, a, s);
