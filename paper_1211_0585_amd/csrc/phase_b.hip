@@ -1,7 +1,7 @@
 // Phase B of a messenger sweep: ring-parallel work in pixel space.
 //
 // One workgroup handles one pair of mirror rings (north ring i, south ring
-// 4 nside - i), which share n_phi and the longitude of pixel 0, for one map.
+// 4 nside - i), which share n_phi and the longitude phi0 of pixel 0, for one map.
 // The two real rings are packed into one complex sequence z_j = x_N[j] + i x_S[j],
 // so each direction costs a single complex FFT of length n_phi, staged in LDS:
 //
@@ -15,14 +15,24 @@
 //              G(m) = Omega exp(-i m phi0) X[m mod n_phi], m = 0..lmax, written as
 //              S = G_N + G_S and D = G_N - G_S for the Legendre phase.
 //
-// Ring lengths are 4 i (polar caps) or 4 nside (belt): powers of two use an
-// in-place radix-2 FFT; other lengths use Bluestein's chirp-z method with a
-// power-of-two convolution of length M >= 2 n - 1 whose filter spectrum is a
-// plan-time table.
+// HEALPix rings have phi0 = pi ph_num / n_phi with ph_num in {0, 1}, so
+// exp(i n_phi phi0) = (-1)^ph_num: the phases of all aliases of a bin follow from
+// one exp(i k phi0).
+//
+// Ring lengths are 4 i (polar caps) or 4 nside (belt). Powers of two use an
+// in-place Stockham FFT (radix 4, plus one radix-2 pass for odd log2 n) whose
+// butterflies are staged in registers between two barriers per pass; other
+// lengths use Bluestein's chirp-z method: chirp, power-of-two FFT of length
+// M >= 2 n - 1, multiply by the plan-time filter spectrum, inverse FFT, chirp.
+// Arithmetic is FP64 in LDS for every storage type T (double or float) of the
+// maps and of the G / F coefficient buffers.
 #include "mwf_internal.hpp"
 
 namespace mwf {
 namespace {
+
+constexpr int PB_THREADS = 512;
+constexpr int PB_MAXB = 4;   // max radix-4 butterflies per thread (n <= 8192)
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -34,8 +44,10 @@ __device__ __forceinline__ double2 csub(double2 a, double2 b) {
   return make_double2(a.x - b.x, a.y - b.y);
 }
 __device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+// multiply by i * s (s = +1 or -1)
+__device__ __forceinline__ double2 cmul_is(double2 a, double s) { return make_double2(-s * a.y, s * a.x); }
 
-// exp(i pi num / den) for integers, with the argument reduced exactly.
+// exp(i pi num / den) with the argument reduced exactly.
 __device__ __forceinline__ double2 expipi(int64_t num, int64_t den) {
   int64_t r = num % (2 * den);
   if (r < 0) r += 2 * den;
@@ -44,68 +56,117 @@ __device__ __forceinline__ double2 expipi(int64_t num, int64_t den) {
   return make_double2(c, s);
 }
 
-// In-place radix-2 DIT FFT of length 2^lg held in LDS; dir = -1 for
-// exp(-2 pi i jk / L), +1 for exp(+...). Unnormalised. All threads of the block
-// must call it.
-__device__ void fft_pow2(double2* x, int lg, int dir, const double2* __restrict__ tw, int tw_len) {
+// Radix-4 DFT of v[0..3] in registers (sd = -1 forward, +1 inverse).
+__device__ __forceinline__ void dft4(double2& v0, double2& v1, double2& v2, double2& v3, double sd) {
+  const double2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3),
+                t3 = cmul_is(csub(v1, v3), sd);
+  v0 = cadd(t0, t2);
+  v1 = cadd(t1, t3);
+  v2 = csub(t0, t2);
+  v3 = csub(t1, t3);
+}
+
+// In-place Stockham FFT of length L = 2^lg (4 <= L <= 8192) in LDS; dir = -1:
+// exp(-2 pi i jk/L), +1: exp(+...). Unnormalised. Radix-4 passes, with one
+// radix-2 pass first when lg is odd. tw[t] = exp(-2 pi i t / tw_len), t < tw_len/2.
+// Every pass loads all butterfly inputs into registers, synchronises, then
+// writes the outputs, so a single LDS buffer suffices.
+__device__ __forceinline__ void fft_pow2(double2* x, int lg, int dir, const double2* __restrict__ tw,
+                                         int tw_len) {
   const int L = 1 << lg;
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int i = tid; i < L; i += nt) {
-    int j = (int)(__brev((unsigned)i) >> (32 - lg));
-    if (j > i) {
-      double2 t = x[i];
-      x[i] = x[j];
-      x[j] = t;
-    }
-  }
-  __syncthreads();
-  for (int s = 1; s <= lg; ++s) {
-    const int half = 1 << (s - 1);
-    const int tstep = tw_len >> s;
-    for (int b = tid; b < (L >> 1); b += nt) {
-      const int pos = b & (half - 1);
-      const int i0 = ((b >> (s - 1)) << s) + pos;
-      const int i1 = i0 + half;
-      double2 w = tw[pos * tstep];
-      if (dir > 0) w.y = -w.y;
-      const double2 u = x[i0];
-      const double2 v = cmul(w, x[i1]);
-      x[i0] = cadd(u, v);
-      x[i1] = csub(u, v);
+  const int tid = threadIdx.x;
+  const double sd = (double)dir;
+  int Ns = 1;
+  int rem = lg;
+  while (Ns < L) {
+    const bool r2 = (rem & 1) != 0;
+    double2 v[4 * PB_MAXB];
+    if (!r2) {
+      const int nb = L / 4;
+#pragma unroll
+      for (int b = 0; b < PB_MAXB; ++b) {
+        const int j = tid + b * PB_THREADS;
+        if (j < nb) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) v[4 * b + r] = x[j + r * nb];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < PB_MAXB; ++b) {
+        const int j = tid + b * PB_THREADS;
+        if (j < nb) {
+          const int k = j & (Ns - 1);
+          double2 w = tw[k * (tw_len / (Ns * 4))];
+          if (dir > 0) w.y = -w.y;
+          const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
+          double2 a0 = v[4 * b], a1 = cmul(v[4 * b + 1], w), a2 = cmul(v[4 * b + 2], w2),
+                  a3 = cmul(v[4 * b + 3], w3);
+          dft4(a0, a1, a2, a3, sd);
+          const int idx = (j - k) * 4 + k;
+          x[idx] = a0;
+          x[idx + Ns] = a1;
+          x[idx + 2 * Ns] = a2;
+          x[idx + 3 * Ns] = a3;
+        }
+      }
+      Ns *= 4;
+      rem -= 2;
+    } else {
+      const int nb = L / 2;
+#pragma unroll
+      for (int b = 0; b < 2 * PB_MAXB; ++b) {
+        const int j = tid + b * PB_THREADS;
+        if (j < nb) {
+          v[2 * b] = x[j];
+          v[2 * b + 1] = x[j + nb];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < 2 * PB_MAXB; ++b) {
+        const int j = tid + b * PB_THREADS;
+        if (j < nb) {
+          const int k = j & (Ns - 1);
+          double2 w = tw[k * (tw_len / (Ns * 2))];
+          if (dir > 0) w.y = -w.y;
+          const double2 a0 = v[2 * b], a1 = cmul(v[2 * b + 1], w);
+          const int idx = (j - k) * 2 + k;
+          x[idx] = cadd(a0, a1);
+          x[idx + Ns] = csub(a0, a1);
+        }
+      }
+      Ns *= 2;
+      rem -= 1;
     }
     __syncthreads();
   }
 }
 
-// Bluestein chirp exp(-i pi j^2 / n) with exact argument reduction.
-__device__ __forceinline__ double2 chirp(int j, int n) {
-  const int64_t jj = ((int64_t)j * j) % (2 * (int64_t)n);
-  return expipi(-jj, n);
-}
-
-// DFT of length n (any n) of x[0..n) in place, dir = -1 forward / +1 inverse,
-// using the LDS buffer x[0..M) and the filter spectrum H (length M).
+// DFT of any length n of x[0..n) in place (dir = -1 forward, +1 inverse) by
+// Bluestein's method, using the LDS buffer x[0..M), the chirp exp(-i pi j^2/n)
+// (length n) and the filter spectrum H (length M).
 __device__ void dft_bluestein(double2* x, int n, int M, int lgM, int dir,
-                              const double2* __restrict__ H, const double2* __restrict__ tw,
-                              int tw_len) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int j = tid; j < M; j += nt) {
+                              const double2* __restrict__ chirp, const double2* __restrict__ H,
+                              const double2* __restrict__ tw, int tw_len) {
+  const int tid = threadIdx.x;
+  for (int j = tid; j < M; j += PB_THREADS) {
     if (j < n) {
       double2 v = x[j];
       if (dir > 0) v = cconj(v);     // inverse DFT = conj(DFT(conj(x)))
-      x[j] = cmul(v, chirp(j, n));
+      x[j] = cmul(v, chirp[j]);
     } else {
       x[j] = make_double2(0.0, 0.0);
     }
   }
   __syncthreads();
   fft_pow2(x, lgM, -1, tw, tw_len);
-  for (int k = tid; k < M; k += nt) x[k] = cmul(x[k], H[k]);
+  for (int k = tid; k < M; k += PB_THREADS) x[k] = cmul(x[k], H[k]);
   __syncthreads();
   fft_pow2(x, lgM, +1, tw, tw_len);
   const double invM = 1.0 / (double)M;
-  for (int k = tid; k < n; k += nt) {
-    double2 v = cmul(x[k], chirp(k, n));
+  for (int k = tid; k < n; k += PB_THREADS) {
+    double2 v = cmul(x[k], chirp[k]);
     v.x *= invM;
     v.y *= invM;
     if (dir > 0) v = cconj(v);
@@ -118,12 +179,25 @@ __device__ __forceinline__ void ring_dft(double2* buf, const RingPair& rp, int d
   if (rp.log2n >= 0) {
     fft_pow2(buf, rp.log2n, dir, P.twiddle, P.tw_len);
   } else {
-    dft_bluestein(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, P.bluestein + rp.bl_off,
-                  P.twiddle, P.tw_len);
+    dft_bluestein(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, P.chirp + rp.chirp_off,
+                  P.bluestein + rp.bl_off, P.twiddle, P.tw_len);
   }
 }
 
-__global__ void __launch_bounds__(256) phase_b_f64_kernel(PlanDev P, PhaseBArgs a) {
+template <class T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+  using type = double4;
+};
+template <>
+struct Vec4<float> {
+  using type = float4;
+};
+
+template <class T>
+__global__ void __launch_bounds__(PB_THREADS, 4) phase_b_kernel(PlanDev P, PhaseBArgs a) {
+  using V4 = typename Vec4<T>::type;
   extern __shared__ double2 buf[];
   const int q = blockIdx.x;
   const int map = blockIdx.y;
@@ -131,72 +205,84 @@ __global__ void __launch_bounds__(256) phase_b_f64_kernel(PlanDev P, PhaseBArgs 
   const int n = rp.nphi;
   const int lmax = P.lmax;
   const bool equator = rp.start_s < 0;
-  const int tid = threadIdx.x, nt = blockDim.x;
+  const int tid = threadIdx.x;
   const size_t pstride = (size_t)(lmax + 1) * 4;
   const size_t pbase = ((size_t)map * P.npairs + q) * pstride;
   const int64_t mbase = (int64_t)map * P.npix;
   const int mode = a.mode;
+  const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
+  const T* __restrict__ q_tab = static_cast<const T*>(P.q);
 
   // ---- ring values into buf (x = north + i south)
   if (mode & PB_SYNTH) {
-    const double* Fp = a.F + pbase;
-    for (int k = tid; k < n; k += nt) {
+    const T* __restrict__ Fp = static_cast<const T*>(a.F) + pbase;
+    // exp(i k phi0) for k = tid + s * PB_THREADS, advanced by one complex multiply
+    double2 ph = expipi((int64_t)tid * rp.ph_num, n);
+    const double2 step = expipi((int64_t)PB_THREADS * rp.ph_num, n);
+    for (int k = tid; k < n; k += PB_THREADS) {
       double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+      double s = 1.0;                               // sig^t for m = k + t n
       for (int m = k; m <= lmax; m += n) {          // m >= 0 with m = k (mod n)
-        const double4 eo = *reinterpret_cast<const double4*>(Fp + (size_t)m * 4);
-        double2 fn = make_double2(eo.x + eo.z, eo.y + eo.w);
-        double2 fs = make_double2(eo.x - eo.z, eo.y - eo.w);
+        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+        double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
+        double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
         if (m == 0) {
           fn.y = 0.0;
           fs.y = 0.0;
         } else {
-          const double2 ph = expipi((int64_t)m * rp.ph_num, rp.ph_den);
-          fn = cmul(fn, ph);
-          fs = cmul(fs, ph);
+          const double2 phm = make_double2(s * ph.x, s * ph.y);
+          fn = cmul(fn, phm);
+          fs = cmul(fs, phm);
         }
         bn = cadd(bn, fn);
         bs = cadd(bs, fs);
+        s *= sig;
       }
-      for (int m = (k == 0 ? n : n - k); m <= lmax; m += n) {   // m < 0: -m = k (mod n)
-        const double4 eo = *reinterpret_cast<const double4*>(Fp + (size_t)m * 4);
-        const double2 ph = expipi((int64_t)m * rp.ph_num, rp.ph_den);
-        const double2 fn = cmul(make_double2(eo.x + eo.z, eo.y + eo.w), ph);
-        const double2 fs = cmul(make_double2(eo.x - eo.z, eo.y - eo.w), ph);
+      // m < 0 terms: |m| = t n - k (t >= 1), exp(i |m| phi0) = sig^t conj(exp(i k phi0))
+      s = sig;
+      for (int m = (k == 0 ? n : n - k); m <= lmax; m += n) {
+        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+        const double2 phm = make_double2(s * ph.x, -s * ph.y);
+        const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
+        const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
         bn = cadd(bn, cconj(fn));
         bs = cadd(bs, cconj(fs));
+        s *= sig;
       }
       buf[k] = make_double2(bn.x - bs.y, bn.y + bs.x);   // B_N + i B_S
+      ph = cmul(ph, step);
     }
     __syncthreads();
     ring_dft(buf, rp, +1, P);
   } else if (mode & PB_READ_MAP) {
-    const double* src = a.map_in + mbase;
-    for (int j = tid; j < n; j += nt)
-      buf[j] = make_double2(src[rp.start_n + j], equator ? 0.0 : src[rp.start_s + j]);
+    const T* src = static_cast<const T*>(a.map_in) + mbase;
+    for (int j = tid; j < n; j += PB_THREADS)
+      buf[j] = make_double2((double)src[rp.start_n + j], equator ? 0.0 : (double)src[rp.start_s + j]);
     __syncthreads();
   } else {
-    for (int j = tid; j < n; j += nt) buf[j] = make_double2(0.0, 0.0);
+    for (int j = tid; j < n; j += PB_THREADS) buf[j] = make_double2(0.0, 0.0);
     __syncthreads();
   }
 
   // ---- map output and the messenger update (Eq. 3)
   if (mode & (PB_WRITE_MAP | PB_UPDATE)) {
     const double lam = a.lambda;
-    for (int j = tid; j < n; j += nt) {
+    const T* __restrict__ d = static_cast<const T*>(a.d) + mbase;
+    T* out = static_cast<T*>(a.map_out) + mbase;
+    for (int j = tid; j < n; j += PB_THREADS) {
       double2 x = buf[j];
       if (mode & PB_WRITE_MAP) {
-        a.map_out[mbase + rp.start_n + j] = x.x;
-        if (!equator) a.map_out[mbase + rp.start_s + j] = x.y;
+        out[rp.start_n + j] = (T)x.x;
+        if (!equator) out[rp.start_s + j] = (T)x.y;
       }
       if (mode & PB_UPDATE) {
-        const double* d = a.d + mbase;
-        const double qn = P.q[rp.start_n + j];
+        const double qn = (double)q_tab[rp.start_n + j];
         const double wn = lam * qn / (1.0 + (lam - 1.0) * qn);
-        x.x = x.x + wn * (d[rp.start_n + j] - x.x);
+        x.x = x.x + wn * ((double)d[rp.start_n + j] - x.x);
         if (!equator) {
-          const double qs = P.q[rp.start_s + j];
+          const double qs = (double)q_tab[rp.start_s + j];
           const double ws = lam * qs / (1.0 + (lam - 1.0) * qs);
-          x.y = x.y + ws * (d[rp.start_s + j] - x.y);
+          x.y = x.y + ws * ((double)d[rp.start_s + j] - x.y);
         }
       }
       if (equator) x.y = 0.0;
@@ -208,37 +294,48 @@ __global__ void __launch_bounds__(256) phase_b_f64_kernel(PlanDev P, PhaseBArgs 
   // ---- analysis: forward DFT and unfold into S/D per m
   if (mode & PB_ANALYSIS) {
     ring_dft(buf, rp, -1, P);
-    double* Gp = a.G + pbase;
+    T* Gp = static_cast<T*>(a.G) + pbase;
     const double half_omega = 0.5 * P.omega;
-    for (int m = tid; m <= lmax; m += nt) {
+    double2 ph = expipi(-(int64_t)tid * rp.ph_num, n);                 // exp(-i m phi0)
+    const double2 step = expipi(-(int64_t)PB_THREADS * rp.ph_num, n);
+    for (int m = tid; m <= lmax; m += PB_THREADS) {
       const int k = m % n;
       const int nk = (k == 0) ? 0 : n - k;
       const double2 zk = buf[k], znk = buf[nk];
       // X_N = (Z_k + conj Z_nk) / 2, X_S = (Z_k - conj Z_nk) / (2 i); Omega folded in
       const double2 xn = make_double2((zk.x + znk.x) * half_omega, (zk.y - znk.y) * half_omega);
       const double2 xs = make_double2((zk.y + znk.y) * half_omega, -(zk.x - znk.x) * half_omega);
-      const double2 ph = expipi(-(int64_t)m * rp.ph_num, rp.ph_den);
       const double2 gn = cmul(xn, ph), gs = cmul(xs, ph);
-      *reinterpret_cast<double4*>(Gp + (size_t)m * 4) =
-          make_double4(gn.x + gs.x, gn.y + gs.y, gn.x - gs.x, gn.y - gs.y);
+      V4 o;
+      o.x = (T)(gn.x + gs.x);
+      o.y = (T)(gn.y + gs.y);
+      o.z = (T)(gn.x - gs.x);
+      o.w = (T)(gn.y - gs.y);
+      *reinterpret_cast<V4*>(Gp + (size_t)m * 4) = o;
+      ph = cmul(ph, step);
     }
   }
 }
 
-}  // namespace
-
-hipError_t launch_phase_b_f64(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes,
-                              hipStream_t s) {
+template <class T>
+hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes, hipStream_t s) {
   static size_t attr_bytes = 0;
   if (lds_bytes > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)phase_b_f64_kernel,
+    hipError_t e = hipFuncSetAttribute((const void*)phase_b_kernel<T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     attr_bytes = lds_bytes;
   }
   dim3 grid(P.npairs, a.nmaps);
-  hipLaunchKernelGGL(phase_b_f64_kernel, grid, dim3(256), lds_bytes, s, P, a);
+  hipLaunchKernelGGL(phase_b_kernel<T>, grid, dim3(PB_THREADS), lds_bytes, s, P, a);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes, bool fp32,
+                          hipStream_t s) {
+  return fp32 ? launch_t<float>(P, a, lds_bytes, s) : launch_t<double>(P, a, lds_bytes, s);
 }
 
 }  // namespace mwf
