@@ -62,6 +62,7 @@ struct wf_plan_s {
   void* d_F = nullptr;
   size_t elem = 8;                 // bytes per stored real (8 for WF_F64, 4 otherwise)
   double2* d_partial = nullptr;    // [batch][blk][nalm]
+  double2* d_bcoef = nullptr;      // [batch][rows_total]
   PlanDev dev{};
 };
 
@@ -156,8 +157,8 @@ int upload(wf_plan_s* p, T** ptr, const std::vector<T>& host) {
 // Ring pairs per analysis work item: two per lane once there are enough rings
 // (the cross-lane reduction is then shared by two rings); synthesis uses one per
 // lane so that long recurrences are spread over as many waves as possible.
-int ana_ring_block(int npairs) { return npairs <= 64 ? 64 : 128; }
-constexpr int SYN_RING_BLOCK = 64;
+int ana_ring_block(int npairs) { return npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256); }
+int syn_ring_block(int npairs) { return npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256); }
 
 size_t buffer_bytes(int nside, int lmax, int nmaps, int* ring_block_out, int* nblk_out) {
   const int npairs = 2 * nside;
@@ -434,7 +435,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   D.tau = p->tau;
   D.omega = p->omega;
   D.ring_block_ana = ring_block;
-  D.ring_block_syn = SYN_RING_BLOCK;
+  D.ring_block_syn = syn_ring_block(p->npairs);
   D.nblk_max = nblk_max;
   D.pairs = p->d_pairs;
   D.q = p->d_q;
@@ -447,6 +448,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   D.tw_len = tw_len;
   D.bluestein = p->d_blue;
   D.chirp = p->d_chirp;
+  D.rows_total = (int64_t)A.size();
 
   // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range
   {
@@ -498,7 +500,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
     items_m.push_back({m, 0});
   }
   const std::vector<WorkItem> items_ana = make_items(ring_block);
-  const std::vector<WorkItem> items_syn = make_items(SYN_RING_BLOCK);
+  const std::vector<WorkItem> items_syn = make_items(syn_ring_block(p->npairs));
   p->nitems_ana = (int)items_ana.size();
   p->nitems_syn = (int)items_syn.size();
   p->nitems_m = (int)items_m.size();
@@ -522,6 +524,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
     p->d_F = f;
   }
   if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->max_batch * nblk_max * p->nalm))) return bail(rc);
+  if ((rc = dev_alloc(p, &p->d_bcoef, (size_t)p->max_batch * D.rows_total))) return bail(rc);
   // F entries of skipped (m, ring pair) combinations are never written: keep them zero
   if (hipMemsetAsync(p->d_F, 0, gf, p->stream) != hipSuccess ||
       hipStreamSynchronize(p->stream) != hipSuccess) {
@@ -640,10 +643,11 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam,
   a.alm_in = alm_in;
   a.alm_out = alm_out;
   a.F = static_cast<double*>(p->d_F);
-  const bool alm_only = (mode == SY_ALM_ONLY);
+  a.bcoef = p->d_bcoef;
   if (g_timer && g_timer->begin()) return WF_EDEVICE;
-  MWF_HIP(launch_legendre_synthesis_f64(p->dev, alm_only ? p->d_items_m : p->d_items_syn,
-                                        alm_only ? p->nitems_m : p->nitems_syn, a, s));
+  MWF_HIP(launch_legendre_coeff(p->dev, a, s));
+  if (mode != SY_ALM_ONLY)
+    MWF_HIP(launch_legendre_synthesis_f64(p->dev, p->d_items_syn, p->nitems_syn, a, s));
   if (g_timer && g_timer->end(2)) return WF_EDEVICE;
   return WF_OK;
 }

@@ -80,6 +80,7 @@ struct PlanDev {
   int32_t pad_;
   const double2* bluestein;  // FFT_M of the Bluestein chirp filter per distinct length
   const double2* chirp;      // exp(-i pi j^2 / n) per distinct Bluestein length
+  int64_t rows_total;        // length of the padded per-m row layout of A / C / bcoef
 };
 
 __host__ __device__ inline int64_t alm_index(int lmax, int l, int m) {
@@ -129,9 +130,12 @@ struct SynthArgs {
   const double2* partial;   // [map][blk][nalm]
   const double2* alm_in;    // [map][nalm]
   double2* alm_out;         // [map][nalm] or null
+  double2* bcoef;           // [map][rows_total] C_l s_lm in the padded row layout
   double* F;                // [map][pair][m][4]
 };
 
+// Sum of partials, filter and C scaling (one launch over all (l, m, map)).
+hipError_t launch_legendre_coeff(const PlanDev& P, const SynthArgs& a, hipStream_t s);
 hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
                                          const SynthArgs& a, hipStream_t s);
 

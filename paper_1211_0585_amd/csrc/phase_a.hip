@@ -25,8 +25,9 @@
 //
 // Each work item is (m, block of 64 R ring pairs) handled by one wavefront; a
 // lane owns R ring pairs. The analysis reduces over lanes through LDS once per
-// chunk of 16 values of l and writes one partial sum per block; the synthesis
-// kernel sums the partials of its m, applies the filter and synthesises.
+// chunk of 16 values of l and writes one partial sum per block; a small kernel
+// sums the partials of each (l, m), applies the filter and scales by C; the
+// synthesis reads those coefficients as wave-uniform (scalar) values per chunk.
 #include "mwf_internal.hpp"
 
 namespace mwf {
@@ -213,109 +214,122 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
   }
 }
 
-template <int R>
-__global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
-    PlanDev P, const WorkItem* __restrict__ items, SynthArgs a) {
-  extern __shared__ double2 bsh[];
-  const WorkItem it = items[blockIdx.x];
-  const int m = it.m, blk = it.blk, map = blockIdx.y;
-  const int lane = threadIdx.x;
+// Filtered coefficients for the synthesis, one thread per (l, m, map):
+//   SY_FROM_PARTIAL  a = C_l sum_blk partial, s = f_l(lambda) a
+//   SY_ALM_ONLY      a = C_l sum_blk partial (the forward transform), s = a
+//   SY_FROM_ALM      s = caller's alm (imaginary part of m = 0 dropped)
+// s goes to alm_out when requested; bcoef = C_l s, in the padded row layout of
+// the recurrence tables (zeros beyond lmax) so the synthesis can read whole chunks.
+__global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
+  const int m = blockIdx.x;
+  const int map = blockIdx.y;
   const int lmax = P.lmax;
   const int nl = lmax - m + 1;
-  const int nl_pad = ((nl + CHUNK - 1) / CHUNK) * CHUNK;
   const int64_t row = alm_index(lmax, m, m);
-  const double* __restrict__ Crow = P.C + P.row_off[m];
+  const int64_t roff = P.row_off[m];
+  const double* __restrict__ Crow = P.C + roff;
   const double lam_t_o = a.lambda * P.tau * P.omega;
-
-  // ---- coefficients: s_lm (alm) and b_l = C_l s_lm for the recurrence in mu
-  for (int i = lane; i < nl_pad; i += LANES) {
+  const int nb = P.nblk[m];
+  for (int i = threadIdx.x; i < nl + CHUNK; i += blockDim.x) {
     double2 b = make_double2(0.0, 0.0);
     if (i < nl) {
-      const int l = m + i;
       double2 alm;
       if (a.mode == SY_FROM_ALM) {
         alm = a.alm_in[(size_t)map * P.nalm + row + i];
         if (m == 0) alm.y = 0.0;
       } else {
         double sr = 0.0, si = 0.0;
-        const int nb = P.nblk[m];
         for (int k = 0; k < nb; ++k) {
           const double2 p = a.partial[((size_t)map * P.nblk_max + k) * P.nalm + row + i];
           sr += p.x;
           si += p.y;
         }
         // the ring phase already applied Omega to G
-        const double sc = Crow[i];
-        alm = make_double2(sr * sc, si * sc);
+        alm = make_double2(sr * Crow[i], si * Crow[i]);
         if (a.mode == SY_FROM_PARTIAL) {
-          const double cl = P.cl[l];
+          const double cl = P.cl[m + i];
           const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
           alm.x *= f;
           alm.y *= f;
         }
       }
-      if (blk == 0 && a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = alm;
+      if (a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = alm;
       b = make_double2(alm.x * Crow[i], alm.y * Crow[i]);
     }
-    bsh[i] = b;
+    if (a.mode != SY_ALM_ONLY) a.bcoef[(size_t)map * P.rows_total + roff + i] = b;
   }
-  __syncthreads();
-  if (a.mode == SY_ALM_ONLY) return;
+}
+
+constexpr int SCH = 8;   // synthesis steps per coefficient chunk
+
+template <int R>
+__global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
+    PlanDev P, const WorkItem* __restrict__ items, SynthArgs a) {
+  const WorkItem it = items[blockIdx.x];
+  const int m = it.m, blk = it.blk, map = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int lmax = P.lmax;
+  const int64_t roff = P.row_off[m];
+  const double* __restrict__ Arow = P.A + roff;
+  const double2* __restrict__ brow = a.bcoef + (size_t)map * P.rows_total + roff;
 
   const int nact = P.n_active[m];
-  const double* __restrict__ Arow = P.A + P.row_off[m];
   RingState<R> st;
   init_rings<R>(P, m, blk, lane, nact, st);
   double Ere[R], Eim[R], Ore[R], Oim[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
 
-  for (int l0 = m; l0 <= lmax; l0 += CHUNK) {
+  for (int l0 = m; l0 <= lmax; l0 += SCH) {
+    // wave-uniform coefficients of this chunk (scalar loads)
+    double A[SCH];
+    double2 b[SCH];
+#pragma unroll
+    for (int j = 0; j < SCH; ++j) {
+      A[j] = Arow[l0 - m + j];
+      b[j] = brow[l0 - m + j];
+    }
     int anysc = 0;
 #pragma unroll
     for (int r = 0; r < R; ++r) anysc |= st.sc[r];
-    const double* Ac = Arow + (l0 - m);
-    const double2* bc = bsh + (l0 - m);
     if (!wave_any(anysc)) {
-      // steps in pairs (l - m even, then odd); only two steps are unrolled at a
-      // time so that the coefficient loads are not all hoisted into registers
-#pragma unroll 1
-      for (int j = 0; j < CHUNK; j += 2) {
-        const double A0 = Ac[j], A1 = Ac[j + 1];
-        const double2 b0 = bc[j], b1 = bc[j + 1];
+#pragma unroll
+      for (int j = 0; j < SCH; ++j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double mu0 = fma(A0 * st.z[r], st.mu1[r], -st.mu2[r]);
-          const double mu1 = fma(A1 * st.z[r], mu0, -st.mu1[r]);
-          st.mu2[r] = mu0;
-          st.mu1[r] = mu1;
-          Ere[r] = fma(mu0, b0.x, Ere[r]);
-          Eim[r] = fma(mu0, b0.y, Eim[r]);
-          Ore[r] = fma(mu1, b1.x, Ore[r]);
-          Oim[r] = fma(mu1, b1.y, Oim[r]);
+          const double mu = fma(A[j] * st.z[r], st.mu1[r], -st.mu2[r]);
+          st.mu2[r] = st.mu1[r];
+          st.mu1[r] = mu;
+          if (j & 1) {
+            Ore[r] = fma(mu, b[j].x, Ore[r]);
+            Oim[r] = fma(mu, b[j].y, Oim[r]);
+          } else {
+            Ere[r] = fma(mu, b[j].x, Ere[r]);
+            Eim[r] = fma(mu, b[j].y, Eim[r]);
+          }
         }
       }
     } else {
       double cf[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) cf[r] = st.sc[r] == 0 ? 1.0 : 0.0;
-#pragma unroll 1
-      for (int j = 0; j < CHUNK; j += 2) {
-        const double A0 = Ac[j], A1 = Ac[j + 1];
-        const double2 b0 = bc[j], b1 = bc[j + 1];
+#pragma unroll
+      for (int j = 0; j < SCH; ++j) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          const double mu0 = fma(A0 * st.z[r], st.mu1[r], -st.mu2[r]);
-          const double mu1 = fma(A1 * st.z[r], mu0, -st.mu1[r]);
-          st.mu2[r] = mu0;
-          st.mu1[r] = mu1;
-          const double e0 = mu0 * cf[r], e1 = mu1 * cf[r];
-          Ere[r] = fma(e0, b0.x, Ere[r]);
-          Eim[r] = fma(e0, b0.y, Eim[r]);
-          Ore[r] = fma(e1, b1.x, Ore[r]);
-          Oim[r] = fma(e1, b1.y, Oim[r]);
+          const double mu = fma(A[j] * st.z[r], st.mu1[r], -st.mu2[r]);
+          st.mu2[r] = st.mu1[r];
+          st.mu1[r] = mu;
+          const double me = mu * cf[r];
+          if (j & 1) {
+            Ore[r] = fma(me, b[j].x, Ore[r]);
+            Oim[r] = fma(me, b[j].y, Oim[r]);
+          } else {
+            Ere[r] = fma(me, b[j].x, Ere[r]);
+            Eim[r] = fma(me, b[j].y, Eim[r]);
+          }
         }
-        if (j & 2) rescale_check<R>(st);    // after every fourth step
+        if ((j & 3) == 3) rescale_check<R>(st);
       }
     }
   }
@@ -372,8 +386,7 @@ hipError_t launch_ana_r(const PlanDev& P, const WorkItem* items, int nitems, int
 template <int R>
 hipError_t launch_syn_r(const PlanDev& P, const WorkItem* items, int nitems, const SynthArgs& a,
                         hipStream_t s) {
-  const size_t lds = (size_t)(P.lmax + 1 + CHUNK) * sizeof(double2);
-  hipLaunchKernelGGL(legendre_synthesis_f64_kernel<R>, dim3(nitems, a.nmaps), dim3(64), lds, s,
+  hipLaunchKernelGGL(legendre_synthesis_f64_kernel<R>, dim3(nitems, a.nmaps), dim3(64), 0, s,
                      P, items, a);
   return hipGetLastError();
 }
@@ -389,6 +402,11 @@ hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items,
     case 4: return launch_ana_r<4>(P, items, nitems, nmaps, G, partial, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_legendre_coeff(const PlanDev& P, const SynthArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(legendre_coeff_kernel, dim3(P.lmax + 1, a.nmaps), dim3(256), 0, s, P, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
