@@ -24,6 +24,8 @@ if ROOT not in sys.path:
 METRIC = "messenger iters/s @Nside512 lmax1024 batched vs plain; p50/p99 solve latency"
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (vector FP64)
 PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {"f32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}   # dense matrix-core peaks
+MFMA_PRODUCTS = {"f32": 1, "bf16x3": 3, "bf16x6": 6}
 REC_FLOPS = 3               # mu = (A z) mu1 - mu2: one multiply + one FMA per value
 CON_FLOPS = 4               # one complex-by-real multiply-accumulate per (l, m, ring pair)
 
@@ -38,6 +40,9 @@ def parse():
     ap.add_argument("--latency-repeats", type=int, default=5)
     ap.add_argument("--cpu-sweeps", type=int, default=1,
                     help="oracle sweeps timed for the CPU baseline (0 disables it)")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="maps of the batched (matrix-core) runs; 0 skips them")
+    ap.add_argument("--batch-modes", default="f32,bf16x6,bf16x3")
     return ap.parse_args()
 
 
@@ -136,6 +141,12 @@ def main():
                 "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
                 "flops_per_launch": leg_flops}
 
+    # ---- batched runs: nmaps independent simulations sharing C_l, N^-1 and mask
+    batched = {}
+    if args.batch > 0:
+        batched = run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside, lmax, K, W,
+                              value)
+
     # ---- CPU baseline: the FP64 oracle, unchanged, on a bounded sample
     cpu = None
     if args.cpu_sweeps > 0:
@@ -174,11 +185,64 @@ def main():
         "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                              "sweeps": int(len(sched)), "repeats": int(len(lat))},
         "kernels": kern,
+        "batched": batched,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside, lmax, K, W, plain_value):
+    """Map-iterations/s of the matrix-core paths on args.batch maps (seeds 0..B-1)."""
+    B = args.batch
+    modes = {"f32": mwf.WF_F32, "bf16x6": mwf.WF_BF16X6, "bf16x3": mwf.WF_BF16X3}
+    model = {k: case[k] for k in ("cl", "sigma2", "mask", "ninv", "schedule", "lmax")}
+    log(f"[bench] drawing {B} simulations")
+    alms = np.stack([synth.draw(model, s)["signal_alm"] for s in range(B)]).astype(np.complex64)
+    noise = np.stack([synth.draw(model, s)["noise"] for s in range(B)]).astype(np.float32)
+    out = {"maps": B, "sweeps": K, "vs_plain_f64": {}}
+    d = None
+    for name in args.batch_modes.split(","):
+        dt = modes[name]
+        plan = mwf.Plan(nside, lmax, case["cl"], case["ninv"], mask=~case["mask"], dtype=dt, max_batch=B)
+        if d is None:
+            d = plan.alm2map(torch.from_numpy(alms).to(dev)) + torch.from_numpy(noise).to(dev)
+            torch.cuda.synchronize()
+        if W:
+            plan.solve(d, lams(W), want_alm=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve(d, lams(K))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        mit = B * K / el
+        tplan = mwf.Plan(nside, lmax, case["cl"], case["ninv"], mask=~case["mask"], dtype=dt, max_batch=B,
+                         flags=mwf.WF_FLAG_TIMING)
+        tplan.solve(d, lams(K))
+        st = tplan.last_stats
+        units = tplan.units_active
+        tplan.close()
+        plan.close()
+        ana = st.ms_analysis / max(st.n_analysis, 1)
+        syn = st.ms_synthesis / max(st.n_synthesis, 1)
+        ring = st.ms_ring / max(st.n_ring, 1)
+        useful = CON_FLOPS * units * B                   # per Legendre launch (one direction)
+        executed = useful * MFMA_PRODUCTS[name]
+        res = {"map_iters_per_s": mit, "ms_per_sweep": 1e3 * el / K,
+               "ms_legendre_analysis": ana, "ms_legendre_synthesis": syn, "ms_ring_fft_update": ring,
+               "useful_tflops_analysis": useful / (ana * 1e-3) / 1e12,
+               "executed_mfma_tflops_analysis": executed / (ana * 1e-3) / 1e12,
+               "frac_mfma_peak_analysis": executed / (ana * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[name],
+               "executed_mfma_tflops_synthesis": executed / (syn * 1e-3) / 1e12,
+               "frac_mfma_peak_synthesis": executed / (syn * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS[name]}
+        # FP32 storage per map-sweep: F read + G write (16 B each per ring pair and m), d and q
+        ring_bytes = B * (32 * 2 * nside * (lmax + 1) + 8 * 12 * nside * nside)
+        res["ring_gbs"] = ring_bytes / (ring * 1e-3) / 1e9
+        out[name] = res
+        out["vs_plain_f64"][name] = mit / plain_value
+        log(f"[bench] batched {name}: {mit:.0f} map-it/s ({1e3 * el / K:.2f} ms per sweep of {B} maps)")
+    return out
 
 
 def _blas_threads():

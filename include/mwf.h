@@ -24,10 +24,12 @@
  *   - Harmonic filter of Eq. (4): s_lm = C_l / (C_l + lambda tau Omega) a_lm
  *     (0 where C_l = 0); pixel step of Eq. (3): t = s + w (d - s) with
  *     w_p = lambda tau ninv_p / (1 + (lambda - 1) tau ninv_p).
- *   - Element type: double for WF_F64; float for WF_F32 and WF_BF16X3 (whose
- *     Legendre contraction runs on bf16 matrix cores with a three-product
- *     hi/lo split and fp32 accumulation). The Legendre recurrence is fp64 on
- *     every path.
+ *   - Element type: double for WF_F64; float for WF_F32, WF_BF16X3 and WF_BF16X6.
+ *     WF_F32 runs the Legendre contraction on fp32 matrix cores; the bf16 modes
+ *     split both operands into bf16 pieces on bf16 matrix cores with fp32
+ *     accumulation: two pieces and three products (WF_BF16X3, ~5e-6 per
+ *     transform) or three pieces and six products (WF_BF16X6, fp32-level).
+ *     The Legendre recurrence and the ring FFTs are fp64 on every path.
  *   - Device pointers are HIP device memory owned by the caller; host pointers
  *     are ordinary host memory, copied before the call returns.
  *   - Calls that take a hip_stream (a hipStream_t, NULL = default stream) only
@@ -56,7 +58,7 @@ enum {
   WF_ENOTREADY = -6     /* result not finished yet (serving)                      */
 };
 
-enum { WF_F64 = 0, WF_F32 = 1, WF_BF16X3 = 2 };
+enum { WF_F64 = 0, WF_F32 = 1, WF_BF16X3 = 2, WF_BF16X6 = 3 };
 
 /* Plan flags. WF_FLAG_TIMING: record HIP events around every kernel launch of a
  * solve on the caller's stream and report the summed durations in wf_stats; the
@@ -66,7 +68,7 @@ enum { WF_FLAG_TIMING = 1 };
 typedef struct wf_plan_s* wf_plan_t;
 
 typedef struct {
-  int32_t dtype;      /* WF_F64 (default), WF_F32 or WF_BF16X3                         */
+  int32_t dtype;      /* WF_F64 (default), WF_F32, WF_BF16X3 or WF_BF16X6              */
   int32_t max_batch;  /* largest nmaps accepted by the batched calls (>= 1; 0 -> 1)    */
   int32_t flags;      /* 0 or WF_FLAG_TIMING                                           */
   const char* tune_cache; /* reserved (may be NULL)                                    */

@@ -58,6 +58,11 @@ struct wf_plan_s {
   WorkItem* d_items_ana = nullptr; // (m, analysis block), longest first
   WorkItem* d_items_syn = nullptr; // (m, synthesis block), longest first
   WorkItem* d_items_m = nullptr;   // (m, 0), one per m
+  WorkItem* d_items_mfa = nullptr; // matrix-core analysis items (256 ring pairs)
+  WorkItem* d_items_mfs = nullptr; // matrix-core synthesis items (64 ring pairs)
+  int nitems_mfa = 0, nitems_mfs = 0;
+  float* d_partial32 = nullptr;    // [blk256][nalm][batch][2]
+  float* d_bcoef32 = nullptr;      // [rows_total][batch][2]
   void* d_G = nullptr;             // [batch][pair][m][4] in the storage type
   void* d_F = nullptr;
   size_t elem = 8;                 // bytes per stored real (8 for WF_F64, 4 otherwise)
@@ -191,7 +196,7 @@ int validate_plan_args(int nside, int lmax, const double* cl, const double* ninv
     return fail(WF_EINVAL, "lmax must satisfy 0 <= lmax <= min(4 nside - 1, 2048)");
   if (!cl || !ninv) return fail(WF_EINVAL, "cl and ninv must not be NULL");
   if (o) {
-    if (o->dtype != WF_F64 && o->dtype != WF_F32 && o->dtype != WF_BF16X3)
+    if (o->dtype != WF_F64 && o->dtype != WF_F32 && o->dtype != WF_BF16X3 && o->dtype != WF_BF16X6)
       return fail(WF_EINVAL, "unknown dtype");
     if (o->max_batch < 0) return fail(WF_EINVAL, "max_batch must be >= 0");
     if (o->flags & ~WF_FLAG_TIMING) return fail(WF_EINVAL, "unknown flags");
@@ -221,7 +226,8 @@ const char* wf_last_error(void) { return g_last_error.c_str(); }
 int wf_footprint(int32_t nside, int32_t lmax, int32_t dtype, int32_t nmaps, size_t* bytes) {
   if (!bytes) return fail(WF_EINVAL, "bytes must not be NULL");
   if (nmaps < 1) return fail(WF_EINVAL, "nmaps must be >= 1");
-  if (dtype != WF_F64 && dtype != WF_F32 && dtype != WF_BF16X3) return fail(WF_EINVAL, "unknown dtype");
+  if (dtype != WF_F64 && dtype != WF_F32 && dtype != WF_BF16X3 && dtype != WF_BF16X6)
+    return fail(WF_EINVAL, "unknown dtype");
   if (nside < 1 || nside > 1024 || !is_pow2(nside) || lmax < 0 || lmax > 4 * nside - 1 || lmax > 2048)
     return fail(WF_EINVAL, "bad nside / lmax");
   *bytes = table_bytes(nside, lmax) + buffer_bytes(nside, lmax, nmaps, nullptr, nullptr);
@@ -259,7 +265,6 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   int rc = validate_plan_args(nside, lmax, cl, ninv, opts);
   if (rc) return rc;
   const int dtype = opts ? opts->dtype : WF_F64;
-  if (dtype != WF_F64) return fail(WF_EUNSUPPORTED, "only WF_F64 plans are available in this build");
   const int64_t npix = 12LL * nside * nside;
   for (int l = 0; l <= lmax; ++l)
     if (!std::isfinite(cl[l]) || cl[l] < 0) return fail(WF_EINVAL, "cl must be finite and >= 0");
@@ -370,7 +375,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
     int64_t off = 0;
     for (int m = 0; m <= lmax; ++m) {
       row_off[m] = off;
-      off += (lmax - m + 1) + CHUNK;
+      off += (lmax - m + 1) + ROW_PAD;
     }
     A.assign(off, 0.0);
     C.assign(off, 0.0);
@@ -501,6 +506,10 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   }
   const std::vector<WorkItem> items_ana = make_items(ring_block);
   const std::vector<WorkItem> items_syn = make_items(syn_ring_block(p->npairs));
+  const std::vector<WorkItem> items_mfa = make_items(256);
+  const std::vector<WorkItem> items_mfs = make_items(64);
+  p->nitems_mfa = (int)items_mfa.size();
+  p->nitems_mfs = (int)items_mfs.size();
   p->nitems_ana = (int)items_ana.size();
   p->nitems_syn = (int)items_syn.size();
   p->nitems_m = (int)items_m.size();
@@ -508,6 +517,8 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   if ((rc = upload(p, &p->d_nblk, nblk))) return bail(rc);
   if ((rc = upload(p, &p->d_items_ana, items_ana))) return bail(rc);
   if ((rc = upload(p, &p->d_items_syn, items_syn))) return bail(rc);
+  if ((rc = upload(p, &p->d_items_mfa, items_mfa))) return bail(rc);
+  if ((rc = upload(p, &p->d_items_mfs, items_mfs))) return bail(rc);
   if ((rc = upload(p, &p->d_items_m, items_m))) return bail(rc);
   D.n_active = p->d_nact;
   D.nblk = p->d_nblk;
@@ -523,8 +534,14 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
     p->d_G = g;
     p->d_F = f;
   }
-  if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->max_batch * nblk_max * p->nalm))) return bail(rc);
-  if ((rc = dev_alloc(p, &p->d_bcoef, (size_t)p->max_batch * D.rows_total))) return bail(rc);
+  if (dtype == WF_F64) {
+    if ((rc = dev_alloc(p, &p->d_partial, (size_t)p->max_batch * nblk_max * p->nalm))) return bail(rc);
+    if ((rc = dev_alloc(p, &p->d_bcoef, (size_t)p->max_batch * D.rows_total))) return bail(rc);
+  } else {
+    const size_t nb256 = (size_t)(p->npairs + 255) / 256;
+    if ((rc = dev_alloc(p, &p->d_partial32, nb256 * p->nalm * p->max_batch * 2))) return bail(rc);
+    if ((rc = dev_alloc(p, &p->d_bcoef32, (size_t)D.rows_total * p->max_batch * 2))) return bail(rc);
+  }
   // F entries of skipped (m, ring pair) combinations are never written: keep them zero
   if (hipMemsetAsync(p->d_F, 0, gf, p->stream) != hipSuccess ||
       hipStreamSynchronize(p->stream) != hipSuccess) {
@@ -625,23 +642,51 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   return WF_OK;
 }
 
+MfmaArgs mfma_args(wf_plan_s* p, int mode, int nmaps, double lam, const void* alm_in, void* alm_out) {
+  MfmaArgs a{};
+  a.mode = mode;
+  a.nmaps = nmaps;
+  a.lambda = lam;
+  a.G = static_cast<const float*>(p->d_G);
+  a.F = static_cast<float*>(p->d_F);
+  a.partial = p->d_partial32;
+  a.bcoef = p->d_bcoef32;
+  a.alm_in = static_cast<const float2*>(alm_in);
+  a.alm_out = static_cast<float2*>(alm_out);
+  return a;
+}
+
 int run_analysis(wf_plan_s* p, hipStream_t s, int nmaps) {
   if (g_timer && g_timer->begin()) return WF_EDEVICE;
-  MWF_HIP(launch_legendre_analysis_f64(p->dev, p->d_items_ana, p->nitems_ana, nmaps,
-                                       static_cast<const double*>(p->d_G), p->d_partial, s));
+  if (p->dtype != WF_F64) {
+    MWF_HIP(launch_mfma_analysis(p->dev, p->d_items_mfa, p->nitems_mfa, p->dtype,
+                                 mfma_args(p, 0, nmaps, 1.0, nullptr, nullptr), s));
+  } else {
+    MWF_HIP(launch_legendre_analysis_f64(p->dev, p->d_items_ana, p->nitems_ana, nmaps,
+                                         static_cast<const double*>(p->d_G), p->d_partial, s));
+  }
   if (g_timer && g_timer->end(1)) return WF_EDEVICE;
   return WF_OK;
 }
 
 int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam,
-                  const double2* alm_in, double2* alm_out) {
+                  const void* alm_in, void* alm_out) {
+  if (p->dtype != WF_F64) {
+    const MfmaArgs ma = mfma_args(p, mode, nmaps, lam, alm_in, alm_out);
+    if (g_timer && g_timer->begin()) return WF_EDEVICE;
+    MWF_HIP(launch_mfma_coeff(p->dev, ma, s));
+    if (mode != SY_ALM_ONLY)
+      MWF_HIP(launch_mfma_synthesis(p->dev, p->d_items_mfs, p->nitems_mfs, p->dtype, ma, s));
+    if (g_timer && g_timer->end(2)) return WF_EDEVICE;
+    return WF_OK;
+  }
   SynthArgs a{};
   a.mode = mode;
   a.nmaps = nmaps;
   a.lambda = lam;
   a.partial = p->d_partial;
-  a.alm_in = alm_in;
-  a.alm_out = alm_out;
+  a.alm_in = static_cast<const double2*>(alm_in);
+  a.alm_out = static_cast<double2*>(alm_out);
   a.F = static_cast<double*>(p->d_F);
   a.bcoef = p->d_bcoef;
   if (g_timer && g_timer->begin()) return WF_EDEVICE;
@@ -688,7 +733,7 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
     const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
     if ((rc = run_phase_b(p, s, mode, nmaps, lambda[k], dd, nullptr, nullptr))) return rc;
     if ((rc = run_analysis(p, s, nmaps))) return rc;
-    double2* alm_out = (k == nsweeps - 1) ? static_cast<double2*>(s_alm) : nullptr;
+    void* alm_out = (k == nsweeps - 1) ? s_alm : nullptr;
     if ((rc = run_synthesis(p, s, SY_FROM_PARTIAL, nmaps, lambda[k], nullptr, alm_out))) return rc;
   }
   if ((rc = run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr, s_wf)))
@@ -715,7 +760,7 @@ int sht_map2alm(wf_plan_t p, int32_t nmaps, const void* map, void* alm, void* hi
   if ((rc = run_phase_b(p, s, PB_READ_MAP | PB_ANALYSIS, nmaps, 1.0, nullptr, map, nullptr)))
     return rc;
   if ((rc = run_analysis(p, s, nmaps))) return rc;
-  return run_synthesis(p, s, SY_ALM_ONLY, nmaps, 1.0, nullptr, static_cast<double2*>(alm));
+  return run_synthesis(p, s, SY_ALM_ONLY, nmaps, 1.0, nullptr, alm);
 }
 
 int sht_alm2map(wf_plan_t p, int32_t nmaps, const void* alm, void* map, void* hip_stream) {
@@ -724,7 +769,7 @@ int sht_alm2map(wf_plan_t p, int32_t nmaps, const void* alm, void* map, void* hi
   if (!map || !alm) return fail(WF_EINVAL, "map and alm must not be NULL");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   p->last_stream = s;
-  if ((rc = run_synthesis(p, s, SY_FROM_ALM, nmaps, 1.0, static_cast<const double2*>(alm), nullptr)))
+  if ((rc = run_synthesis(p, s, SY_FROM_ALM, nmaps, 1.0, alm, nullptr)))
     return rc;
   return run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr, map);
 }

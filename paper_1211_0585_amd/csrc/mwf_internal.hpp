@@ -48,7 +48,9 @@ struct RingPair {
 // with an integer s >= 0. While s > 0 the value is below 2^(64 - SCALE_BITS)
 // and contributes nothing; it is rescaled (s -= 1) when |v| exceeds 2^64.
 constexpr int SCALE_BITS = 512;
-constexpr int CHUNK = 16;            // l-steps per reduction chunk in phase A
+constexpr int CHUNK = 16;            // l-steps per reduction chunk in phase A (FP64 path)
+constexpr int MCH = 32;              // l-steps per staged chunk on the matrix-core path
+constexpr int ROW_PAD = 64;          // zero padding after each per-m row of A / C / coefficients
 constexpr int LANES = 64;            // wavefront width on CDNA
 
 // Work item of the m-parallel phase: one m and one block of ring pairs.
@@ -71,7 +73,7 @@ struct PlanDev {
   const double* cl;          // [lmax+1]
   const double* A;           // recurrence coefficients, padded rows (see row_off)
   const double* C;           // lambda = C * mu
-  const int64_t* row_off;    // [lmax+1] start of row m in A / C (row length lmax-m+1+CHUNK)
+  const int64_t* row_off;    // [lmax+1] start of row m in A / C (row length lmax-m+1+ROW_PAD)
   const double* norm_m;      // [lmax+1] signed sectoral normalisation
   const int32_t* n_active;   // [lmax+1] ring pairs with non-negligible lambda_lm
   const int32_t* nblk;       // [lmax+1] analysis blocks of m
@@ -138,6 +140,25 @@ struct SynthArgs {
 hipError_t launch_legendre_coeff(const PlanDev& P, const SynthArgs& a, hipStream_t s);
 hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
                                          const SynthArgs& a, hipStream_t s);
+
+// Matrix-core (FP32 / BF16x3) Legendre phase for batches stored in float.
+struct MfmaArgs {
+  int32_t mode;             // SynthMode of the coefficient step
+  int32_t nmaps;
+  double lambda;
+  const float* G;           // [map][pair][m][4]
+  float* F;                 // [map][pair][m][4]
+  float* partial;           // [blk of 256 pairs][nalm][nmaps][2]
+  float* bcoef;             // [rows_total][nmaps][2]
+  const float2* alm_in;     // [map][nalm]
+  float2* alm_out;          // [map][nalm] or null
+};
+
+hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+                                const MfmaArgs& a, hipStream_t s);
+hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s);
+hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+                                 const MfmaArgs& a, hipStream_t s);
 
 // Plan-time: which ring pairs ever reach a non-negligible lambda_lm (polar skip).
 hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s);

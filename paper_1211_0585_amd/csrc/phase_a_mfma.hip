@@ -1,0 +1,457 @@
+// Phase A on matrix cores: the Legendre contraction of a batch of maps as GEMMs.
+//
+// For each m and each parity of l - m, the analysis is the product
+//   a[l][c] = sum_q lambda_lm(z_q) P[q][c],  P = S (l-m even) or D (l-m odd),
+// with c running over (map, re/im) columns, and the synthesis is
+//   E[q][c] = sum_{l-m even} lambda_lm(z_q) b[l][c],  O likewise for odd l - m,
+// b = C_l s_lm (the filtered alm scaled by the recurrence normalisation).
+// Here M = l, K = ring pairs, N = columns (analysis) and M = ring pairs,
+// K = l, N = columns (synthesis). The Legendre values are generated on the fly
+// in FP64 by the same rescaled recurrence as the VALU path (one ring pair per
+// lane), rounded to the matrix type and staged through LDS in chunks of 32 l.
+//
+// Matrix paths:
+//   FP32    v_mfma_f32_16x16x4_f32: A 16x4 (lane i + 16 k), B 4x16 (lane j + 16 k),
+//           D 16x16 (lane j + 16 (i / 4), register i % 4).
+//   BF16x3  v_mfma_f32_16x16x32_bf16 with operands split as x = hi + lo
+//           (hi = bf16(x), lo = bf16(x - hi)) and three products
+//           hi*hi + hi*lo + lo*hi accumulated in FP32; A 16x32 (lane i + 16 (k / 8),
+//           element k % 8), B 32x16 (lane j + 16 (k / 8), element k % 8).
+//   BF16x6  the same with three pieces x = hi + mid + lo and six products (terms
+//           below 2^-24 relative dropped), reaching FP32-level accuracy.
+// Both accumulate in FP32 within a block of ring pairs; blocks are summed in FP64.
+#include "mwf_internal.hpp"
+
+namespace mwf {
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+constexpr double BIG_THRESH = 0x1p64;
+constexpr double RESCALE = 0x1p-512;
+
+// lambda_mm(z) = norm_m sin^m(theta) as v * 2^(-512 s) (same construction as the VALU path).
+__device__ __forceinline__ void seed(int m, double sin_t, double norm, double* v, int* s) {
+  int eb;
+  double b = frexp(sin_t, &eb);
+  double r = 1.0;
+  int er = 0;
+  int k = m;
+  while (k) {
+    if (k & 1) {
+      int t;
+      r = frexp(r * b, &t);
+      er += eb + t;
+    }
+    k >>= 1;
+    if (k) {
+      int t;
+      b = frexp(b * b, &t);
+      eb = 2 * eb + t;
+    }
+  }
+  int t;
+  double x = frexp(norm * r, &t);
+  const int e = er + t;
+  int sc = 0;
+  if (e < 64 - SCALE_BITS) sc = (64 - SCALE_BITS - e + SCALE_BITS - 1) / SCALE_BITS;
+  *v = ldexp(x, e + SCALE_BITS * sc);
+  *s = sc;
+}
+
+// One ring pair per thread: recurrence state.
+struct Ring {
+  double z, mu1, mu2;
+  int sc;
+};
+
+__device__ __forceinline__ Ring ring_init(const PlanDev& P, int m, int q, int nact) {
+  Ring r{0.0, 0.0, 0.0, 0};
+  if (q < nact) {
+    const RingPair rp = P.pairs[q];
+    double v;
+    int s;
+    seed(m, rp.sin_t, P.norm_m[m], &v, &s);
+    r.z = rp.z;
+    r.mu2 = -v;     // with A_mm = 0 the first step yields mu_m = v
+    r.sc = s;
+  }
+  return r;
+}
+
+// Advance MCH steps from l0 and hand each value (zero while scaled) to emit(j, value).
+template <class Emit>
+__device__ __forceinline__ void ring_steps(Ring& r, const double* __restrict__ Ac, Emit emit) {
+  const double cf = r.sc == 0 ? 1.0 : 0.0;
+#pragma unroll
+  for (int j = 0; j < MCH; ++j) {
+    const double mu = fma(Ac[j] * r.z, r.mu1, -r.mu2);
+    r.mu2 = r.mu1;
+    r.mu1 = mu;
+    emit(j, mu * cf);
+    if ((j & 3) == 3 && r.sc > 0 && fabs(r.mu1) > BIG_THRESH) {
+      r.mu1 *= RESCALE;
+      r.mu2 *= RESCALE;
+      r.sc -= 1;
+    }
+  }
+}
+
+__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)x;
+  lo = (__bf16)(x - (float)hi);
+}
+
+// x = p[0] + p[1] (+ p[2]): successive bf16 roundings of the remainder.
+template <int NP>
+__device__ __forceinline__ void split_pieces(float x, __bf16 (&p)[NP]) {
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    p[i] = (__bf16)x;
+    x = x - (float)p[i];
+  }
+}
+
+// Piece products kept for an NP-piece split (smallest first): NP = 2 -> hi*lo,
+// lo*hi, hi*hi; NP = 3 -> mid*mid, hi*lo, lo*hi, hi*mid, mid*hi, hi*hi.
+template <int NP>
+struct Products;
+template <>
+struct Products<1> {
+  static constexpr int n = 1;
+  static constexpr int a[1] = {0};
+  static constexpr int b[1] = {0};
+};
+template <>
+struct Products<2> {
+  static constexpr int n = 3;
+  static constexpr int a[3] = {0, 1, 0};
+  static constexpr int b[3] = {1, 0, 0};
+};
+template <>
+struct Products<3> {
+  static constexpr int n = 6;
+  static constexpr int a[6] = {1, 0, 2, 0, 1, 0};
+  static constexpr int b[6] = {1, 2, 0, 1, 0, 0};
+};
+
+// ------------------------------------------------------------------ analysis
+// Work item (m, block of 256 ring pairs); blockIdx.y = column group of 32
+// columns (16 maps). Wave w owns the output tile (parity w & 1, column tile w >> 1).
+// NP = 1: FP32 matrix cores; NP = 2 or 3: bf16 pieces.
+template <int NP>
+__global__ void __launch_bounds__(256) mfma_analysis_kernel(PlanDev P, const WorkItem* __restrict__ items,
+                                                            MfmaArgs a) {
+  constexpr int RB = 256;
+  constexpr bool F32 = (NP == 1);
+  constexpr int NB = F32 ? 1 : NP;
+  // staged Legendre values [parity][row][ring]; FP32 or bf16 pieces (rows 16 B aligned)
+  __shared__ float lam_f[F32 ? 2 : 1][16][RB + 4];
+  __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][16][RB + 8];
+  const WorkItem it = items[blockIdx.x];
+  const int m = it.m, blk = it.blk, cg = blockIdx.y;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lmax = P.lmax;
+  const int nact = P.n_active[m];
+  const int q0 = blk * RB;
+  const double* __restrict__ Arow = P.A + P.row_off[m];
+  const size_t pstride = (size_t)(lmax + 1) * 4;
+  const float* __restrict__ G = a.G;
+
+  Ring ring = ring_init(P, m, q0 + tid, nact);
+
+  const int par = wave & 1, ct = wave >> 1;
+  const int col = cg * 32 + ct * 16 + (lane & 15);
+  const int map = col >> 1, comp = col & 1;
+  const bool colok = map < a.nmaps;
+  const float* Gc = G + (size_t)map * P.npairs * pstride + (size_t)m * 4 + 2 * par + comp;
+
+  // B fragments: the S (even) or D (odd) column of this wave for all 256 ring pairs
+  float bf[F32 ? 64 : 1];
+  bf8 bb[NB][F32 ? 1 : 8];
+  if constexpr (F32) {
+#pragma unroll
+    for (int t = 0; t < 64; ++t) {
+      const int q = q0 + 4 * t + (lane >> 4);
+      bf[t] = (colok && q < nact) ? Gc[(size_t)q * pstride] : 0.0f;
+    }
+  } else {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int q = q0 + 32 * t + 8 * (lane >> 4) + e;
+        const float v = (colok && q < nact) ? Gc[(size_t)q * pstride] : 0.0f;
+        __bf16 pc[NB];
+        split_pieces<NB>(v, pc);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) bb[i][t][e] = pc[i];
+      }
+    }
+  }
+
+  float* out = a.partial + (size_t)blk * P.nalm * 2 * a.nmaps;
+  const int64_t row = alm_index(lmax, m, m);
+
+  for (int l0 = m; l0 <= lmax; l0 += MCH) {
+    const double* Ac = Arow + (l0 - m);
+    if constexpr (F32) {
+      ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][tid] = (float)v; });
+    } else {
+      ring_steps(ring, Ac, [&](int j, double v) {
+        __bf16 pc[NB];
+        split_pieces<NB>((float)v, pc);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) lam_b[i][j & 1][j >> 1][tid] = pc[i];
+      });
+    }
+    __syncthreads();
+    f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    if constexpr (F32) {
+#pragma unroll
+      for (int t = 0; t < 64; ++t) {
+        const float av = lam_f[par][lane & 15][4 * t + (lane >> 4)];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[t], acc, 0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        bf8 av[NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          av[i] = *reinterpret_cast<const bf8*>(&lam_b[i][par][lane & 15][32 * t + 8 * (lane >> 4)]);
+#pragma unroll
+        for (int k = 0; k < Products<NB>::n; ++k)
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[Products<NB>::a[k]], bb[Products<NB>::b[k]][t],
+                                                        acc, 0, 0, 0);
+      }
+    }
+    if (colok) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * (lane >> 4) + r;
+        const int l = l0 + 2 * i + par;
+        if (l <= lmax) out[((size_t)(row + (l - m)) * a.nmaps + map) * 2 + comp] = acc[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ synthesis
+// Work item (m, block of 64 ring pairs), one wave; blockIdx.y = column group.
+// The wave's own Legendre values are staged through its LDS in chunks of MCH l.
+template <int NP>
+__global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const WorkItem* __restrict__ items,
+                                                            MfmaArgs a) {
+  constexpr bool F32 = (NP == 1);
+  constexpr int NB = F32 ? 1 : NP;
+  // FP32: [parity][row][ring]; bf16 pieces: [piece][parity][ring][row] (row = k contiguous)
+  __shared__ float lam_f[F32 ? 2 : 1][16][64 + 4];
+  __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][64][16 + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 b_b[NB][F32 ? 1 : 2][32][16 + 8];  // [piece][parity][column][row]
+  const WorkItem it = items[blockIdx.x];
+  const int m = it.m, blk = it.blk, cg = blockIdx.y;
+  const int lane = threadIdx.x;
+  const int lmax = P.lmax;
+  const int nact = P.n_active[m];
+  const int q0 = blk * 64;
+  const int64_t roff = P.row_off[m];
+  const double* __restrict__ Arow = P.A + roff;
+  const int ncols = 2 * a.nmaps;
+  const float* __restrict__ brow = a.bcoef + (size_t)roff * ncols;
+
+  Ring ring = ring_init(P, m, q0 + lane, nact);
+  f4 acc[4][2][2];   // [ring tile][column tile][E / O]
+#pragma unroll
+  for (int qt = 0; qt < 4; ++qt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int eo = 0; eo < 2; ++eo) acc[qt][ct][eo] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  for (int l0 = m; l0 <= lmax; l0 += MCH) {
+    const double* Ac = Arow + (l0 - m);
+    if constexpr (F32) {
+      ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][lane] = (float)v; });
+    } else {
+      ring_steps(ring, Ac, [&](int j, double v) {
+        __bf16 pc[NB];
+        split_pieces<NB>((float)v, pc);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) lam_b[i][j & 1][lane][j >> 1] = pc[i];
+      });
+      // coefficient tile b[row][column] of this chunk, split and transposed to [column][row]
+      for (int e = lane; e < 2 * 16 * 32; e += 64) {
+        const int c = e & 31, rr = (e >> 5) & 15, pp = e >> 9;
+        const int colg = cg * 32 + c;
+        const float v = colg < ncols ? brow[(size_t)(l0 - m + 2 * rr + pp) * ncols + colg] : 0.0f;
+        __bf16 pc[NB];
+        split_pieces<NB>(v, pc);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) b_b[i][pp][c][rr] = pc[i];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp) {
+      if constexpr (F32) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int rr = 4 * kk + (lane >> 4);          // row within the parity
+          const size_t lrow = (size_t)(l0 - m + 2 * rr + pp) * ncols;
+          float bv[2];
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            const int colg = cg * 32 + ct * 16 + (lane & 15);
+            bv[ct] = colg < ncols ? brow[lrow + colg] : 0.0f;
+          }
+#pragma unroll
+          for (int qt = 0; qt < 4; ++qt) {
+            const float av = lam_f[pp][rr][qt * 16 + (lane & 15)];
+#pragma unroll
+            for (int ct = 0; ct < 2; ++ct)
+              acc[qt][ct][pp] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ct], acc[qt][ct][pp], 0, 0, 0);
+          }
+        }
+      } else {
+        // K = the 16 rows of this parity: lanes 32..63 supply the zero upper half of K = 32
+        const bool hi_k = (lane >> 4) >= 2;
+        const int k8 = 8 * ((lane >> 4) & 1);
+        bf8 bv[NB][2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+          const int c = ct * 16 + (lane & 15);
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            bf8 v = *reinterpret_cast<const bf8*>(&b_b[i][pp][c][k8]);
+            if (hi_k) v = bf8{};
+            bv[i][ct] = v;
+          }
+        }
+#pragma unroll
+        for (int qt = 0; qt < 4; ++qt) {
+          bf8 av[NB];
+#pragma unroll
+          for (int i = 0; i < NB; ++i) {
+            bf8 v = *reinterpret_cast<const bf8*>(&lam_b[i][pp][qt * 16 + (lane & 15)][k8]);
+            if (hi_k) v = bf8{};
+            av[i] = v;
+          }
+#pragma unroll
+          for (int ct = 0; ct < 2; ++ct) {
+            f4 c = acc[qt][ct][pp];
+#pragma unroll
+            for (int k = 0; k < Products<NB>::n; ++k)
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[Products<NB>::a[k]], bv[Products<NB>::b[k]][ct],
+                                                          c, 0, 0, 0);
+            acc[qt][ct][pp] = c;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const size_t pstride = (size_t)(lmax + 1) * 4;
+#pragma unroll
+  for (int qt = 0; qt < 4; ++qt)
+#pragma unroll
+    for (int ct = 0; ct < 2; ++ct) {
+      const int colg = cg * 32 + ct * 16 + (lane & 15);
+      const int map = colg >> 1, comp = colg & 1;
+      if (map >= a.nmaps) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int q = q0 + qt * 16 + 4 * (lane >> 4) + r;
+        if (q >= nact) continue;
+        float* Fq = a.F + ((size_t)map * P.npairs + q) * pstride + (size_t)m * 4;
+        Fq[comp] = acc[qt][ct][0][r];
+        Fq[2 + comp] = acc[qt][ct][1][r];
+      }
+    }
+}
+
+// ------------------------------------------------------------------ coefficients
+// Sum the analysis blocks (FP64), scale by C_l, apply the filter, emit the alm and
+// the synthesis coefficients b = C_l s_lm in the layout [padded row][map][re/im].
+__global__ void mfma_coeff_kernel(PlanDev P, MfmaArgs a) {
+  const int m = blockIdx.x;
+  const int lmax = P.lmax;
+  const int nl = lmax - m + 1;
+  const int64_t row = alm_index(lmax, m, m);
+  const int64_t roff = P.row_off[m];
+  const double* __restrict__ Crow = P.C + roff;
+  const double lam_t_o = a.lambda * P.tau * P.omega;
+  const int nb = (P.n_active[m] + 255) / 256;
+  const int nm = a.nmaps;
+  for (int e = threadIdx.x; e < (nl + ROW_PAD) * nm; e += blockDim.x) {
+    const int i = e / nm, map = e - i * nm;
+    double br = 0.0, bi = 0.0;
+    if (i < nl) {
+      double sr, si;
+      if (a.mode == SY_FROM_ALM) {
+        const float2 v = a.alm_in[(size_t)map * P.nalm + row + i];
+        sr = v.x;
+        si = (m == 0) ? 0.0 : v.y;
+      } else {
+        sr = si = 0.0;
+        for (int k = 0; k < nb; ++k) {
+          const float* pk = a.partial + (((size_t)k * P.nalm + row + i) * nm + map) * 2;
+          sr += pk[0];
+          si += pk[1];
+        }
+        sr *= Crow[i];
+        si *= Crow[i];
+        if (a.mode == SY_FROM_PARTIAL) {
+          const double cl = P.cl[m + i];
+          const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
+          sr *= f;
+          si *= f;
+        }
+      }
+      if (a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = make_float2((float)sr, (float)si);
+      br = sr * Crow[i];
+      bi = si * Crow[i];
+    }
+    if (a.mode != SY_ALM_ONLY) {
+      float* b = a.bcoef + ((size_t)(roff + i) * nm + map) * 2;
+      b[0] = (float)br;
+      b[1] = (float)bi;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+                                const MfmaArgs& a, hipStream_t s) {
+  const dim3 grid(nitems, (2 * a.nmaps + 31) / 32);
+  if (mode == WF_BF16X3)
+    hipLaunchKernelGGL(mfma_analysis_kernel<2>, grid, dim3(256), 0, s, P, items, a);
+  else if (mode == WF_BF16X6)
+    hipLaunchKernelGGL(mfma_analysis_kernel<3>, grid, dim3(256), 0, s, P, items, a);
+  else
+    hipLaunchKernelGGL(mfma_analysis_kernel<1>, grid, dim3(256), 0, s, P, items, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(mfma_coeff_kernel, dim3(P.lmax + 1), dim3(256), 0, s, P, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+                                 const MfmaArgs& a, hipStream_t s) {
+  const dim3 grid(nitems, (2 * a.nmaps + 31) / 32);
+  if (mode == WF_BF16X3)
+    hipLaunchKernelGGL(mfma_synthesis_kernel<2>, grid, dim3(64), 0, s, P, items, a);
+  else if (mode == WF_BF16X6)
+    hipLaunchKernelGGL(mfma_synthesis_kernel<3>, grid, dim3(64), 0, s, P, items, a);
+  else
+    hipLaunchKernelGGL(mfma_synthesis_kernel<1>, grid, dim3(64), 0, s, P, items, a);
+  return hipGetLastError();
+}
+
+}  // namespace mwf

@@ -10,7 +10,7 @@ import os
 import numpy as np
 
 WF_OK, WF_EINVAL, WF_ENOMEM, WF_EDEVICE, WF_EUNSUPPORTED, WF_EBUSY, WF_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
-WF_F64, WF_F32, WF_BF16X3 = 0, 1, 2
+WF_F64, WF_F32, WF_BF16X3, WF_BF16X6 = 0, 1, 2, 3
 WF_FLAG_TIMING = 1
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmwf.so")

@@ -123,12 +123,12 @@ def small_band_case(theta, lmax, seed=0, model_seed=0):
     return _finish(cl, sigma2, mask, lmax, seed, geometric_schedule(1e4, 40, 100))
 
 
-def satellite_case(theta, phi, lmax, seed=0, model_seed=0, nobs_scale=1.0,
-                   bcut_deg=15.0, ndisc=500, disc_deg=0.5, sigma0_muk=2200.0,
-                   n_cool=30, n_final=50):
-    """Satellite-style case: beam-smoothed bumpy spectrum; sigma_p^2 =
-    sigma0^2 / N_obs with N_obs = 300 (1 + 2 |cos theta_ecl|^4) lognormal(0, 0.2)
-    (times nobs_scale); mask |b| < bcut plus `ndisc` discs of radius disc_deg."""
+def satellite_model(theta, phi, lmax, model_seed=0, nobs_scale=1.0, bcut_deg=15.0, ndisc=500,
+                    disc_deg=0.5, sigma0_muk=2200.0, n_cool=30, n_final=50):
+    """Shared part of the satellite-style case: beam-smoothed bumpy spectrum;
+    sigma_p^2 = sigma0^2 / N_obs with N_obs = 300 (1 + 2 |cos theta_ecl|^4)
+    lognormal(0, 0.2) (times nobs_scale); mask |b| < bcut plus `ndisc` discs of
+    radius disc_deg; schedule n_cool geometric steps 1e4 -> 1, then n_final at 1."""
     lmax = int(lmax)
     cl = cl_satellite(lmax)
     ce = ecliptic_cos_colatitude(theta, phi)
@@ -139,7 +139,21 @@ def satellite_case(theta, phi, lmax, seed=0, model_seed=0, nobs_scale=1.0,
     mask = galactic_cut(theta, bcut_deg)
     if ndisc:
         mask |= disc_holes(theta, phi, ndisc, disc_deg, model_seed + 1)
-    return _finish(cl, sigma2, mask, lmax, seed, geometric_schedule(1e4, n_cool, n_final))
+    return {"cl": cl, "sigma2": sigma2, "mask": mask, "ninv": np.where(mask, 0.0, 1.0 / sigma2),
+            "schedule": geometric_schedule(1e4, n_cool, n_final), "lmax": lmax}
+
+
+def draw(model, seed):
+    """Signal alm and noise of one simulation of a shared model."""
+    return {"signal_alm": random_alm(model["cl"], model["lmax"], seed),
+            "noise": noise_draw(model["sigma2"], seed)}
+
+
+def satellite_case(theta, phi, lmax, seed=0, model_seed=0, **kw):
+    """Satellite-style case (model + one draw)."""
+    c = dict(satellite_model(theta, phi, lmax, model_seed=model_seed, **kw))
+    c.update(draw(c, seed))
+    return c
 
 
 def uniform_fullsky_case(npix, lmax, sigma_muk=30.0, seed=0, n_sweeps=3):
