@@ -241,16 +241,19 @@ __global__ void __launch_bounds__(256) mfma_analysis_kernel(PlanDev P, const Wor
 
 // ------------------------------------------------------------------ synthesis
 // Work item (m, block of 64 ring pairs), one wave; blockIdx.y = column group.
-// The wave's own Legendre values are staged through its LDS in chunks of MCH l.
+// The wave's own Legendre values are staged through its LDS: FP32 in chunks of
+// 32 l (16 per parity, K = 4 per product), bf16 pieces in chunks of 64 l
+// (32 per parity, K = 32 per product).
 template <int NP>
 __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const WorkItem* __restrict__ items,
                                                             MfmaArgs a) {
   constexpr bool F32 = (NP == 1);
   constexpr int NB = F32 ? 1 : NP;
+  constexpr int CHL = F32 ? MCH : 2 * MCH;       // l per chunk
+  constexpr int ROWS = CHL / 2;                  // rows per parity
   // FP32: [parity][row][ring]; bf16 pieces: [piece][parity][ring][row] (row = k contiguous)
   __shared__ float lam_f[F32 ? 2 : 1][16][64 + 4];
-  __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][64][16 + 8];
-  __shared__ __attribute__((aligned(16))) __bf16 b_b[NB][F32 ? 1 : 2][32][16 + 8];  // [piece][parity][column][row]
+  __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][64][ROWS + 8];
   const WorkItem it = items[blockIdx.x];
   const int m = it.m, blk = it.blk, cg = blockIdx.y;
   const int lane = threadIdx.x;
@@ -271,74 +274,78 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
 #pragma unroll
       for (int eo = 0; eo < 2; ++eo) acc[qt][ct][eo] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  for (int l0 = m; l0 <= lmax; l0 += MCH) {
+  for (int l0 = m; l0 <= lmax; l0 += CHL) {
     const double* Ac = Arow + (l0 - m);
     if constexpr (F32) {
-      ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][lane] = (float)v; });
-    } else {
-      ring_steps(ring, Ac, [&](int j, double v) {
-        __bf16 pc[NB];
-        split_pieces<NB>((float)v, pc);
+      // B fragments of the whole chunk first: their latency hides behind the recurrence
+      float bv[2][4][2];
 #pragma unroll
-        for (int i = 0; i < NB; ++i) lam_b[i][j & 1][lane][j >> 1] = pc[i];
-      });
-      // coefficient tile b[row][column] of this chunk, split and transposed to [column][row]
-      for (int e = lane; e < 2 * 16 * 32; e += 64) {
-        const int c = e & 31, rr = (e >> 5) & 15, pp = e >> 9;
-        const int colg = cg * 32 + c;
-        const float v = colg < ncols ? brow[(size_t)(l0 - m + 2 * rr + pp) * ncols + colg] : 0.0f;
-        __bf16 pc[NB];
-        split_pieces<NB>(v, pc);
+      for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
-        for (int i = 0; i < NB; ++i) b_b[i][pp][c][rr] = pc[i];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int pp = 0; pp < 2; ++pp) {
-      if constexpr (F32) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int rr = 4 * kk + (lane >> 4);          // row within the parity
-          const size_t lrow = (size_t)(l0 - m + 2 * rr + pp) * ncols;
-          float bv[2];
+        for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) {
+            const int rr = 4 * kk + (lane >> 4);
             const int colg = cg * 32 + ct * 16 + (lane & 15);
-            bv[ct] = colg < ncols ? brow[lrow + colg] : 0.0f;
+            bv[pp][kk][ct] = colg < ncols ? brow[(size_t)(l0 - m + 2 * rr + pp) * ncols + colg] : 0.0f;
           }
+      ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][lane] = (float)v; });
+      __syncthreads();
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int rr = 4 * kk + (lane >> 4);
 #pragma unroll
           for (int qt = 0; qt < 4; ++qt) {
             const float av = lam_f[pp][rr][qt * 16 + (lane & 15)];
 #pragma unroll
             for (int ct = 0; ct < 2; ++ct)
-              acc[qt][ct][pp] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[ct], acc[qt][ct][pp], 0, 0, 0);
+              acc[qt][ct][pp] =
+                  __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[pp][kk][ct], acc[qt][ct][pp], 0, 0, 0);
           }
         }
-      } else {
-        // K = the 16 rows of this parity: lanes 32..63 supply the zero upper half of K = 32
-        const bool hi_k = (lane >> 4) >= 2;
-        const int k8 = 8 * ((lane >> 4) & 1);
-        bf8 bv[NB][2];
+    } else {
+      // B fragments straight from global: lane holds rows k8..k8+7 of one column
+      const int k8 = 8 * (lane >> 4);
+      float bvf[2][2][8];
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
         for (int ct = 0; ct < 2; ++ct) {
-          const int c = ct * 16 + (lane & 15);
+          const int colg = cg * 32 + ct * 16 + (lane & 15);
 #pragma unroll
-          for (int i = 0; i < NB; ++i) {
-            bf8 v = *reinterpret_cast<const bf8*>(&b_b[i][pp][c][k8]);
-            if (hi_k) v = bf8{};
-            bv[i][ct] = v;
-          }
+          for (int e = 0; e < 8; ++e)
+            bvf[pp][ct][e] = colg < ncols ? brow[(size_t)(l0 - m + 2 * (k8 + e) + pp) * ncols + colg] : 0.0f;
         }
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        ring_steps(ring, Ac + half * MCH, [&](int j, double v) {
+          __bf16 pc[NB];
+          split_pieces<NB>((float)v, pc);
+#pragma unroll
+          for (int i = 0; i < NB; ++i) lam_b[i][j & 1][lane][half * (MCH / 2) + (j >> 1)] = pc[i];
+        });
+      }
+      __syncthreads();
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) {
+        bf8 bv[NB][2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            __bf16 pc[NB];
+            split_pieces<NB>(bvf[pp][ct][e], pc);
+#pragma unroll
+            for (int i = 0; i < NB; ++i) bv[i][ct][e] = pc[i];
+          }
 #pragma unroll
         for (int qt = 0; qt < 4; ++qt) {
           bf8 av[NB];
 #pragma unroll
-          for (int i = 0; i < NB; ++i) {
-            bf8 v = *reinterpret_cast<const bf8*>(&lam_b[i][pp][qt * 16 + (lane & 15)][k8]);
-            if (hi_k) v = bf8{};
-            av[i] = v;
-          }
+          for (int i = 0; i < NB; ++i)
+            av[i] = *reinterpret_cast<const bf8*>(&lam_b[i][pp][qt * 16 + (lane & 15)][k8]);
 #pragma unroll
           for (int ct = 0; ct < 2; ++ct) {
             f4 c = acc[qt][ct][pp];
