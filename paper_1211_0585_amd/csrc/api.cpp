@@ -55,6 +55,13 @@ struct wf_plan_s {
   double2* d_tw = nullptr;
   double2* d_blue = nullptr;
   double2* d_chirp = nullptr;
+  float2* d_tw32 = nullptr;
+  float2* d_chirp32 = nullptr;
+  float2* d_blue32 = nullptr;
+  int32_t* d_ring_small = nullptr;  // ring pairs whose FFT has at most SMALL_FFT points
+  int32_t* d_ring_large = nullptr;
+  int32_t* d_ring_all = nullptr;
+  RingClass ring_small{}, ring_large{}, ring_all{};
   WorkItem* d_items_ana = nullptr; // (m, analysis block), longest first
   WorkItem* d_items_syn = nullptr; // (m, synthesis block), longest first
   WorkItem* d_items_m = nullptr;   // (m, 0), one per m
@@ -162,6 +169,11 @@ int upload(wf_plan_s* p, T** ptr, const std::vector<T>& host) {
 // Ring pairs per analysis work item: two per lane once there are enough rings
 // (the cross-lane reduction is then shared by two rings); synthesis uses one per
 // lane so that long recurrences are spread over as many waves as possible.
+// Ring pairs whose transform (n, or the Bluestein length M) has at most this many
+// points run one wave per pair; longer ones a 512-thread workgroup.
+constexpr int SMALL_FFT = 1024;
+constexpr int SPLIT_MIN_MAPS = 4;
+
 int ana_ring_block(int npairs) { return npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256); }
 int syn_ring_block(int npairs) { return npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256); }
 
@@ -426,6 +438,36 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   if ((rc = upload(p, &p->d_tw, tw))) return bail(rc);
   if ((rc = upload(p, &p->d_blue, blue))) return bail(rc);
   if ((rc = upload(p, &p->d_chirp, chirp))) return bail(rc);
+  auto to32 = [](const std::vector<double2>& v) {
+    std::vector<float2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = make_float2((float)v[i].x, (float)v[i].y);
+    return o;
+  };
+  const std::vector<float2> tw32 = to32(tw), chirp32 = to32(chirp), blue32 = to32(blue);
+  if ((rc = upload(p, &p->d_tw32, tw32))) return bail(rc);
+  if ((rc = upload(p, &p->d_chirp32, chirp32))) return bail(rc);
+  if ((rc = upload(p, &p->d_blue32, blue32))) return bail(rc);
+  // ring classes by transform length
+  std::vector<int32_t> qs_small, qs_large;
+  int len_small = 4, len_large = 4;
+  for (int qq = 0; qq < p->npairs; ++qq) {
+    const int L = pairs[qq].log2n >= 0 ? pairs[qq].nphi : pairs[qq].bl_M;
+    if (L <= SMALL_FFT) {
+      qs_small.push_back(qq);
+      len_small = std::max(len_small, L);
+    } else {
+      qs_large.push_back(qq);
+      len_large = std::max(len_large, L);
+    }
+  }
+  std::vector<int32_t> qs_all(p->npairs);
+  for (int qq = 0; qq < p->npairs; ++qq) qs_all[qq] = qq;
+  if ((rc = upload(p, &p->d_ring_small, qs_small))) return bail(rc);
+  if ((rc = upload(p, &p->d_ring_large, qs_large))) return bail(rc);
+  if ((rc = upload(p, &p->d_ring_all, qs_all))) return bail(rc);
+  p->ring_small = RingClass{p->d_ring_small, (int32_t)qs_small.size(), len_small};
+  p->ring_large = RingClass{p->d_ring_large, (int32_t)qs_large.size(), len_large};
+  p->ring_all = RingClass{p->d_ring_all, p->npairs, std::max(len_small, len_large)};
 
   int ring_block = 0, nblk_max = 0;
   buffer_bytes(nside, lmax, p->max_batch, &ring_block, &nblk_max);
@@ -453,6 +495,9 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   D.tw_len = tw_len;
   D.bluestein = p->d_blue;
   D.chirp = p->d_chirp;
+  D.twiddle32 = p->d_tw32;
+  D.chirp32 = p->d_chirp32;
+  D.bluestein32 = p->d_blue32;
   D.rows_total = (int64_t)A.size();
 
   // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range
@@ -637,7 +682,13 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   a.map_in = map_in;
   a.map_out = map_out;
   if (g_timer && g_timer->begin()) return WF_EDEVICE;
-  MWF_HIP(launch_phase_b(p->dev, a, p->lds_phase_b, p->dtype != WF_F64, s));
+  // With few maps one launch over all ring pairs fills the GPU better than two
+  // back-to-back launches split by transform length.
+  const RingClass none{nullptr, 0, 4};
+  if (nmaps < SPLIT_MIN_MAPS)
+    MWF_HIP(launch_phase_b(p->dev, a, none, p->ring_all, p->dtype != WF_F64, s));
+  else
+    MWF_HIP(launch_phase_b(p->dev, a, p->ring_small, p->ring_large, p->dtype != WF_F64, s));
   if (g_timer && g_timer->end(0)) return WF_EDEVICE;
   return WF_OK;
 }

@@ -82,6 +82,9 @@ struct PlanDev {
   int32_t pad_;
   const double2* bluestein;  // FFT_M of the Bluestein chirp filter per distinct length
   const double2* chirp;      // exp(-i pi j^2 / n) per distinct Bluestein length
+  const float2* twiddle32;   // the same three tables rounded to float (FP32 plans)
+  const float2* chirp32;
+  const float2* bluestein32;
   int64_t rows_total;        // length of the padded per-m row layout of A / C / bcoef
 };
 
@@ -111,8 +114,16 @@ struct PhaseBArgs {
   void* map_out;          // [map][npix]
 };
 
-hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes, bool fp32,
-                          hipStream_t s);
+// Ring pairs launched together: a device list of pair indices and the largest
+// FFT length (power-of-two n, or the Bluestein M) among them.
+struct RingClass {
+  const int32_t* q;
+  int32_t count;
+  int32_t fft_len;
+};
+
+hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,
+                          const RingClass& large, bool fp32, hipStream_t s);
 
 // Phase A (m-parallel): Legendre analysis into per-block partial sums.
 hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,

@@ -24,68 +24,107 @@
 // butterflies are staged in registers between two barriers per pass; other
 // lengths use Bluestein's chirp-z method: chirp, power-of-two FFT of length
 // M >= 2 n - 1, multiply by the plan-time filter spectrum, inverse FFT, chirp.
-// Arithmetic is FP64 in LDS for every storage type T (double or float) of the
-// maps and of the G / F coefficient buffers.
+// The FFT arithmetic type C is double for FP64 plans and float for plans that
+// store maps and ring coefficients in float. Rings are launched in two classes:
+// transforms of at most 1024 points run one wave per ring pair, longer ones 512
+// threads, so short polar rings do not leave most of a large workgroup idle.
 #include "mwf_internal.hpp"
 
 namespace mwf {
 namespace {
 
-constexpr int PB_THREADS = 512;
-constexpr int PB_MAXB = 4;   // max radix-4 butterflies per thread (n <= 8192)
+constexpr int PB_MAXB = 4;   // max radix-4 butterflies per thread (L <= 4 * PB_MAXB * threads)
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <class C>
+struct CT;
+template <>
+struct CT<double> {
+  using V = double2;
+  __device__ static V make(double x, double y) { return make_double2(x, y); }
+};
+template <>
+struct CT<float> {
+  using V = float2;
+  __device__ static V make(float x, float y) { return make_float2(x, y); }
+};
+
+template <class V>
+__device__ __forceinline__ V cmul(V a, V b) {
+  V r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
-  return make_double2(a.x + b.x, a.y + b.y);
+template <class V>
+__device__ __forceinline__ V cadd(V a, V b) {
+  V r;
+  r.x = a.x + b.x;
+  r.y = a.y + b.y;
+  return r;
 }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) {
-  return make_double2(a.x - b.x, a.y - b.y);
+template <class V>
+__device__ __forceinline__ V csub(V a, V b) {
+  V r;
+  r.x = a.x - b.x;
+  r.y = a.y - b.y;
+  return r;
 }
-__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+template <class V>
+__device__ __forceinline__ V cconj(V a) {
+  a.y = -a.y;
+  return a;
+}
 // multiply by i * s (s = +1 or -1)
-__device__ __forceinline__ double2 cmul_is(double2 a, double s) { return make_double2(-s * a.y, s * a.x); }
+template <class V, class S>
+__device__ __forceinline__ V cmul_is(V a, S s) {
+  V r;
+  r.x = -s * a.y;
+  r.y = s * a.x;
+  return r;
+}
 
-// exp(i pi num / den) with the argument reduced exactly.
-__device__ __forceinline__ double2 expipi(int64_t num, int64_t den) {
+// exp(i pi num / den) with the argument reduced exactly (in FP64, then rounded to C).
+template <class C>
+__device__ __forceinline__ typename CT<C>::V expipi(int64_t num, int64_t den) {
   int64_t r = num % (2 * den);
   if (r < 0) r += 2 * den;
   double s, c;
   sincospi((double)r / (double)den, &s, &c);
-  return make_double2(c, s);
+  return CT<C>::make((C)c, (C)s);
 }
 
 // Radix-4 DFT of v[0..3] in registers (sd = -1 forward, +1 inverse).
-__device__ __forceinline__ void dft4(double2& v0, double2& v1, double2& v2, double2& v3, double sd) {
-  const double2 t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3),
-                t3 = cmul_is(csub(v1, v3), sd);
+template <class V, class S>
+__device__ __forceinline__ void dft4(V& v0, V& v1, V& v2, V& v3, S sd) {
+  const V t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = cmul_is(csub(v1, v3), sd);
   v0 = cadd(t0, t2);
   v1 = cadd(t1, t3);
   v2 = csub(t0, t2);
   v3 = csub(t1, t3);
 }
 
-// In-place Stockham FFT of length L = 2^lg (4 <= L <= 8192) in LDS; dir = -1:
-// exp(-2 pi i jk/L), +1: exp(+...). Unnormalised. Radix-4 passes, with one
-// radix-2 pass first when lg is odd. tw[t] = exp(-2 pi i t / tw_len), t < tw_len/2.
-// Every pass loads all butterfly inputs into registers, synchronises, then
-// writes the outputs, so a single LDS buffer suffices.
-__device__ __forceinline__ void fft_pow2(double2* x, int lg, int dir, const double2* __restrict__ tw,
-                                         int tw_len) {
+// In-place Stockham FFT of length L = 2^lg (4 <= L <= 4 PB_MAXB NT) in LDS, run by
+// all NT threads of the workgroup; dir = -1: exp(-2 pi i jk/L), +1: exp(+...). Unnormalised. Radix-4 passes,
+// with one radix-2 pass first when lg is odd. tw[t] = exp(-2 pi i t / tw_len),
+// t < tw_len / 2. Every pass loads all butterfly inputs into registers,
+// synchronises, then writes the outputs, so a single LDS buffer suffices.
+template <class C, int NT>
+__device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
+                                         const typename CT<C>::V* __restrict__ tw, int tw_len) {
+  using V = typename CT<C>::V;
   const int L = 1 << lg;
   const int tid = threadIdx.x;
-  const double sd = (double)dir;
+  const C sd = (C)dir;
   int Ns = 1;
   int rem = lg;
   while (Ns < L) {
     const bool r2 = (rem & 1) != 0;
-    double2 v[4 * PB_MAXB];
+    V v[4 * PB_MAXB];
     if (!r2) {
       const int nb = L / 4;
 #pragma unroll
       for (int b = 0; b < PB_MAXB; ++b) {
-        const int j = tid + b * PB_THREADS;
+        const int j = tid + b * NT;
         if (j < nb) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) v[4 * b + r] = x[j + r * nb];
@@ -94,14 +133,13 @@ __device__ __forceinline__ void fft_pow2(double2* x, int lg, int dir, const doub
       __syncthreads();
 #pragma unroll
       for (int b = 0; b < PB_MAXB; ++b) {
-        const int j = tid + b * PB_THREADS;
+        const int j = tid + b * NT;
         if (j < nb) {
           const int k = j & (Ns - 1);
-          double2 w = tw[k * (tw_len / (Ns * 4))];
+          V w = tw[k * (tw_len / (Ns * 4))];
           if (dir > 0) w.y = -w.y;
-          const double2 w2 = cmul(w, w), w3 = cmul(w2, w);
-          double2 a0 = v[4 * b], a1 = cmul(v[4 * b + 1], w), a2 = cmul(v[4 * b + 2], w2),
-                  a3 = cmul(v[4 * b + 3], w3);
+          const V w2 = cmul(w, w), w3 = cmul(w2, w);
+          V a0 = v[4 * b], a1 = cmul(v[4 * b + 1], w), a2 = cmul(v[4 * b + 2], w2), a3 = cmul(v[4 * b + 3], w3);
           dft4(a0, a1, a2, a3, sd);
           const int idx = (j - k) * 4 + k;
           x[idx] = a0;
@@ -116,7 +154,7 @@ __device__ __forceinline__ void fft_pow2(double2* x, int lg, int dir, const doub
       const int nb = L / 2;
 #pragma unroll
       for (int b = 0; b < 2 * PB_MAXB; ++b) {
-        const int j = tid + b * PB_THREADS;
+        const int j = tid + b * NT;
         if (j < nb) {
           v[2 * b] = x[j];
           v[2 * b + 1] = x[j + nb];
@@ -125,12 +163,12 @@ __device__ __forceinline__ void fft_pow2(double2* x, int lg, int dir, const doub
       __syncthreads();
 #pragma unroll
       for (int b = 0; b < 2 * PB_MAXB; ++b) {
-        const int j = tid + b * PB_THREADS;
+        const int j = tid + b * NT;
         if (j < nb) {
           const int k = j & (Ns - 1);
-          double2 w = tw[k * (tw_len / (Ns * 2))];
+          V w = tw[k * (tw_len / (Ns * 2))];
           if (dir > 0) w.y = -w.y;
-          const double2 a0 = v[2 * b], a1 = cmul(v[2 * b + 1], w);
+          const V a0 = v[2 * b], a1 = cmul(v[2 * b + 1], w);
           const int idx = (j - k) * 2 + k;
           x[idx] = cadd(a0, a1);
           x[idx + Ns] = csub(a0, a1);
@@ -146,27 +184,30 @@ __device__ __forceinline__ void fft_pow2(double2* x, int lg, int dir, const doub
 // DFT of any length n of x[0..n) in place (dir = -1 forward, +1 inverse) by
 // Bluestein's method, using the LDS buffer x[0..M), the chirp exp(-i pi j^2/n)
 // (length n) and the filter spectrum H (length M).
-__device__ void dft_bluestein(double2* x, int n, int M, int lgM, int dir,
-                              const double2* __restrict__ chirp, const double2* __restrict__ H,
-                              const double2* __restrict__ tw, int tw_len) {
+template <class C, int NT>
+__device__ void dft_bluestein(typename CT<C>::V* x, int n, int M, int lgM, int dir,
+                              const typename CT<C>::V* __restrict__ chirp,
+                              const typename CT<C>::V* __restrict__ H,
+                              const typename CT<C>::V* __restrict__ tw, int tw_len) {
+  using V = typename CT<C>::V;
   const int tid = threadIdx.x;
-  for (int j = tid; j < M; j += PB_THREADS) {
+  for (int j = tid; j < M; j += NT) {
     if (j < n) {
-      double2 v = x[j];
+      V v = x[j];
       if (dir > 0) v = cconj(v);     // inverse DFT = conj(DFT(conj(x)))
       x[j] = cmul(v, chirp[j]);
     } else {
-      x[j] = make_double2(0.0, 0.0);
+      x[j] = CT<C>::make(0, 0);
     }
   }
   __syncthreads();
-  fft_pow2(x, lgM, -1, tw, tw_len);
-  for (int k = tid; k < M; k += PB_THREADS) x[k] = cmul(x[k], H[k]);
+  fft_pow2<C, NT>(x, lgM, -1, tw, tw_len);
+  for (int k = tid; k < M; k += NT) x[k] = cmul(x[k], H[k]);
   __syncthreads();
-  fft_pow2(x, lgM, +1, tw, tw_len);
-  const double invM = 1.0 / (double)M;
-  for (int k = tid; k < n; k += PB_THREADS) {
-    double2 v = cmul(x[k], chirp[k]);
+  fft_pow2<C, NT>(x, lgM, +1, tw, tw_len);
+  const C invM = (C)1 / (C)M;
+  for (int k = tid; k < n; k += NT) {
+    V v = cmul(x[k], chirp[k]);
     v.x *= invM;
     v.y *= invM;
     if (dir > 0) v = cconj(v);
@@ -175,12 +216,30 @@ __device__ void dft_bluestein(double2* x, int n, int M, int lgM, int dir,
   __syncthreads();
 }
 
-__device__ __forceinline__ void ring_dft(double2* buf, const RingPair& rp, int dir, const PlanDev& P) {
+// Plan tables in the FFT arithmetic type.
+template <class C>
+struct Tabs;
+template <>
+struct Tabs<double> {
+  __device__ static const double2* tw(const PlanDev& P) { return P.twiddle; }
+  __device__ static const double2* chirp(const PlanDev& P) { return P.chirp; }
+  __device__ static const double2* blue(const PlanDev& P) { return P.bluestein; }
+};
+template <>
+struct Tabs<float> {
+  __device__ static const float2* tw(const PlanDev& P) { return P.twiddle32; }
+  __device__ static const float2* chirp(const PlanDev& P) { return P.chirp32; }
+  __device__ static const float2* blue(const PlanDev& P) { return P.bluestein32; }
+};
+
+template <class C, int NT>
+__device__ __forceinline__ void ring_dft(typename CT<C>::V* buf, const RingPair& rp, int dir,
+                                         const PlanDev& P) {
   if (rp.log2n >= 0) {
-    fft_pow2(buf, rp.log2n, dir, P.twiddle, P.tw_len);
+    fft_pow2<C, NT>(buf, rp.log2n, dir, Tabs<C>::tw(P), P.tw_len);
   } else {
-    dft_bluestein(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, P.chirp + rp.chirp_off,
-                  P.bluestein + rp.bl_off, P.twiddle, P.tw_len);
+    dft_bluestein<C, NT>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, Tabs<C>::chirp(P) + rp.chirp_off,
+                         Tabs<C>::blue(P) + rp.bl_off, Tabs<C>::tw(P), P.tw_len);
   }
 }
 
@@ -195,11 +254,14 @@ struct Vec4<float> {
   using type = float4;
 };
 
-template <class T>
-__global__ void __launch_bounds__(PB_THREADS, 4) phase_b_kernel(PlanDev P, PhaseBArgs a) {
+template <class T, class C, int NT>
+__global__ void __launch_bounds__(NT, 4) phase_b_kernel(PlanDev P, PhaseBArgs a,
+                                                                       const int32_t* __restrict__ qlist) {
   using V4 = typename Vec4<T>::type;
-  extern __shared__ double2 buf[];
-  const int q = blockIdx.x;
+  using V = typename CT<C>::V;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  V* buf = reinterpret_cast<V*>(lds_raw);
+  const int q = qlist[blockIdx.x];
   const int map = blockIdx.y;
   const RingPair rp = P.pairs[q];
   const int n = rp.nphi;
@@ -216,10 +278,10 @@ __global__ void __launch_bounds__(PB_THREADS, 4) phase_b_kernel(PlanDev P, Phase
   // ---- ring values into buf (x = north + i south)
   if (mode & PB_SYNTH) {
     const T* __restrict__ Fp = static_cast<const T*>(a.F) + pbase;
-    // exp(i k phi0) for k = tid + s * PB_THREADS, advanced by one complex multiply
-    double2 ph = expipi((int64_t)tid * rp.ph_num, n);
-    const double2 step = expipi((int64_t)PB_THREADS * rp.ph_num, n);
-    for (int k = tid; k < n; k += PB_THREADS) {
+    // exp(i k phi0) for k = tid + s * NT, advanced by one complex multiply
+    double2 ph = expipi<double>((int64_t)tid * rp.ph_num, n);
+    const double2 step = expipi<double>((int64_t)NT * rp.ph_num, n);
+    for (int k = tid; k < n; k += NT) {
       double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
       double s = 1.0;                               // sig^t for m = k + t n
       for (int m = k; m <= lmax; m += n) {          // m >= 0 with m = k (mod n)
@@ -249,18 +311,18 @@ __global__ void __launch_bounds__(PB_THREADS, 4) phase_b_kernel(PlanDev P, Phase
         bs = cadd(bs, cconj(fs));
         s *= sig;
       }
-      buf[k] = make_double2(bn.x - bs.y, bn.y + bs.x);   // B_N + i B_S
+      buf[k] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
       ph = cmul(ph, step);
     }
     __syncthreads();
-    ring_dft(buf, rp, +1, P);
+    ring_dft<C, NT>(buf, rp, +1, P);
   } else if (mode & PB_READ_MAP) {
     const T* src = static_cast<const T*>(a.map_in) + mbase;
-    for (int j = tid; j < n; j += PB_THREADS)
-      buf[j] = make_double2((double)src[rp.start_n + j], equator ? 0.0 : (double)src[rp.start_s + j]);
+    for (int j = tid; j < n; j += NT)
+      buf[j] = CT<C>::make((C)src[rp.start_n + j], equator ? (C)0 : (C)src[rp.start_s + j]);
     __syncthreads();
   } else {
-    for (int j = tid; j < n; j += PB_THREADS) buf[j] = make_double2(0.0, 0.0);
+    for (int j = tid; j < n; j += NT) buf[j] = CT<C>::make(0, 0);
     __syncthreads();
   }
 
@@ -269,8 +331,9 @@ __global__ void __launch_bounds__(PB_THREADS, 4) phase_b_kernel(PlanDev P, Phase
     const double lam = a.lambda;
     const T* __restrict__ d = static_cast<const T*>(a.d) + mbase;
     T* out = static_cast<T*>(a.map_out) + mbase;
-    for (int j = tid; j < n; j += PB_THREADS) {
-      double2 x = buf[j];
+    for (int j = tid; j < n; j += NT) {
+      const V xv = buf[j];
+      double2 x = make_double2((double)xv.x, (double)xv.y);
       if (mode & PB_WRITE_MAP) {
         out[rp.start_n + j] = (T)x.x;
         if (!equator) out[rp.start_s + j] = (T)x.y;
@@ -286,22 +349,24 @@ __global__ void __launch_bounds__(PB_THREADS, 4) phase_b_kernel(PlanDev P, Phase
         }
       }
       if (equator) x.y = 0.0;
-      buf[j] = x;
+      buf[j] = CT<C>::make((C)x.x, (C)x.y);
     }
     __syncthreads();
   }
 
   // ---- analysis: forward DFT and unfold into S/D per m
   if (mode & PB_ANALYSIS) {
-    ring_dft(buf, rp, -1, P);
+    ring_dft<C, NT>(buf, rp, -1, P);
     T* Gp = static_cast<T*>(a.G) + pbase;
     const double half_omega = 0.5 * P.omega;
-    double2 ph = expipi(-(int64_t)tid * rp.ph_num, n);                 // exp(-i m phi0)
-    const double2 step = expipi(-(int64_t)PB_THREADS * rp.ph_num, n);
-    for (int m = tid; m <= lmax; m += PB_THREADS) {
+    double2 ph = expipi<double>(-(int64_t)tid * rp.ph_num, n);          // exp(-i m phi0)
+    const double2 step = expipi<double>(-(int64_t)NT * rp.ph_num, n);
+    for (int m = tid; m <= lmax; m += NT) {
       const int k = m % n;
       const int nk = (k == 0) ? 0 : n - k;
-      const double2 zk = buf[k], znk = buf[nk];
+      const V zkv = buf[k], znkv = buf[nk];
+      const double2 zk = make_double2((double)zkv.x, (double)zkv.y);
+      const double2 znk = make_double2((double)znkv.x, (double)znkv.y);
       // X_N = (Z_k + conj Z_nk) / 2, X_S = (Z_k - conj Z_nk) / (2 i); Omega folded in
       const double2 xn = make_double2((zk.x + znk.x) * half_omega, (zk.y - znk.y) * half_omega);
       const double2 xs = make_double2((zk.y + znk.y) * half_omega, -(zk.x - znk.x) * half_omega);
@@ -317,25 +382,35 @@ __global__ void __launch_bounds__(PB_THREADS, 4) phase_b_kernel(PlanDev P, Phase
   }
 }
 
-template <class T>
-hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes, hipStream_t s) {
+template <class T, class C, int NT>
+hipError_t launch_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
   static size_t attr_bytes = 0;
-  if (lds_bytes > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)phase_b_kernel<T>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+  const size_t lds = rc.fft_len * sizeof(typename CT<C>::V);
+  if (lds > attr_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)phase_b_kernel<T, C, NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    attr_bytes = lds_bytes;
+    attr_bytes = lds;
   }
-  dim3 grid(P.npairs, a.nmaps);
-  hipLaunchKernelGGL(phase_b_kernel<T>, grid, dim3(PB_THREADS), lds_bytes, s, P, a);
+  hipLaunchKernelGGL((phase_b_kernel<T, C, NT>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q);
   return hipGetLastError();
+}
+
+template <class T, class C>
+hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,
+                    const RingClass& large, hipStream_t s) {
+  hipError_t e = launch_class<T, C, 512>(P, a, large, s);
+  if (e != hipSuccess) return e;
+  return launch_class<T, C, 64>(P, a, small, s);
 }
 
 }  // namespace
 
-hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, size_t lds_bytes, bool fp32,
-                          hipStream_t s) {
-  return fp32 ? launch_t<float>(P, a, lds_bytes, s) : launch_t<double>(P, a, lds_bytes, s);
+hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,
+                          const RingClass& large, bool fp32, hipStream_t s) {
+  return fp32 ? launch_t<float, float>(P, a, small, large, s)
+              : launch_t<double, double>(P, a, small, large, s);
 }
 
 }  // namespace mwf
