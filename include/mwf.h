@@ -66,12 +66,14 @@ enum { WF_F64 = 0, WF_F32 = 1, WF_BF16X3 = 2, WF_BF16X6 = 3 };
 enum { WF_FLAG_TIMING = 1 };
 
 typedef struct wf_plan_s* wf_plan_t;
+typedef struct wf_group_s* wf_group_t;
 
 typedef struct {
   int32_t dtype;      /* WF_F64 (default), WF_F32, WF_BF16X3 or WF_BF16X6              */
   int32_t max_batch;  /* largest nmaps accepted by the batched calls (>= 1; 0 -> 1)    */
   int32_t flags;      /* 0 or WF_FLAG_TIMING                                           */
-  const char* tune_cache; /* reserved (may be NULL)                                    */
+  const char* tune_cache; /* NULL, or a text file of launch shapes found by wf_autotune:
+                           read at plan time, appended to by wf_autotune            */
 } wf_plan_opts;
 
 typedef struct {
@@ -166,6 +168,58 @@ int wf_plan_info(wf_plan_t plan, int64_t* npix, int64_t* nalm, double* tau,
  * HEALPix RING order at this nside (host arrays of npix doubles).
  */
 int wf_pixel_angles(int32_t nside, double* theta, double* phi);
+
+/*
+ * wf_autotune -- time every launch shape of the matrix-core Legendre kernels
+ * (analysis: 1 or 2 column tiles per workgroup; synthesis: 1, 2 or 4 column tiles
+ * per wave) on this plan at nmaps maps, keep the fastest in the plan, record it
+ * in the process-wide cache (and in opts.tune_cache if given) so that later plans
+ * of the same shape start with it. Overwrites the plan's work buffers (run it
+ * before a solve, not between the calls of one). Waits for its own launches.
+ *   ana_ct, syn_nct  NULL, or receive the chosen shape (0 for WF_F64 plans, which
+ *                    have a single shape)
+ * Errors: WF_EINVAL (nmaps outside [1, max_batch]), WF_EDEVICE.
+ */
+int wf_autotune(wf_plan_t plan, int32_t nmaps, void* hip_stream, int32_t* ana_ct,
+                int32_t* syn_nct);
+
+/*
+ * Task groups: several plans (different nside / lmax / C_l / N^-1, one shared
+ * matrix-core dtype) stepped together, one kernel launch per phase for all of
+ * them, so that a batch of uneven map sizes (the independent maps of Sect. 3's
+ * timing runs at several resolutions) fills the GPU as one launch would.
+ *
+ * wf_group_create -- group nplans existing plans; plan i runs nmaps[i] maps
+ *   (1 <= nmaps[i] <= its max_batch). The group borrows the plans: they must
+ *   outlive it and must not run other calls while a group solve is in flight.
+ *   Errors: WF_EINVAL (NULL plan, mixed dtypes, bad nmaps), WF_EUNSUPPORTED
+ *   (WF_F64 plans: run those with wf_solve_batch).
+ */
+int wf_group_create(wf_group_t* out, int32_t nplans, const wf_plan_t* plans,
+                    const int32_t* nmaps);
+
+/*
+ * wf_group_solve -- wf_solve_batch for every plan of the group with one shared
+ * lambda schedule. d[i], s_wf[i] (and s_alm[i] unless s_alm is NULL) are device
+ * buffers laid out as for plan i's wf_solve_batch. Results equal those of the
+ * separate wf_solve_batch calls up to the floating-point summation order fixed by
+ * the group's launch shape. The call synchronises the stream once before it
+ * uploads the group's task table.
+ * Errors: WF_EINVAL (NULL buffers, bad schedule), WF_ENOMEM, WF_EDEVICE.
+ */
+int wf_group_solve(wf_group_t group, const void* const* d, void* const* s_wf,
+                   void* const* s_alm, const double* lambda, int32_t nsweeps,
+                   void* hip_stream, wf_stats* stats);
+
+/*
+ * wf_group_autotune -- time two-sweep group solves over every launch shape (6
+ * combinations) and keep the fastest for this group. Overwrites s_wf.
+ */
+int wf_group_autotune(wf_group_t group, const void* const* d, void* const* s_wf,
+                      void* hip_stream, int32_t* ana_ct, int32_t* syn_nct);
+
+/* wf_group_destroy -- free a group (not its plans); waits for the device. */
+void wf_group_destroy(wf_group_t group);
 
 /* wf_sync -- wait for the plan's stream work; reports asynchronous device errors. */
 int wf_sync(wf_plan_t plan);

@@ -1,4 +1,5 @@
 """Build libmwf.so (HIP kernels + C ABI) in-tree for gfx950 with hipcc."""
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -10,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmwf.so")
 
-SOURCES = ["api.cpp", "phase_a.hip", "phase_a_mfma.hip", "phase_b.hip"]
+SOURCES = ["api.cpp", "geometry.cpp", "phase_a.hip", "phase_a_mfma.hip", "phase_b.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
@@ -41,7 +42,7 @@ def build(verbose=False):
     """Compile every source and link libmwf.so next to this file."""
     hipcc = _hipcc()
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
@@ -50,8 +51,12 @@ def build(verbose=False):
             cmd[1:1] = DEVICE
         else:
             cmd[1:1] = ["--offload-arch=" + ARCH]
-        _run(cmd, verbose)
+        cmds.append(cmd)
         objs.append(obj)
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
     os.replace(tmp, LIB)

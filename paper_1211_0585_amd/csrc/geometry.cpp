@@ -1,0 +1,323 @@
+// Plan-time tables shared by every plan of a given (device, nside, lmax):
+// HEALPix ring geometry (Gorski et al. 2005), the rescaled Legendre recurrence
+// coefficients, FFT twiddles and Bluestein tables, and the polar-skip work lists.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <map>
+#include <tuple>
+
+#include "runtime.hpp"
+
+namespace mwf {
+
+namespace {
+
+constexpr long double PI_L = 3.141592653589793238462643383279502884L;
+// Ring pairs whose transform (n, or the Bluestein length M) has at most this many
+// points run one wave per pair when batched; longer ones a 512-thread workgroup.
+constexpr int SMALL_FFT = 1024;
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int ilog2_ceil(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+// In-place iterative radix-2 FFT in long double (plan time only).
+void host_fft(std::vector<std::complex<long double>>& a, int sign) {
+  const size_t n = a.size();
+  for (size_t i = 1, j = 0; i < n; ++i) {
+    size_t bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (size_t len = 2; len <= n; len <<= 1) {
+    for (size_t k = 0; k < len / 2; ++k) {
+      const long double ang = sign * 2.0L * PI_L * (long double)k / (long double)len;
+      const std::complex<long double> w(cosl(ang), sinl(ang));
+      for (size_t i = k; i < n; i += len) {
+        const auto u = a[i], v = a[i + len / 2] * w;
+        a[i] = u + v;
+        a[i + len / 2] = u - v;
+      }
+    }
+  }
+}
+
+int ana_ring_block(int npairs) { return npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256); }
+
+std::mutex g_geo_mu;
+std::map<std::tuple<int, int, int>, std::shared_ptr<Geometry>> g_geo;
+
+int build_geometry(Geometry& g) {
+  const int nside = g.nside, lmax = g.lmax;
+  g.npix = 12LL * nside * nside;
+  g.nalm = (int64_t)(lmax + 1) * (lmax + 2) / 2;
+  g.nrings = 4 * nside - 1;
+  g.npairs = 2 * nside;
+  g.omega = 4.0 * 3.141592653589793238462643383279502884 / (double)g.npix;
+  int rc;
+
+  // ---- ring pairs, equator first
+  std::vector<RingPair> pairs(g.npairs);
+  std::vector<int> blue_len;
+  for (int q = 0; q < g.npairs; ++q) {
+    const int i = 2 * nside - q;
+    const RingGeo gn = ring_geometry(nside, i);
+    RingPair rp{};
+    rp.z = gn.z;
+    rp.sin_t = std::sqrt((1.0 - gn.z) * (1.0 + gn.z));
+    rp.start_n = gn.start;
+    rp.start_s = (q == 0) ? -1 : ring_geometry(nside, 4 * nside - i).start;
+    rp.nphi = gn.nphi;
+    rp.ph_num = gn.ph_num;
+    rp.ph_den = gn.ph_den;
+    if (is_pow2(gn.nphi)) {
+      rp.log2n = ilog2_ceil(gn.nphi);
+      rp.bl_M = 0;
+      g.tw_len = std::max(g.tw_len, gn.nphi);
+    } else {
+      rp.log2n = -1;
+      rp.bl_M = 1 << ilog2_ceil(2 * gn.nphi - 1);
+      g.tw_len = std::max(g.tw_len, rp.bl_M);
+      blue_len.push_back(gn.nphi);
+    }
+    pairs[q] = rp;
+  }
+
+  // ---- Bluestein chirps exp(-i pi j^2 / n) and filter spectra H = FFT_M(h),
+  //      h_j = exp(+i pi j^2 / n) for |j| < n
+  std::vector<double2> blue, chirp;
+  {
+    std::vector<int64_t> off_of(4 * nside + 1, -1), coff_of(4 * nside + 1, -1);
+    for (int n : blue_len) {
+      if (off_of[n] >= 0) continue;
+      coff_of[n] = (int64_t)chirp.size();
+      for (int j = 0; j < n; ++j) {
+        const long double ang = -PI_L * (long double)(((int64_t)j * j) % (2LL * n)) / (long double)n;
+        chirp.push_back(make_double2((double)cosl(ang), (double)sinl(ang)));
+      }
+      const int M = 1 << ilog2_ceil(2 * n - 1);
+      std::vector<std::complex<long double>> h(M, 0.0L);
+      for (int j = 0; j < n; ++j) {
+        const long double ang = PI_L * (long double)(((int64_t)j * j) % (2LL * n)) / (long double)n;
+        const std::complex<long double> w(cosl(ang), sinl(ang));
+        h[j] = w;
+        if (j) h[M - j] = w;
+      }
+      host_fft(h, -1);
+      off_of[n] = (int64_t)blue.size();
+      for (int k = 0; k < M; ++k) blue.push_back(make_double2((double)h[k].real(), (double)h[k].imag()));
+    }
+    for (auto& rp : pairs)
+      if (rp.log2n < 0) {
+        rp.bl_off = off_of[rp.nphi];
+        rp.chirp_off = coff_of[rp.nphi];
+      }
+    if (blue.empty()) blue.push_back(make_double2(0.0, 0.0));
+    if (chirp.empty()) chirp.push_back(make_double2(0.0, 0.0));
+  }
+  std::vector<double2> tw(g.tw_len / 2);
+  for (int k = 0; k < g.tw_len / 2; ++k) {
+    const long double ang = -2.0L * PI_L * (long double)k / (long double)g.tw_len;
+    tw[k] = make_double2((double)cosl(ang), (double)sinl(ang));
+  }
+  auto to32 = [](const std::vector<double2>& v) {
+    std::vector<float2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = make_float2((float)v[i].x, (float)v[i].y);
+    return o;
+  };
+
+  // ---- recurrence tables mu_l = (A z) mu_{l-1} - mu_{l-2}, lambda = C mu; padded rows
+  std::vector<int64_t> row_off(lmax + 1);
+  std::vector<double> A, C, norm(lmax + 1);
+  {
+    int64_t off = 0;
+    for (int m = 0; m <= lmax; ++m) {
+      row_off[m] = off;
+      off += (lmax - m + 1) + ROW_PAD;
+    }
+    g.rows_total = off;
+    A.assign(off, 0.0);
+    C.assign(off, 0.0);
+    long double nm = 1.0L / sqrtl(4.0L * PI_L);
+    for (int m = 0; m <= lmax; ++m) {
+      if (m > 0) nm *= -sqrtl((2.0L * m + 1.0L) / (2.0L * m));
+      norm[m] = (double)nm;
+      auto alpha = [&](int l) {
+        return sqrtl((4.0L * l * l - 1.0L) / ((long double)(l - m) * (long double)(l + m)));
+      };
+      const int64_t r = row_off[m];
+      long double c_lm2 = 1.0L, c_lm1 = 1.0L;
+      A[r] = 0.0;
+      C[r] = 1.0;
+      if (m + 1 <= lmax) {
+        A[r + 1] = (double)alpha(m + 1);
+        C[r + 1] = 1.0;
+      }
+      for (int l = m + 2; l <= lmax; ++l) {
+        const long double al = alpha(l), alm1 = alpha(l - 1);
+        const long double cl_ = c_lm2 * al / alm1;
+        A[r + (l - m)] = (double)(al * c_lm1 / cl_);
+        C[r + (l - m)] = (double)cl_;
+        c_lm2 = c_lm1;
+        c_lm1 = cl_;
+      }
+    }
+  }
+
+  DevMem& M = g.mem;
+  if ((rc = M.upload(&g.pairs, pairs))) return rc;
+  if ((rc = M.upload(&g.A, A))) return rc;
+  if ((rc = M.upload(&g.C, C))) return rc;
+  if ((rc = M.upload(&g.row_off, row_off))) return rc;
+  if ((rc = M.upload(&g.norm, norm))) return rc;
+  if ((rc = M.upload(&g.tw, tw))) return rc;
+  if ((rc = M.upload(&g.chirp, chirp))) return rc;
+  if ((rc = M.upload(&g.blue, blue))) return rc;
+  if ((rc = M.upload(&g.tw32, to32(tw)))) return rc;
+  if ((rc = M.upload(&g.chirp32, to32(chirp)))) return rc;
+  if ((rc = M.upload(&g.blue32, to32(blue)))) return rc;
+
+  // ---- ring classes by transform length
+  std::vector<int32_t> qs_small, qs_large, qs_all(g.npairs);
+  int len_small = 4, len_large = 4;
+  for (int q = 0; q < g.npairs; ++q) {
+    qs_all[q] = q;
+    const int L = pairs[q].log2n >= 0 ? pairs[q].nphi : pairs[q].bl_M;
+    if (L <= SMALL_FFT) {
+      qs_small.push_back(q);
+      len_small = std::max(len_small, L);
+    } else {
+      qs_large.push_back(q);
+      len_large = std::max(len_large, L);
+    }
+  }
+  int32_t *d_small = nullptr, *d_large = nullptr, *d_all = nullptr;
+  if ((rc = M.upload(&d_small, qs_small))) return rc;
+  if ((rc = M.upload(&d_large, qs_large))) return rc;
+  if ((rc = M.upload(&d_all, qs_all))) return rc;
+  g.ring_small = RingClass{d_small, (int32_t)qs_small.size(), len_small};
+  g.ring_large = RingClass{d_large, (int32_t)qs_large.size(), len_large};
+  g.ring_all = RingClass{d_all, g.npairs, std::max(len_small, len_large)};
+
+  // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range
+  PlanDev D{};
+  D.nside = nside;
+  D.lmax = lmax;
+  D.npairs = g.npairs;
+  D.pairs = g.pairs;
+  D.A = g.A;
+  D.row_off = g.row_off;
+  D.norm_m = g.norm;
+  {
+    uint8_t* d_reach = nullptr;
+    DevMem tmp;
+    if ((rc = tmp.alloc(&d_reach, (size_t)(lmax + 1) * g.npairs))) return rc;
+    MWF_HIP(launch_reach(D, d_reach, nullptr));
+    std::vector<uint8_t> reach((size_t)(lmax + 1) * g.npairs);
+    MWF_HIP(hipMemcpy(reach.data(), d_reach, reach.size(), hipMemcpyDeviceToHost));
+    g.n_active.assign(lmax + 1, 0);
+    g.units_active = 0;
+    for (int m = 0; m <= lmax; ++m) {
+      int na = 0;
+      for (int q = 0; q < g.npairs; ++q)
+        if (reach[(size_t)m * g.npairs + q]) na = q + 1;
+      g.n_active[m] = na;
+      g.units_active += (int64_t)na * (lmax - m + 1);
+    }
+  }
+  auto make_items = [&](int rb) {
+    std::vector<WorkItem> items;
+    for (int m = 0; m <= lmax; ++m) {
+      const int nb = (g.n_active[m] + rb - 1) / rb;
+      for (int b = 0; b < nb; ++b) items.push_back({m, b});
+    }
+    std::stable_sort(items.begin(), items.end(), [&](const WorkItem& a, const WorkItem& b) {
+      auto c = [&](const WorkItem& w) {
+        const int rings = std::min(rb, g.n_active[w.m] - w.blk * rb);
+        return (double)(lmax - w.m + 1) * (double)std::max(rings, 1);
+      };
+      return c(a) > c(b);
+    });
+    if (items.empty()) items.push_back({0, 0});
+    return items;
+  };
+  g.ring_block_ana = ana_ring_block(g.npairs);
+  g.ring_block_syn = ana_ring_block(g.npairs);
+  g.nblk_max_ana = (g.npairs + g.ring_block_ana - 1) / g.ring_block_ana;
+  std::vector<int32_t> nblk(lmax + 1);
+  for (int m = 0; m <= lmax; ++m) nblk[m] = (g.n_active[m] + g.ring_block_ana - 1) / g.ring_block_ana;
+  const auto ia = make_items(g.ring_block_ana), is = make_items(g.ring_block_syn);
+  const auto i128 = make_items(128), i256 = make_items(256), i64 = make_items(64);
+  g.n_ana = (int)ia.size();
+  g.n_syn = (int)is.size();
+  g.n_a128 = (int)i128.size();
+  g.n_a256 = (int)i256.size();
+  g.n_s64 = (int)i64.size();
+  if ((rc = M.upload(&g.nact, g.n_active))) return rc;
+  if ((rc = M.upload(&g.nblk_ana, nblk))) return rc;
+  if ((rc = M.upload(&g.items_ana, ia))) return rc;
+  if ((rc = M.upload(&g.items_syn, is))) return rc;
+  if ((rc = M.upload(&g.items_a128, i128))) return rc;
+  if ((rc = M.upload(&g.items_a256, i256))) return rc;
+  if ((rc = M.upload(&g.items_s64, i64))) return rc;
+  return WF_OK;
+}
+
+}  // namespace
+
+RingGeo ring_geometry(int n, int i) {
+  RingGeo g{};
+  const int64_t npix = 12LL * n * n;
+  if (i < n) {
+    g.z = 1.0 - (double)((int64_t)i * i) / (3.0 * n * n);
+    g.nphi = 4 * i;
+    g.ph_num = 1;
+    g.ph_den = 4 * i;
+    g.start = 2LL * i * (i - 1);
+  } else if (i <= 3 * n) {
+    g.z = 2.0 * (2 * n - i) / (3.0 * n);
+    g.nphi = 4 * n;
+    g.ph_num = (i - n + 1) % 2;
+    g.ph_den = 4 * n;
+    g.start = 2LL * n * (n - 1) + 4LL * n * (i - n);
+  } else {
+    const int ip = 4 * n - i;
+    g.z = -(1.0 - (double)((int64_t)ip * ip) / (3.0 * n * n));
+    g.nphi = 4 * ip;
+    g.ph_num = 1;
+    g.ph_den = 4 * ip;
+    g.start = npix - 2LL * ip * (ip + 1);
+  }
+  return g;
+}
+
+int get_geometry(int nside, int lmax, std::shared_ptr<Geometry>* out) {
+  int dev = 0;
+  MWF_HIP(hipGetDevice(&dev));
+  const auto key = std::make_tuple(dev, nside, lmax);
+  std::lock_guard<std::mutex> lock(g_geo_mu);
+  auto it = g_geo.find(key);
+  if (it != g_geo.end()) {
+    *out = it->second;
+    return WF_OK;
+  }
+  auto g = std::make_shared<Geometry>();
+  g->device = dev;
+  g->nside = nside;
+  g->lmax = lmax;
+  const int rc = build_geometry(*g);
+  if (rc) return rc;
+  g_geo[key] = g;
+  *out = g;
+  return WF_OK;
+}
+
+}  // namespace mwf

@@ -157,6 +157,8 @@ struct MfmaArgs {
   int32_t mode;             // SynthMode of the coefficient step
   int32_t nmaps;
   double lambda;
+  int32_t ana_rb;           // ring pairs per analysis block (128 or 256): partial blocks per m
+  int32_t pad_;
   const float* G;           // [map][pair][m][4]
   float* F;                 // [map][pair][m][4]
   float* partial;           // [blk of 256 pairs][nalm][nmaps][2]
@@ -165,11 +167,50 @@ struct MfmaArgs {
   float2* alm_out;          // [map][nalm] or null
 };
 
-hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+// ct: column tiles (16 columns) per analysis workgroup, 1 or 2 (ring block 128 ct);
+// nct: column tiles per synthesis wave, 1, 2 or 4.
+hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nitems, int mode, int ct,
                                 const MfmaArgs& a, hipStream_t s);
 hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s);
-hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode, int nct,
                                  const MfmaArgs& a, hipStream_t s);
+
+// One entry of a task group: a plan's tables and buffers, its maps and its lambda for
+// this step. Groups run every task of a step in one launch per phase.
+struct TaskDev {
+  PlanDev P;
+  int32_t nmaps;
+  int32_t pb_mode;          // PhaseBMode bits
+  int32_t sy_mode;          // SynthMode
+  int32_t pad_;
+  double lambda;
+  void* G;
+  void* F;
+  const void* d;
+  const void* map_in;
+  void* map_out;
+  float* partial;
+  float* bcoef;
+  const float2* alm_in;
+  float2* alm_out;
+  const WorkItem* items_a128;   // analysis items for 128- and 256-pair blocks
+  const WorkItem* items_a256;
+  const WorkItem* items_s64;    // synthesis items (64 pairs)
+};
+
+struct GroupLaunch {
+  const TaskDev* tasks;     // device
+  const int64_t* offs;      // device, ntasks + 1 block offsets
+  int32_t ntasks;
+  int32_t pad_;
+  int64_t nblocks;
+};
+
+hipError_t launch_group_analysis(const GroupLaunch& g, int mode, int ct, hipStream_t s);
+hipError_t launch_group_coeff(const GroupLaunch& g, int ana_rb, hipStream_t s);
+hipError_t launch_group_synthesis(const GroupLaunch& g, int mode, int nct, int ana_rb, hipStream_t s);
+// Ring phase over (task, ring pair, map) blocks, float storage and arithmetic.
+hipError_t launch_group_phase_b(const GroupLaunch& g, size_t lds_bytes, hipStream_t s);
 
 // Plan-time: which ring pairs ever reach a non-negligible lambda_lm (polar skip).
 hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s);

@@ -137,20 +137,20 @@ struct Products<3> {
 };
 
 // ------------------------------------------------------------------ analysis
-// Work item (m, block of 256 ring pairs); blockIdx.y = column group of 32
-// columns (16 maps). Wave w owns the output tile (parity w & 1, column tile w >> 1).
+// Work item (m, block of RB = 128 CT ring pairs) and column group cg of 16 CT
+// columns (8 CT maps); 2 CT waves, one ring pair per thread for the recurrence.
+// Wave w owns the output tile (parity w & 1, column tile w >> 1).
 // NP = 1: FP32 matrix cores; NP = 2 or 3: bf16 pieces.
-template <int NP>
-__global__ void __launch_bounds__(256) mfma_analysis_kernel(PlanDev P, const WorkItem* __restrict__ items,
-                                                            MfmaArgs a) {
-  constexpr int RB = 256;
+template <int NP, int CT>
+__device__ __forceinline__ void analysis_body(const PlanDev& P, const MfmaArgs& a, const WorkItem it,
+                                              const int cg) {
+  constexpr int RB = 128 * CT;
   constexpr bool F32 = (NP == 1);
   constexpr int NB = F32 ? 1 : NP;
   // staged Legendre values [parity][row][ring]; FP32 or bf16 pieces (rows 16 B aligned)
   __shared__ float lam_f[F32 ? 2 : 1][16][RB + 4];
   __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][16][RB + 8];
-  const WorkItem it = items[blockIdx.x];
-  const int m = it.m, blk = it.blk, cg = blockIdx.y;
+  const int m = it.m, blk = it.blk;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lmax = P.lmax;
   const int nact = P.n_active[m];
@@ -162,23 +162,25 @@ __global__ void __launch_bounds__(256) mfma_analysis_kernel(PlanDev P, const Wor
   Ring ring = ring_init(P, m, q0 + tid, nact);
 
   const int par = wave & 1, ct = wave >> 1;
-  const int col = cg * 32 + ct * 16 + (lane & 15);
+  const int col = cg * (16 * CT) + ct * 16 + (lane & 15);
   const int map = col >> 1, comp = col & 1;
   const bool colok = map < a.nmaps;
   const float* Gc = G + (size_t)map * P.npairs * pstride + (size_t)m * 4 + 2 * par + comp;
 
   // B fragments: the S (even) or D (odd) column of this wave for all 256 ring pairs
-  float bf[F32 ? 64 : 1];
-  bf8 bb[NB][F32 ? 1 : 8];
+  constexpr int KF = RB / 4;    // FP32 k-steps (K = 4)
+  constexpr int KB = RB / 32;   // bf16 k-steps (K = 32)
+  float bf[F32 ? KF : 1];
+  bf8 bb[NB][F32 ? 1 : KB];
   if constexpr (F32) {
 #pragma unroll
-    for (int t = 0; t < 64; ++t) {
+    for (int t = 0; t < KF; ++t) {
       const int q = q0 + 4 * t + (lane >> 4);
       bf[t] = (colok && q < nact) ? Gc[(size_t)q * pstride] : 0.0f;
     }
   } else {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
+    for (int t = 0; t < KB; ++t) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int q = q0 + 32 * t + 8 * (lane >> 4) + e;
@@ -192,6 +194,8 @@ __global__ void __launch_bounds__(256) mfma_analysis_kernel(PlanDev P, const Wor
   }
 
   float* out = a.partial + (size_t)blk * P.nalm * 2 * a.nmaps;
+  (void)KF;
+  (void)KB;
   const int64_t row = alm_index(lmax, m, m);
 
   for (int l0 = m; l0 <= lmax; l0 += MCH) {
@@ -210,13 +214,13 @@ __global__ void __launch_bounds__(256) mfma_analysis_kernel(PlanDev P, const Wor
     f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
     if constexpr (F32) {
 #pragma unroll
-      for (int t = 0; t < 64; ++t) {
+      for (int t = 0; t < KF; ++t) {
         const float av = lam_f[par][lane & 15][4 * t + (lane >> 4)];
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bf[t], acc, 0, 0, 0);
       }
     } else {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < KB; ++t) {
         bf8 av[NB];
 #pragma unroll
         for (int i = 0; i < NB; ++i)
@@ -240,13 +244,13 @@ __global__ void __launch_bounds__(256) mfma_analysis_kernel(PlanDev P, const Wor
 }
 
 // ------------------------------------------------------------------ synthesis
-// Work item (m, block of 64 ring pairs), one wave; blockIdx.y = column group.
+// Work item (m, block of 64 ring pairs) and column group cg of 16 NCT columns, one wave.
 // The wave's own Legendre values are staged through its LDS: FP32 in chunks of
 // 32 l (16 per parity, K = 4 per product), bf16 pieces in chunks of 64 l
 // (32 per parity, K = 32 per product).
-template <int NP>
-__global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const WorkItem* __restrict__ items,
-                                                            MfmaArgs a) {
+template <int NP, int NCT>
+__device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs& a, const WorkItem it,
+                                               const int cg) {
   constexpr bool F32 = (NP == 1);
   constexpr int NB = F32 ? 1 : NP;
   constexpr int CHL = F32 ? MCH : 2 * MCH;       // l per chunk
@@ -254,9 +258,9 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
   // FP32: [parity][row][ring]; bf16 pieces: [piece][parity][ring][row] (row = k contiguous)
   __shared__ float lam_f[F32 ? 2 : 1][16][64 + 4];
   __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][64][ROWS + 8];
-  const WorkItem it = items[blockIdx.x];
-  const int m = it.m, blk = it.blk, cg = blockIdx.y;
+  const int m = it.m, blk = it.blk;
   const int lane = threadIdx.x;
+  constexpr int CW = 16 * NCT;   // columns of this wave
   const int lmax = P.lmax;
   const int nact = P.n_active[m];
   const int q0 = blk * 64;
@@ -266,11 +270,11 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
   const float* __restrict__ brow = a.bcoef + (size_t)roff * ncols;
 
   Ring ring = ring_init(P, m, q0 + lane, nact);
-  f4 acc[4][2][2];   // [ring tile][column tile][E / O]
+  f4 acc[4][NCT][2];   // [ring tile][column tile][E / O]
 #pragma unroll
   for (int qt = 0; qt < 4; ++qt)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct)
+    for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
       for (int eo = 0; eo < 2; ++eo) acc[qt][ct][eo] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
@@ -278,15 +282,15 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
     const double* Ac = Arow + (l0 - m);
     if constexpr (F32) {
       // B fragments of the whole chunk first: their latency hides behind the recurrence
-      float bv[2][4][2];
+      float bv[2][4][NCT];
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
+          for (int ct = 0; ct < NCT; ++ct) {
             const int rr = 4 * kk + (lane >> 4);
-            const int colg = cg * 32 + ct * 16 + (lane & 15);
+            const int colg = cg * CW + ct * 16 + (lane & 15);
             bv[pp][kk][ct] = colg < ncols ? brow[(size_t)(l0 - m + 2 * rr + pp) * ncols + colg] : 0.0f;
           }
       ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][lane] = (float)v; });
@@ -300,7 +304,7 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
           for (int qt = 0; qt < 4; ++qt) {
             const float av = lam_f[pp][rr][qt * 16 + (lane & 15)];
 #pragma unroll
-            for (int ct = 0; ct < 2; ++ct)
+            for (int ct = 0; ct < NCT; ++ct)
               acc[qt][ct][pp] =
                   __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[pp][kk][ct], acc[qt][ct][pp], 0, 0, 0);
           }
@@ -308,12 +312,12 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
     } else {
       // B fragments straight from global: lane holds rows k8..k8+7 of one column
       const int k8 = 8 * (lane >> 4);
-      float bvf[2][2][8];
+      float bvf[2][NCT][8];
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp)
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct) {
-          const int colg = cg * 32 + ct * 16 + (lane & 15);
+        for (int ct = 0; ct < NCT; ++ct) {
+          const int colg = cg * CW + ct * 16 + (lane & 15);
 #pragma unroll
           for (int e = 0; e < 8; ++e)
             bvf[pp][ct][e] = colg < ncols ? brow[(size_t)(l0 - m + 2 * (k8 + e) + pp) * ncols + colg] : 0.0f;
@@ -330,9 +334,9 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
       __syncthreads();
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp) {
-        bf8 bv[NB][2];
+        bf8 bv[NB][NCT];
 #pragma unroll
-        for (int ct = 0; ct < 2; ++ct)
+        for (int ct = 0; ct < NCT; ++ct)
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
             __bf16 pc[NB];
@@ -347,7 +351,7 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
           for (int i = 0; i < NB; ++i)
             av[i] = *reinterpret_cast<const bf8*>(&lam_b[i][pp][qt * 16 + (lane & 15)][k8]);
 #pragma unroll
-          for (int ct = 0; ct < 2; ++ct) {
+          for (int ct = 0; ct < NCT; ++ct) {
             f4 c = acc[qt][ct][pp];
 #pragma unroll
             for (int k = 0; k < Products<NB>::n; ++k)
@@ -365,8 +369,8 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
 #pragma unroll
   for (int qt = 0; qt < 4; ++qt)
 #pragma unroll
-    for (int ct = 0; ct < 2; ++ct) {
-      const int colg = cg * 32 + ct * 16 + (lane & 15);
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int colg = cg * CW + ct * 16 + (lane & 15);
       const int map = colg >> 1, comp = colg & 1;
       if (map >= a.nmaps) continue;
 #pragma unroll
@@ -383,15 +387,14 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
 // ------------------------------------------------------------------ coefficients
 // Sum the analysis blocks (FP64), scale by C_l, apply the filter, emit the alm and
 // the synthesis coefficients b = C_l s_lm in the layout [padded row][map][re/im].
-__global__ void mfma_coeff_kernel(PlanDev P, MfmaArgs a) {
-  const int m = blockIdx.x;
+__device__ __forceinline__ void coeff_body(const PlanDev& P, const MfmaArgs& a, const int m) {
   const int lmax = P.lmax;
   const int nl = lmax - m + 1;
   const int64_t row = alm_index(lmax, m, m);
   const int64_t roff = P.row_off[m];
   const double* __restrict__ Crow = P.C + roff;
   const double lam_t_o = a.lambda * P.tau * P.omega;
-  const int nb = (P.n_active[m] + 255) / 256;
+  const int nb = (P.n_active[m] + a.ana_rb - 1) / a.ana_rb;
   const int nm = a.nmaps;
   for (int e = threadIdx.x; e < (nl + ROW_PAD) * nm; e += blockDim.x) {
     const int i = e / nm, map = e - i * nm;
@@ -430,18 +433,132 @@ __global__ void mfma_coeff_kernel(PlanDev P, MfmaArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ kernels
+template <int NP, int CT>
+__global__ void __launch_bounds__(128 * CT) mfma_analysis_kernel(PlanDev P, const WorkItem* __restrict__ items,
+                                                                 MfmaArgs a) {
+  analysis_body<NP, CT>(P, a, items[blockIdx.x], blockIdx.y);
+}
+
+template <int NP, int NCT>
+__global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const WorkItem* __restrict__ items,
+                                                            MfmaArgs a) {
+  synthesis_body<NP, NCT>(P, a, items[blockIdx.x], blockIdx.y);
+}
+
+__global__ void mfma_coeff_kernel(PlanDev P, MfmaArgs a) { coeff_body(P, a, blockIdx.x); }
+
+// Task groups: block b belongs to the task t with offs[t] <= b < offs[t + 1].
+__device__ __forceinline__ int find_task(const int64_t* __restrict__ offs, int ntasks, int64_t b) {
+  int lo = 0, hi = ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ MfmaArgs task_args(const TaskDev& t, int ana_rb) {
+  MfmaArgs a{};
+  a.mode = t.sy_mode;
+  a.nmaps = t.nmaps;
+  a.lambda = t.lambda;
+  a.ana_rb = ana_rb;
+  a.G = static_cast<const float*>(t.G);
+  a.F = static_cast<float*>(t.F);
+  a.partial = t.partial;
+  a.bcoef = t.bcoef;
+  a.alm_in = t.alm_in;
+  a.alm_out = t.alm_out;
+  return a;
+}
+
+template <int NP, int CT>
+__global__ void __launch_bounds__(128 * CT) group_analysis_kernel(const TaskDev* __restrict__ tasks,
+                                                                  const int64_t* __restrict__ offs, int ntasks) {
+  const int t = find_task(offs, ntasks, blockIdx.x);
+  const TaskDev& T = tasks[t];
+  const int64_t local = blockIdx.x - offs[t];
+  const int ncg = (2 * T.nmaps + 16 * CT - 1) / (16 * CT);
+  const WorkItem* items = CT == 1 ? T.items_a128 : T.items_a256;
+  analysis_body<NP, CT>(T.P, task_args(T, 128 * CT), items[local / ncg], (int)(local % ncg));
+}
+
+template <int NP, int NCT>
+__global__ void __launch_bounds__(64) group_synthesis_kernel(const TaskDev* __restrict__ tasks,
+                                                             const int64_t* __restrict__ offs, int ntasks,
+                                                             int ana_rb) {
+  const int t = find_task(offs, ntasks, blockIdx.x);
+  const TaskDev& T = tasks[t];
+  const int64_t local = blockIdx.x - offs[t];
+  const int ncg = (2 * T.nmaps + 16 * NCT - 1) / (16 * NCT);
+  synthesis_body<NP, NCT>(T.P, task_args(T, ana_rb), T.items_s64[local / ncg], (int)(local % ncg));
+}
+
+__global__ void group_coeff_kernel(const TaskDev* __restrict__ tasks, const int64_t* __restrict__ offs,
+                                   int ntasks, int ana_rb) {
+  const int t = find_task(offs, ntasks, blockIdx.x);
+  const TaskDev& T = tasks[t];
+  coeff_body(T.P, task_args(T, ana_rb), (int)(blockIdx.x - offs[t]));
+}
+
+template <int NP>
+hipError_t ana_np(const PlanDev& P, const WorkItem* items, int nitems, int ct, const MfmaArgs& a,
+                  hipStream_t s) {
+  if (ct == 1) {
+    hipLaunchKernelGGL((mfma_analysis_kernel<NP, 1>), dim3(nitems, (2 * a.nmaps + 15) / 16), dim3(128), 0, s,
+                       P, items, a);
+  } else {
+    hipLaunchKernelGGL((mfma_analysis_kernel<NP, 2>), dim3(nitems, (2 * a.nmaps + 31) / 32), dim3(256), 0, s,
+                       P, items, a);
+  }
+  return hipGetLastError();
+}
+
+template <int NP>
+hipError_t syn_np(const PlanDev& P, const WorkItem* items, int nitems, int nct, const MfmaArgs& a,
+                  hipStream_t s) {
+  const int cw = 16 * nct;
+  const dim3 grid(nitems, (2 * a.nmaps + cw - 1) / cw);
+  if (nct == 1)
+    hipLaunchKernelGGL((mfma_synthesis_kernel<NP, 1>), grid, dim3(64), 0, s, P, items, a);
+  else if (nct == 2)
+    hipLaunchKernelGGL((mfma_synthesis_kernel<NP, 2>), grid, dim3(64), 0, s, P, items, a);
+  else
+    hipLaunchKernelGGL((mfma_synthesis_kernel<NP, 4>), grid, dim3(64), 0, s, P, items, a);
+  return hipGetLastError();
+}
+
+template <int NP>
+hipError_t gana_np(const GroupLaunch& g, int ct, hipStream_t s) {
+  if (ct == 1)
+    hipLaunchKernelGGL((group_analysis_kernel<NP, 1>), dim3(g.nblocks), dim3(128), 0, s, g.tasks, g.offs, g.ntasks);
+  else
+    hipLaunchKernelGGL((group_analysis_kernel<NP, 2>), dim3(g.nblocks), dim3(256), 0, s, g.tasks, g.offs, g.ntasks);
+  return hipGetLastError();
+}
+
+template <int NP>
+hipError_t gsyn_np(const GroupLaunch& g, int nct, int ana_rb, hipStream_t s) {
+  if (nct == 1)
+    hipLaunchKernelGGL((group_synthesis_kernel<NP, 1>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
+                       ana_rb);
+  else if (nct == 2)
+    hipLaunchKernelGGL((group_synthesis_kernel<NP, 2>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
+                       ana_rb);
+  else
+    hipLaunchKernelGGL((group_synthesis_kernel<NP, 4>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
+                       ana_rb);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nitems, int mode, int ct,
                                 const MfmaArgs& a, hipStream_t s) {
-  const dim3 grid(nitems, (2 * a.nmaps + 31) / 32);
-  if (mode == WF_BF16X3)
-    hipLaunchKernelGGL(mfma_analysis_kernel<2>, grid, dim3(256), 0, s, P, items, a);
-  else if (mode == WF_BF16X6)
-    hipLaunchKernelGGL(mfma_analysis_kernel<3>, grid, dim3(256), 0, s, P, items, a);
-  else
-    hipLaunchKernelGGL(mfma_analysis_kernel<1>, grid, dim3(256), 0, s, P, items, a);
-  return hipGetLastError();
+  if (mode == WF_BF16X3) return ana_np<2>(P, items, nitems, ct, a, s);
+  if (mode == WF_BF16X6) return ana_np<3>(P, items, nitems, ct, a, s);
+  return ana_np<1>(P, items, nitems, ct, a, s);
 }
 
 hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s) {
@@ -449,16 +566,31 @@ hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode,
+hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode, int nct,
                                  const MfmaArgs& a, hipStream_t s) {
-  const dim3 grid(nitems, (2 * a.nmaps + 31) / 32);
-  if (mode == WF_BF16X3)
-    hipLaunchKernelGGL(mfma_synthesis_kernel<2>, grid, dim3(64), 0, s, P, items, a);
-  else if (mode == WF_BF16X6)
-    hipLaunchKernelGGL(mfma_synthesis_kernel<3>, grid, dim3(64), 0, s, P, items, a);
-  else
-    hipLaunchKernelGGL(mfma_synthesis_kernel<1>, grid, dim3(64), 0, s, P, items, a);
+  if (mode == WF_BF16X3) return syn_np<2>(P, items, nitems, nct, a, s);
+  if (mode == WF_BF16X6) return syn_np<3>(P, items, nitems, nct, a, s);
+  return syn_np<1>(P, items, nitems, nct, a, s);
+}
+
+hipError_t launch_group_analysis(const GroupLaunch& g, int mode, int ct, hipStream_t s) {
+  if (g.nblocks == 0) return hipSuccess;
+  if (mode == WF_BF16X3) return gana_np<2>(g, ct, s);
+  if (mode == WF_BF16X6) return gana_np<3>(g, ct, s);
+  return gana_np<1>(g, ct, s);
+}
+
+hipError_t launch_group_coeff(const GroupLaunch& g, int ana_rb, hipStream_t s) {
+  if (g.nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(group_coeff_kernel, dim3(g.nblocks), dim3(256), 0, s, g.tasks, g.offs, g.ntasks, ana_rb);
   return hipGetLastError();
+}
+
+hipError_t launch_group_synthesis(const GroupLaunch& g, int mode, int nct, int ana_rb, hipStream_t s) {
+  if (g.nblocks == 0) return hipSuccess;
+  if (mode == WF_BF16X3) return gsyn_np<2>(g, nct, ana_rb, s);
+  if (mode == WF_BF16X6) return gsyn_np<3>(g, nct, ana_rb, s);
+  return gsyn_np<1>(g, nct, ana_rb, s);
 }
 
 }  // namespace mwf

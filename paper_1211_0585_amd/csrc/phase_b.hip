@@ -255,14 +255,12 @@ struct Vec4<float> {
 };
 
 template <class T, class C, int NT>
-__global__ void __launch_bounds__(NT, 4) phase_b_kernel(PlanDev P, PhaseBArgs a,
-                                                                       const int32_t* __restrict__ qlist) {
+__device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs& a, const int q,
+                                             const int map) {
   using V4 = typename Vec4<T>::type;
   using V = typename CT<C>::V;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   V* buf = reinterpret_cast<V*>(lds_raw);
-  const int q = qlist[blockIdx.x];
-  const int map = blockIdx.y;
   const RingPair rp = P.pairs[q];
   const int n = rp.nphi;
   const int lmax = P.lmax;
@@ -383,6 +381,36 @@ __global__ void __launch_bounds__(NT, 4) phase_b_kernel(PlanDev P, PhaseBArgs a,
 }
 
 template <class T, class C, int NT>
+__global__ void __launch_bounds__(NT, 4) phase_b_kernel(PlanDev P, PhaseBArgs a,
+                                                        const int32_t* __restrict__ qlist) {
+  phase_b_body<T, C, NT>(P, a, qlist[blockIdx.x], blockIdx.y);
+}
+
+// Task groups (float storage and arithmetic): block b of task t covers ring pair
+// (b - offs[t]) / nmaps and map (b - offs[t]) % nmaps.
+__global__ void __launch_bounds__(512, 4) group_phase_b_kernel(const TaskDev* __restrict__ tasks,
+                                                               const int64_t* __restrict__ offs, int ntasks) {
+  int lo = 0, hi = ntasks - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const TaskDev& t = tasks[lo];
+  const int64_t local = b - offs[lo];
+  PhaseBArgs a{};
+  a.mode = t.pb_mode;
+  a.nmaps = t.nmaps;
+  a.lambda = t.lambda;
+  a.F = t.F;
+  a.G = t.G;
+  a.d = t.d;
+  a.map_in = t.map_in;
+  a.map_out = t.map_out;
+  phase_b_body<float, float, 512>(t.P, a, (int)(local / t.nmaps), (int)(local % t.nmaps));
+}
+
+template <class T, class C, int NT>
 hipError_t launch_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
   if (rc.count == 0) return hipSuccess;
   static size_t attr_bytes = 0;
@@ -406,6 +434,19 @@ hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, const RingClass& smal
 }
 
 }  // namespace
+
+hipError_t launch_group_phase_b(const GroupLaunch& g, size_t lds_bytes, hipStream_t s) {
+  if (g.nblocks == 0) return hipSuccess;
+  static size_t attr_bytes = 0;
+  if (lds_bytes > attr_bytes) {
+    hipError_t e = hipFuncSetAttribute((const void*)group_phase_b_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+    if (e != hipSuccess) return e;
+    attr_bytes = lds_bytes;
+  }
+  hipLaunchKernelGGL(group_phase_b_kernel, dim3(g.nblocks), dim3(512), lds_bytes, s, g.tasks, g.offs, g.ntasks);
+  return hipGetLastError();
+}
 
 hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,
                           const RingClass& large, bool fp32, hipStream_t s) {

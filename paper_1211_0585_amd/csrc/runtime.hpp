@@ -1,0 +1,142 @@
+// Host runtime structures of libmwf: cached geometry, plans, task groups.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mwf_internal.hpp"
+
+namespace mwf {
+
+// Device allocations owned by one object, released with it.
+struct DevMem {
+  std::vector<void*> ptrs;
+  DevMem() = default;
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  ~DevMem() {
+    for (void* p : ptrs) hipFree(p);
+  }
+  template <class T>
+  int alloc(T** out, size_t count) {
+    void* v = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&v, count * sizeof(T));
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? WF_ENOMEM : WF_EDEVICE,
+                  std::string("hipMalloc: ") + hipGetErrorString(e));
+    ptrs.push_back(v);
+    *out = static_cast<T*>(v);
+    return WF_OK;
+  }
+  // Synchronous upload (the host vector may be released right after).
+  template <class T>
+  int upload(T** out, const std::vector<T>& host) {
+    int rc = alloc(out, host.size());
+    if (rc) return rc;
+    MWF_HIP(hipMemcpy(*out, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice));
+    return WF_OK;
+  }
+};
+
+// Everything that depends only on (device, nside, lmax): ring geometry, Legendre
+// recurrence tables, FFT tables, polar-skip work lists. Shared by every plan of
+// that shape through a process-wide cache.
+struct Geometry {
+  int device = 0, nside = 0, lmax = 0;
+  int64_t npix = 0, nalm = 0;
+  int npairs = 0, nrings = 0;
+  double omega = 0.0;
+  int tw_len = 4;
+  int64_t rows_total = 0;
+  int64_t units_active = 0;
+  std::vector<int32_t> n_active;       // per m
+  // FP64 VALU path
+  int ring_block_ana = 64, ring_block_syn = 64, nblk_max_ana = 1;
+  // device tables
+  RingPair* pairs = nullptr;
+  double* A = nullptr;
+  double* C = nullptr;
+  int64_t* row_off = nullptr;
+  double* norm = nullptr;
+  int32_t* nact = nullptr;
+  int32_t* nblk_ana = nullptr;
+  double2* tw = nullptr;
+  double2* chirp = nullptr;
+  double2* blue = nullptr;
+  float2* tw32 = nullptr;
+  float2* chirp32 = nullptr;
+  float2* blue32 = nullptr;
+  // work lists, longest first
+  WorkItem* items_ana = nullptr;       // FP64 analysis (ring_block_ana)
+  WorkItem* items_syn = nullptr;       // FP64 synthesis (ring_block_syn)
+  WorkItem* items_a128 = nullptr;      // matrix-core analysis, 128 / 256 ring pairs
+  WorkItem* items_a256 = nullptr;
+  WorkItem* items_s64 = nullptr;       // matrix-core synthesis, 64 ring pairs
+  int n_ana = 0, n_syn = 0, n_a128 = 0, n_a256 = 0, n_s64 = 0;
+  RingClass ring_small{}, ring_large{}, ring_all{};
+  DevMem mem;
+};
+
+int get_geometry(int nside, int lmax, std::shared_ptr<Geometry>* out);
+
+// One HEALPix ring (RING order, 1 <= i <= 4 nside - 1): z = cos(theta), first
+// pixel index, pixel count and the longitude of its first pixel, pi ph_num / ph_den.
+struct RingGeo {
+  double z;
+  int64_t start;
+  int32_t nphi, ph_num, ph_den;
+};
+RingGeo ring_geometry(int n, int i);
+
+// Launch-shape choices of the matrix-core kernels (see the autotuner).
+struct Tuning {
+  int ana_ct = 2;    // column tiles per analysis workgroup (ring block 128 ct)
+  int syn_nct = 2;   // column tiles per synthesis wave
+};
+
+bool lookup_tuning(const std::string& key, Tuning* t);
+void store_tuning(const std::string& key, const Tuning& t, const char* cache_path);
+void load_tuning_file(const char* cache_path);
+
+}  // namespace mwf
+
+struct wf_plan_s {
+  std::shared_ptr<mwf::Geometry> geo;
+  int dtype = WF_F64, max_batch = 1, flags = 0;
+  double tau = 0.0;
+  hipStream_t stream = nullptr;        // plan-time uploads
+  hipStream_t last_stream = nullptr;   // stream of the last enqueued call
+  std::string tune_cache;
+  mwf::Tuning tune;
+  bool tuned = false;
+  void* q = nullptr;                   // tau * ninv in the storage type
+  double* cl = nullptr;
+  void* G = nullptr;                   // [batch][pair][m][4]
+  void* F = nullptr;
+  size_t elem = 8;
+  double2* partial = nullptr;          // FP64: [batch][blk][nalm]
+  double2* bcoef = nullptr;            // FP64: [batch][rows_total]
+  float* partial32 = nullptr;          // matrix cores: [blk128][nalm][batch][2]
+  float* bcoef32 = nullptr;            // matrix cores: [rows_total][batch][2]
+  mwf::PlanDev dev{};
+  mwf::DevMem mem;
+};
+
+struct wf_group_s {
+  std::vector<wf_plan_t> plans;
+  std::vector<int32_t> nmaps;
+  int dtype = WF_F32;
+  mwf::Tuning tune;
+  size_t lds_phase_b = 0;
+  // per solve: one TaskDev array per step (sweeps + final synthesis)
+  mwf::TaskDev* d_tasks = nullptr;
+  size_t d_tasks_cap = 0;
+  int64_t* d_offs = nullptr;           // [4 phases][ntasks + 1]
+  int64_t nblocks[4] = {0, 0, 0, 0};
+  std::unique_ptr<mwf::DevMem> mem;
+};

@@ -30,6 +30,14 @@ _SIGS = [
     ("wf_plan_info", _c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
                                 _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64)]),
     ("wf_pixel_angles", _c.c_int, [_c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("wf_autotune", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.POINTER(_c.c_int32),
+                               _c.POINTER(_c.c_int32)]),
+    ("wf_group_create", _c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("wf_group_solve", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                  _c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("wf_group_autotune", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                     _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
+    ("wf_group_destroy", None, [_c.c_void_p]),
     ("wf_sync", _c.c_int, [_c.c_void_p]),
     ("wf_destroy", None, [_c.c_void_p]),
     ("wf_strerror", _c.c_char_p, [_c.c_int]),
@@ -122,7 +130,7 @@ class Plan:
     """A planned (nside, lmax, C_l, N^-1, mask) problem; owns device tables and buffers."""
 
     def __init__(self, nside, lmax, cl, ninv, mask=None, dtype=WF_F64, max_batch=1, stream=None,
-                 flags=0):
+                 flags=0, tune_cache=None):
         L = lib()
         cl = np.ascontiguousarray(cl, dtype=np.float64)
         ninv = np.ascontiguousarray(ninv, dtype=np.float64)
@@ -137,7 +145,8 @@ class Plan:
             if mask.size != npix:
                 raise ValueError("mask must have npix entries")
             mptr = mask.ctypes.data
-        opts = wf_plan_opts(dtype, max_batch, flags, None)
+        opts = wf_plan_opts(dtype, max_batch, flags,
+                            None if tune_cache is None else os.fsencode(tune_cache))
         h = ctypes.c_void_p()
         sh = _stream_handle(stream)
         _check(L.wf_plan(ctypes.byref(h), nside, lmax, cl.ctypes.data, ninv.ctypes.data, mptr,
@@ -205,6 +214,13 @@ class Plan:
                                  _dev_ptr(maps, rt, nmaps * self.npix, "map"), _stream_handle(stream)))
         return maps
 
+    def autotune(self, nmaps=None, stream=None):
+        """Pick the fastest matrix-core launch shape at nmaps maps; returns (ana_ct, syn_nct)."""
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().wf_autotune(self.handle, nmaps or self.max_batch, _stream_handle(stream),
+                                 ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
     def sync(self):
         _check(lib().wf_sync(self.handle))
 
@@ -224,3 +240,74 @@ class Plan:
 
     def __exit__(self, *exc):
         self.close()
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * len(ptrs))()
+    for i, p in enumerate(ptrs):
+        arr[i] = p.value if isinstance(p, ctypes.c_void_p) else p
+    return arr
+
+
+class Group:
+    """Several matrix-core plans stepped together, one launch per phase (wf_group_*).
+
+    plans: list of Plan (same dtype); nmaps: maps per plan. The group borrows the
+    plans, which must stay open while it is used.
+    """
+
+    def __init__(self, plans, nmaps):
+        if len(plans) != len(nmaps) or not plans:
+            raise ValueError("need one nmaps entry per plan")
+        self.plans, self.nmaps = list(plans), [int(n) for n in nmaps]
+        hp = _ptr_array([p.handle for p in self.plans])
+        nm = (ctypes.c_int32 * len(nmaps))(*self.nmaps)
+        h = ctypes.c_void_p()
+        _check(lib().wf_group_create(ctypes.byref(h), len(plans), hp, nm))
+        self._h = h
+        self.last_stats = None
+
+    def _bufs(self, ds, s_wf, s_alm, want_alm):
+        import torch
+        if len(ds) != len(self.plans):
+            raise ValueError("need one data tensor per plan")
+        s_wf = s_wf or [torch.empty_like(d) for d in ds]
+        if s_alm is None and want_alm:
+            s_alm = [torch.empty((n, p.nalm), dtype=torch.complex64, device=d.device)
+                     for p, n, d in zip(self.plans, self.nmaps, ds)]
+        pd, pw, pa = [], [], []
+        for i, (p, n) in enumerate(zip(self.plans, self.nmaps)):
+            pd.append(_dev_ptr(ds[i], torch.float32, n * p.npix, f"d[{i}]"))
+            pw.append(_dev_ptr(s_wf[i], torch.float32, n * p.npix, f"s_wf[{i}]"))
+            if s_alm is not None:
+                pa.append(_dev_ptr(s_alm[i], torch.complex64, n * p.nalm, f"s_alm[{i}]"))
+        return s_wf, s_alm, _ptr_array(pd), _ptr_array(pw), (_ptr_array(pa) if s_alm is not None else None)
+
+    def solve(self, ds, lambdas, s_wf=None, s_alm=None, stream=None, want_alm=True):
+        """ds[i]: float32 [nmaps_i, npix_i] data of plan i. Returns (s_wf list, s_alm list)."""
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        s_wf, s_alm, pd, pw, pa = self._bufs(ds, s_wf, s_alm, want_alm)
+        st = wf_stats()
+        _check(lib().wf_group_solve(self._h, pd, pw, pa, lam.ctypes.data, lam.size, _stream_handle(stream),
+                                    ctypes.byref(st)))
+        self.last_stats = st
+        return s_wf, s_alm
+
+    def autotune(self, ds, stream=None):
+        """Time every launch shape on data ds and keep the fastest; returns (ana_ct, syn_nct)."""
+        _, _, pd, pw, _ = self._bufs(ds, None, None, False)
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().wf_group_autotune(self._h, pd, pw, _stream_handle(stream), ctypes.byref(a),
+                                       ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if self._h is not None:
+            lib().wf_group_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,141 @@
+"""GPU parity of task groups: plans of different nside / lmax stepped together,
+one launch per phase (wf_group_solve), against the same plans solved one by one
+and against the FP64 oracle.
+
+Bars: each group member within 1e-5 relative L2 of the oracle (the reduced-
+precision bar); group and separate solves within 1e-6 of each other (they differ
+only in the ring-phase launch shape, which may regroup FP32 FFT sums).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import messenger
+from tests.helpers import alm_rel_l2, rel_l2, small_band_inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 32, 3), (32, 64, 2), (64, 128, 1), (8, 16, 4)]
+LAMS = np.geomspace(3e3, 1.0, 12)
+
+
+def _log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_1211_0585_amd import mwf
+    mwf.lib()
+    return torch
+
+
+def _cases():
+    out = []
+    for i, (nside, lmax, nm) in enumerate(SHAPES):
+        cs = [small_band_inputs(nside, lmax, seed=10 * i + j) for j in range(nm)]
+        d = np.stack([c["d"] for c in cs]).astype(np.float32)
+        # the maps of one plan share C_l and N^-1 (those of the first draw)
+        out.append(dict(nside=nside, lmax=lmax, nmaps=nm, cl=cs[0]["cl"], ninv=cs[0]["ninv"], d=d))
+    return out
+
+
+@pytest.fixture(scope="module")
+def cases():
+    return _cases()
+
+
+def _plans(mwf, cases, dt):
+    return [mwf.Plan(c["nside"], c["lmax"], c["cl"], c["ninv"], dtype=dt, max_batch=c["nmaps"]) for c in cases]
+
+
+@pytest.mark.parametrize("name,dt", [("f32", 1), ("bf16x6", 3)])
+def test_group_matches_separate_and_oracle(torch_dev, cases, name, dt):
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    plans = _plans(mwf, cases, dt)
+    ds = [torch.from_numpy(c["d"]).cuda() for c in cases]
+    g = mwf.Group(plans, [c["nmaps"] for c in cases])
+    gw, ga = g.solve(ds, LAMS)
+    torch.cuda.synchronize()
+    for i, (c, p) in enumerate(zip(cases, plans)):
+        sw, sa = p.solve(ds[i], LAMS)
+        p.sync()
+        gwi, gai = gw[i].cpu().numpy(), ga[i].cpu().numpy()
+        swi, sai = sw.cpu().numpy(), sa.cpu().numpy()
+        e_sep = rel_l2(gwi, swi)
+        e_sep_alm = max(alm_rel_l2(gai[k], sai[k], c["lmax"]) for k in range(c["nmaps"]))
+        e_or = 0.0
+        for k in range(c["nmaps"]):
+            ref_map, ref_alm = messenger.solve(c["d"][k].astype(np.float64), c["ninv"], c["cl"], LAMS,
+                                               c["nside"], c["lmax"])
+            e_or = max(e_or, rel_l2(gwi[k], ref_map), alm_rel_l2(gai[k], ref_alm, c["lmax"]))
+        _log(f"group {name} Nside {c['nside']} lmax {c['lmax']} x{c['nmaps']}: vs separate "
+             f"{e_sep:.2e}/{e_sep_alm:.2e} (bitwise {np.array_equal(gwi, swi)}), vs oracle {e_or:.2e}")
+        assert e_sep <= 1e-6 and e_sep_alm <= 1e-6
+        assert e_or <= 1e-5
+    g.close()
+    for p in plans:
+        p.close()
+
+
+def test_group_autotune_and_resolve(torch_dev, cases):
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    plans = _plans(mwf, cases, mwf.WF_F32)
+    ds = [torch.from_numpy(c["d"]).cuda() for c in cases]
+    g = mwf.Group(plans, [c["nmaps"] for c in cases])
+    ct, nct = g.autotune(ds)
+    _log(f"group autotune: ana_ct {ct} syn_nct {nct}")
+    assert ct in (1, 2) and nct in (1, 2, 4)
+    w1, a1 = g.solve(ds, LAMS)
+    w2, a2 = g.solve(ds, LAMS)   # a repeated solve reuses the task table
+    torch.cuda.synchronize()
+    for i in range(len(cases)):
+        assert torch.equal(w1[i], w2[i]) and torch.equal(a1[i], a2[i])
+    g.close()
+    for p in plans:
+        p.close()
+
+
+def test_plan_autotune_keeps_results(torch_dev, cases):
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    c = cases[1]
+    d = torch.from_numpy(c["d"]).cuda()
+    with mwf.Plan(c["nside"], c["lmax"], c["cl"], c["ninv"], dtype=mwf.WF_F32, max_batch=c["nmaps"]) as p:
+        w0, a0 = p.solve(d, LAMS)
+        p.sync()
+        w0 = w0.cpu().numpy()
+        ct, nct = p.autotune()
+        assert ct in (1, 2) and nct in (1, 2, 4)
+        w1, a1 = p.solve(d, LAMS)
+        p.sync()
+        e = rel_l2(w1.cpu().numpy(), w0)
+        _log(f"plan autotune ({ct}, {nct}): change vs default shape {e:.2e}")
+        assert e <= 1e-6
+    with mwf.Plan(c["nside"], c["lmax"], c["cl"], c["ninv"], dtype=mwf.WF_F64) as p:
+        assert p.autotune() == (0, 0)
+
+
+def test_group_rejects_bad_input(torch_dev, cases):
+    from paper_1211_0585_amd import mwf
+    c = cases[0]
+    p64 = mwf.Plan(c["nside"], c["lmax"], c["cl"], c["ninv"], dtype=mwf.WF_F64)
+    p32 = mwf.Plan(c["nside"], c["lmax"], c["cl"], c["ninv"], dtype=mwf.WF_F32, max_batch=2)
+    pbf = mwf.Plan(c["nside"], c["lmax"], c["cl"], c["ninv"], dtype=mwf.WF_BF16X6)
+    with pytest.raises(mwf.WFError) as e:
+        mwf.Group([p64], [1])
+    assert e.value.code == mwf.WF_EUNSUPPORTED
+    with pytest.raises(mwf.WFError) as e:
+        mwf.Group([p32, pbf], [1, 1])
+    assert e.value.code == mwf.WF_EINVAL
+    with pytest.raises(mwf.WFError) as e:
+        mwf.Group([p32], [3])
+    assert e.value.code == mwf.WF_EINVAL
+    for p in (p64, p32, pbf):
+        p.close()
