@@ -221,6 +221,74 @@ int wf_group_autotune(wf_group_t group, const void* const* d, void* const* s_wf,
 /* wf_group_destroy -- free a group (not its plans); waits for the device. */
 void wf_group_destroy(wf_group_t group);
 
+/*
+ * Serving. A server owns a non-blocking HIP stream on the device current at
+ * creation, two host threads and device memory up to an HBM budget. Requests
+ * (independent messenger solves, each with its own nside, lmax, C_l, N^-1, mask,
+ * data and lambda schedule) are admitted in arrival order as request slots and
+ * memory free up; requests of the same (nside, lmax, dtype) share a lane, a plan
+ * whose maps are the lane's slots, and every step advances every admitted request
+ * by one sweep with one kernel launch per phase for all lanes. A request therefore
+ * joins the running batch at the next step and its result is the one a plan of
+ * the same dtype computes for it alone (same kernels, column-independent sums).
+ */
+typedef struct wf_server_s* wf_server_t;
+
+typedef struct {
+  int64_t submitted, completed;   /* requests accepted by submit / finished               */
+  int64_t steps;                  /* batched steps launched                               */
+  int64_t map_sweeps;             /* sweeps of finished requests                          */
+  int64_t peak_slots;             /* most requests admitted at once                       */
+  int64_t lanes_created, lanes_evicted;
+  int64_t bytes_in_use;           /* budget charged now (lanes + shape tables)            */
+  int64_t peak_bytes;
+  int64_t slots_in_use, pending, lanes;
+} wf_server_stats;
+
+/*
+ * wf_server_create -- start a server.
+ *   hbm_budget_bytes  device bytes its lanes and tables may hold (>= 16 MiB); a lane
+ *                     of (nside, lmax, dtype) with c slots needs about
+ *                     wf_footprint(nside, lmax, dtype, c) plus 12 nside^2 * 8 c bytes
+ *   max_slots         requests admitted at once, over all lanes (>= 1); a lane holds
+ *                     at most min(max_slots, 16) slots, fewer if that exceeds half
+ *                     the budget
+ * Errors: WF_EINVAL, WF_ENOMEM, WF_EDEVICE.
+ */
+int wf_server_create(wf_server_t* out, size_t hbm_budget_bytes, int32_t max_slots);
+
+/*
+ * wf_server_submit -- queue one solve; copies every input and returns at once.
+ *   cl (lmax+1), ninv, mask (npix, or NULL), d (npix): host doubles / bytes, as for
+ *   wf_plan and wf_solve; lambda: host, nsweeps entries (Sect. 3's cooling)
+ *   dtype     WF_F32, WF_BF16X6 or WF_BF16X3 (matrix-core Legendre contraction)
+ *   ticket    receives the request's id for wf_server_poll
+ * Errors: WF_EINVAL (as wf_plan / wf_solve), WF_EUNSUPPORTED (WF_F64),
+ * WF_ENOMEM (a one-slot lane of this shape alone exceeds the budget), or the
+ * status of a server stopped by a device error.
+ */
+int wf_server_submit(wf_server_t server, int32_t nside, int32_t lmax, const double* cl,
+                     const double* ninv, const uint8_t* mask, const double* d,
+                     const double* lambda, int32_t nsweeps, int32_t dtype, uint64_t* ticket);
+
+/*
+ * wf_server_poll -- WF_ENOTREADY while the request runs. When it has finished:
+ * WF_OK, s_wf_host (npix doubles, or NULL) receives the signal map, latency_s
+ * (or NULL) the seconds from submit to the result in host memory, and the ticket
+ * is released. A request that failed returns its error once. Unknown or already
+ * collected tickets: WF_EINVAL. Thread-safe.
+ */
+int wf_server_poll(wf_server_t server, uint64_t ticket, double* s_wf_host, double* latency_s);
+
+/* wf_server_query -- counters; returns the error status of a stopped server, else WF_OK. */
+int wf_server_query(wf_server_t server, wf_server_stats* out);
+
+/*
+ * wf_server_destroy -- stop both threads, drop queued requests, wait for the
+ * device and free everything (NULL is accepted).
+ */
+void wf_server_destroy(wf_server_t server);
+
 /* wf_sync -- wait for the plan's stream work; reports asynchronous device errors. */
 int wf_sync(wf_plan_t plan);
 

@@ -295,6 +295,72 @@ void apply_cached_tuning(wf_plan_s* p, int nmaps) {
 
 }  // namespace
 
+namespace mwf {
+
+// Work buffers and the device view of a plan whose geo, dtype, max_batch, tau, q
+// and cl are set (a solve plan or a serving lane).
+int plan_alloc(wf_plan_s* p) {
+  int rc;
+  const Geometry& g = *p->geo;
+  const int dtype = p->dtype, nside = g.nside, lmax = g.lmax;
+  // ---- work buffers
+  p->elem = (dtype == WF_F64) ? 8 : 4;
+  const size_t gf = (size_t)p->max_batch * g.npairs * (lmax + 1) * 4 * p->elem;
+  {
+    uint8_t *G = nullptr, *F = nullptr;
+    if ((rc = p->mem.alloc(&G, gf))) return rc;
+    if ((rc = p->mem.alloc(&F, gf))) return rc;
+    p->G = G;
+    p->F = F;
+  }
+  if (dtype == WF_F64) {
+    if ((rc = p->mem.alloc(&p->partial, (size_t)p->max_batch * g.nblk_max_ana * g.nalm))) return rc;
+    if ((rc = p->mem.alloc(&p->bcoef, (size_t)p->max_batch * g.rows_total))) return rc;
+  } else {
+    const size_t nb128 = (size_t)(g.npairs + 127) / 128;
+    if ((rc = p->mem.alloc(&p->partial32, nb128 * g.nalm * p->max_batch * 2))) return rc;
+    if ((rc = p->mem.alloc(&p->bcoef32, (size_t)g.rows_total * p->max_batch * 2))) return rc;
+  }
+  // F entries of skipped (m, ring pair) combinations are never written: keep them zero
+  if (hipMemset(p->F, 0, gf) != hipSuccess || hipMemset(p->G, 0, gf) != hipSuccess) {
+    set_error("initialising work buffers failed");
+    return WF_EDEVICE;
+  }
+
+  PlanDev& D = p->dev;
+  D.nside = nside;
+  D.lmax = lmax;
+  D.npairs = g.npairs;
+  D.nrings = g.nrings;
+  D.npix = g.npix;
+  D.nalm = g.nalm;
+  D.tau = p->tau;
+  D.omega = g.omega;
+  D.ring_block_ana = g.ring_block_ana;
+  D.ring_block_syn = g.ring_block_syn;
+  D.nblk_max = g.nblk_max_ana;
+  D.pairs = g.pairs;
+  D.q = p->q;
+  D.cl = p->cl;
+  D.A = g.A;
+  D.C = g.C;
+  D.row_off = g.row_off;
+  D.norm_m = g.norm;
+  D.n_active = g.nact;
+  D.nblk = g.nblk_ana;
+  D.twiddle = g.tw;
+  D.tw_len = g.tw_len;
+  D.bluestein = g.blue;
+  D.chirp = g.chirp;
+  D.twiddle32 = g.tw32;
+  D.chirp32 = g.chirp32;
+  D.bluestein32 = g.blue32;
+  D.rows_total = g.rows_total;
+  return WF_OK;
+}
+
+}  // namespace mwf
+
 extern "C" {
 
 const char* wf_strerror(int status) {
@@ -400,60 +466,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   }
   if ((rc = p->mem.upload(&p->cl, std::vector<double>(cl, cl + lmax + 1)))) return bail(rc);
 
-  // ---- work buffers
-  const Geometry& g = *geo;
-  p->elem = (dtype == WF_F64) ? 8 : 4;
-  const size_t gf = (size_t)p->max_batch * g.npairs * (lmax + 1) * 4 * p->elem;
-  {
-    uint8_t *G = nullptr, *F = nullptr;
-    if ((rc = p->mem.alloc(&G, gf))) return bail(rc);
-    if ((rc = p->mem.alloc(&F, gf))) return bail(rc);
-    p->G = G;
-    p->F = F;
-  }
-  if (dtype == WF_F64) {
-    if ((rc = p->mem.alloc(&p->partial, (size_t)p->max_batch * g.nblk_max_ana * g.nalm))) return bail(rc);
-    if ((rc = p->mem.alloc(&p->bcoef, (size_t)p->max_batch * g.rows_total))) return bail(rc);
-  } else {
-    const size_t nb128 = (size_t)(g.npairs + 127) / 128;
-    if ((rc = p->mem.alloc(&p->partial32, nb128 * g.nalm * p->max_batch * 2))) return bail(rc);
-    if ((rc = p->mem.alloc(&p->bcoef32, (size_t)g.rows_total * p->max_batch * 2))) return bail(rc);
-  }
-  // F entries of skipped (m, ring pair) combinations are never written: keep them zero
-  if (hipMemset(p->F, 0, gf) != hipSuccess || hipMemset(p->G, 0, gf) != hipSuccess) {
-    set_error("initialising work buffers failed");
-    return bail(WF_EDEVICE);
-  }
-
-  PlanDev& D = p->dev;
-  D.nside = nside;
-  D.lmax = lmax;
-  D.npairs = g.npairs;
-  D.nrings = g.nrings;
-  D.npix = g.npix;
-  D.nalm = g.nalm;
-  D.tau = p->tau;
-  D.omega = g.omega;
-  D.ring_block_ana = g.ring_block_ana;
-  D.ring_block_syn = g.ring_block_syn;
-  D.nblk_max = g.nblk_max_ana;
-  D.pairs = g.pairs;
-  D.q = p->q;
-  D.cl = p->cl;
-  D.A = g.A;
-  D.C = g.C;
-  D.row_off = g.row_off;
-  D.norm_m = g.norm;
-  D.n_active = g.nact;
-  D.nblk = g.nblk_ana;
-  D.twiddle = g.tw;
-  D.tw_len = g.tw_len;
-  D.bluestein = g.blue;
-  D.chirp = g.chirp;
-  D.twiddle32 = g.tw32;
-  D.chirp32 = g.chirp32;
-  D.bluestein32 = g.blue32;
-  D.rows_total = g.rows_total;
+  if ((rc = plan_alloc(p))) return bail(rc);
   apply_cached_tuning(p, p->max_batch);
   *out = p;
   return WF_OK;
@@ -610,9 +623,10 @@ extern "C" int wf_autotune(wf_plan_t p, int32_t nmaps, void* hip_stream, int32_t
 namespace mwf {
 
 // Block offsets of the four phases (ring, analysis, coefficients, synthesis) of a
-// list of tasks under a tuning; offs holds 4 x (ntasks + 1) entries.
+// list of tasks under a tuning; offs holds 4 x (ntasks + 1) entries. Tasks whose
+// gemm flag is 0 get no blocks in the three Legendre phases.
 void task_offsets(const std::vector<const Geometry*>& geos, const std::vector<int>& nmaps, const Tuning& tune,
-                  std::vector<int64_t>& offs, int64_t* nblocks) {
+                  std::vector<int64_t>& offs, int64_t* nblocks, const std::vector<char>* gemm) {
   const int nt = (int)geos.size();
   offs.assign(4 * (size_t)(nt + 1), 0);
   for (int ph = 0; ph < 4; ++ph) {
@@ -621,6 +635,7 @@ void task_offsets(const std::vector<const Geometry*>& geos, const std::vector<in
       offs[ph * (nt + 1) + t] = acc;
       const Geometry& g = *geos[t];
       const int nm = nmaps[t];
+      if (ph > 0 && gemm && !(*gemm)[t]) continue;   // ring phase only for this task
       switch (ph) {
         case 0: acc += (int64_t)g.npairs * nm; break;
         case 1: {
@@ -761,7 +776,7 @@ int wf_group_solve(wf_group_t gr, const void* const* d, void* const* s_wf, void*
     nm.push_back(gr->nmaps[t]);
   }
   std::vector<int64_t> offs;
-  task_offsets(geos, nm, gr->tune, offs, gr->nblocks);
+  task_offsets(geos, nm, gr->tune, offs, gr->nblocks, nullptr);
   MWF_HIP(hipMemcpy(gr->d_tasks, host.data(), host.size() * sizeof(TaskDev), hipMemcpyHostToDevice));
   MWF_HIP(hipMemcpy(gr->d_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   Timer timer;

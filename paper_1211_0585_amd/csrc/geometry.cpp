@@ -53,7 +53,8 @@ void host_fft(std::vector<std::complex<long double>>& a, int sign) {
 int ana_ring_block(int npairs) { return npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256); }
 
 std::mutex g_geo_mu;
-std::map<std::tuple<int, int, int>, std::shared_ptr<Geometry>> g_geo;
+// Weak entries: the tables of a shape live while a plan or serving lane holds them.
+std::map<std::tuple<int, int, int>, std::weak_ptr<Geometry>> g_geo;
 
 int build_geometry(Geometry& g) {
   const int nside = g.nside, lmax = g.lmax;
@@ -306,8 +307,10 @@ int get_geometry(int nside, int lmax, std::shared_ptr<Geometry>* out) {
   std::lock_guard<std::mutex> lock(g_geo_mu);
   auto it = g_geo.find(key);
   if (it != g_geo.end()) {
-    *out = it->second;
-    return WF_OK;
+    if (auto live = it->second.lock()) {
+      *out = live;
+      return WF_OK;
+    }
   }
   auto g = std::make_shared<Geometry>();
   g->device = dev;

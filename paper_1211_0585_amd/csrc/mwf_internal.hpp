@@ -103,6 +103,16 @@ enum PhaseBMode : int32_t {
 };
 
 // Pointers are in the plan's storage type (double, or float for the FP32 / BF16x3 paths).
+// Per-map parameters of a batch whose maps are independent requests (serving):
+// each map has its own lambda, lambda tau Omega (filter denominator term), phase-B
+// mode (0 = slot idle) and its own rows of tau N^-1 and C_l.
+struct SlotParam {
+  double lambda;
+  double lam_t_o;
+  int32_t pb_mode;
+  int32_t pad_;
+};
+
 struct PhaseBArgs {
   int32_t mode;
   int32_t nmaps;
@@ -112,6 +122,8 @@ struct PhaseBArgs {
   const void* d;          // [map][npix]
   const void* map_in;     // [map][npix]
   void* map_out;          // [map][npix]
+  const SlotParam* slots; // null: mode, lambda and P.q shared by all maps
+  int64_t q_stride;       // with slots: elements between the tau N^-1 rows of two maps
 };
 
 // Ring pairs launched together: a device list of pair indices and the largest
@@ -165,6 +177,8 @@ struct MfmaArgs {
   float* bcoef;             // [rows_total][nmaps][2]
   const float2* alm_in;     // [map][nalm]
   float2* alm_out;          // [map][nalm] or null
+  const SlotParam* slots;   // null: lambda and P.cl, P.tau shared by all maps
+  int64_t cl_stride;        // with slots: entries between the C_l rows of two maps
 };
 
 // ct: column tiles (16 columns) per analysis workgroup, 1 or 2 (ring block 128 ct);
@@ -196,6 +210,9 @@ struct TaskDev {
   const WorkItem* items_a128;   // analysis items for 128- and 256-pair blocks
   const WorkItem* items_a256;
   const WorkItem* items_s64;    // synthesis items (64 pairs)
+  const SlotParam* slots;       // per-map parameters (serving lanes) or null
+  int64_t q_stride;
+  int64_t cl_stride;
 };
 
 struct GroupLaunch {

@@ -393,11 +393,13 @@ __device__ __forceinline__ void coeff_body(const PlanDev& P, const MfmaArgs& a, 
   const int64_t row = alm_index(lmax, m, m);
   const int64_t roff = P.row_off[m];
   const double* __restrict__ Crow = P.C + roff;
-  const double lam_t_o = a.lambda * P.tau * P.omega;
+  const double lam_t_o_all = a.lambda * P.tau * P.omega;
   const int nb = (P.n_active[m] + a.ana_rb - 1) / a.ana_rb;
   const int nm = a.nmaps;
   for (int e = threadIdx.x; e < (nl + ROW_PAD) * nm; e += blockDim.x) {
     const int i = e / nm, map = e - i * nm;
+    const double lam_t_o = a.slots ? a.slots[map].lam_t_o : lam_t_o_all;
+    const double* __restrict__ cl_row = P.cl + (a.slots ? map * a.cl_stride : 0);
     double br = 0.0, bi = 0.0;
     if (i < nl) {
       double sr, si;
@@ -415,7 +417,7 @@ __device__ __forceinline__ void coeff_body(const PlanDev& P, const MfmaArgs& a, 
         sr *= Crow[i];
         si *= Crow[i];
         if (a.mode == SY_FROM_PARTIAL) {
-          const double cl = P.cl[m + i];
+          const double cl = cl_row[m + i];
           const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
           sr *= f;
           si *= f;
@@ -470,6 +472,8 @@ __device__ __forceinline__ MfmaArgs task_args(const TaskDev& t, int ana_rb) {
   a.bcoef = t.bcoef;
   a.alm_in = t.alm_in;
   a.alm_out = t.alm_out;
+  a.slots = t.slots;
+  a.cl_stride = t.cl_stride;
   return a;
 }
 

@@ -269,9 +269,10 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   const size_t pstride = (size_t)(lmax + 1) * 4;
   const size_t pbase = ((size_t)map * P.npairs + q) * pstride;
   const int64_t mbase = (int64_t)map * P.npix;
-  const int mode = a.mode;
+  const int mode = a.slots ? a.slots[map].pb_mode : a.mode;
+  if (mode == 0) return;                          // idle slot (uniform over the block)
   const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
-  const T* __restrict__ q_tab = static_cast<const T*>(P.q);
+  const T* __restrict__ q_tab = static_cast<const T*>(P.q) + (a.slots ? map * a.q_stride : 0);
 
   // ---- ring values into buf (x = north + i south)
   if (mode & PB_SYNTH) {
@@ -326,7 +327,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
 
   // ---- map output and the messenger update (Eq. 3)
   if (mode & (PB_WRITE_MAP | PB_UPDATE)) {
-    const double lam = a.lambda;
+    const double lam = a.slots ? a.slots[map].lambda : a.lambda;
     const T* __restrict__ d = static_cast<const T*>(a.d) + mbase;
     T* out = static_cast<T*>(a.map_out) + mbase;
     for (int j = tid; j < n; j += NT) {
@@ -407,6 +408,8 @@ __global__ void __launch_bounds__(512, 4) group_phase_b_kernel(const TaskDev* __
   a.d = t.d;
   a.map_in = t.map_in;
   a.map_out = t.map_out;
+  a.slots = t.slots;
+  a.q_stride = t.q_stride;
   phase_b_body<float, float, 512>(t.P, a, (int)(local / t.nmaps), (int)(local % t.nmaps));
 }
 

@@ -105,6 +105,22 @@ void load_tuning_file(const char* cache_path);
 
 }  // namespace mwf
 
+struct wf_plan_s;
+
+namespace mwf {
+
+int plan_alloc(wf_plan_s* p);
+void task_offsets(const std::vector<const Geometry*>& geos, const std::vector<int>& nmaps, const Tuning& tune,
+                  std::vector<int64_t>& offs, int64_t* nblocks, const std::vector<char>* gemm);
+TaskDev make_task(wf_plan_s* p, int nmaps, int pb_mode, int sy_mode, double lam, const void* d,
+                  void* map_out, void* alm_out);
+int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, int ntasks,
+                   int dtype, const Tuning& tune, size_t lds, bool synth_only, hipStream_t s);
+size_t plan_buffer_bytes(int nside, int lmax, int dtype, int nmaps);
+size_t geometry_bytes(int nside, int lmax);
+
+}  // namespace mwf
+
 struct wf_plan_s {
   std::shared_ptr<mwf::Geometry> geo;
   int dtype = WF_F64, max_batch = 1, flags = 0;

@@ -38,6 +38,12 @@ _SIGS = [
     ("wf_group_autotune", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                      _c.POINTER(_c.c_int32), _c.POINTER(_c.c_int32)]),
     ("wf_group_destroy", None, [_c.c_void_p]),
+    ("wf_server_create", _c.c_int, [_c.POINTER(_c.c_void_p), _c.c_size_t, _c.c_int32]),
+    ("wf_server_submit", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                    _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_uint64)]),
+    ("wf_server_poll", _c.c_int, [_c.c_void_p, _c.c_uint64, _c.c_void_p, _c.POINTER(_c.c_double)]),
+    ("wf_server_query", _c.c_int, [_c.c_void_p, _c.c_void_p]),
+    ("wf_server_destroy", None, [_c.c_void_p]),
     ("wf_sync", _c.c_int, [_c.c_void_p]),
     ("wf_destroy", None, [_c.c_void_p]),
     ("wf_strerror", _c.c_char_p, [_c.c_int]),
@@ -311,3 +317,91 @@ class Group:
             self.close()
         except Exception:
             pass
+
+
+class wf_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "submitted", "completed", "steps", "map_sweeps", "peak_slots", "lanes_created", "lanes_evicted",
+        "bytes_in_use", "peak_bytes", "slots_in_use", "pending", "lanes")]
+
+
+class Server:
+    """Continuous-batching request loop (wf_server_*): submit solves, poll results.
+
+    Inputs are host arrays; results come back as host float64 maps with the
+    submit-to-result latency measured inside the library.
+    """
+
+    def __init__(self, hbm_budget=64 << 30, max_slots=64):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the server needs a HIP device")
+        torch.cuda.init()
+        h = ctypes.c_void_p()
+        _check(lib().wf_server_create(ctypes.byref(h), int(hbm_budget), int(max_slots)))
+        self._h = h
+        self._npix = {}
+
+    def submit(self, nside, lmax, cl, ninv, d, lambdas, mask=None, dtype=WF_F32):
+        npix = 12 * nside * nside
+        cl = np.ascontiguousarray(cl, dtype=np.float64)
+        ninv = np.ascontiguousarray(ninv, dtype=np.float64)
+        d = np.ascontiguousarray(d, dtype=np.float64)
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        if cl.size != lmax + 1 or ninv.size != npix or d.size != npix:
+            raise ValueError("cl needs lmax+1 entries, ninv and d npix entries")
+        mptr = None
+        if mask is not None:
+            mask = np.ascontiguousarray(np.asarray(mask).astype(np.uint8))
+            if mask.size != npix:
+                raise ValueError("mask must have npix entries")
+            mptr = mask.ctypes.data
+        t = ctypes.c_uint64()
+        _check(lib().wf_server_submit(self._h, nside, lmax, cl.ctypes.data, ninv.ctypes.data, mptr, d.ctypes.data,
+                                      lam.ctypes.data, lam.size, dtype, ctypes.byref(t)))
+        self._npix[t.value] = npix
+        return t.value
+
+    def poll(self, ticket):
+        """None while running; (s_wf float64 [npix], latency seconds) once finished."""
+        out = np.empty(self._npix[ticket])
+        lat = ctypes.c_double()
+        rc = lib().wf_server_poll(self._h, ticket, out.ctypes.data, ctypes.byref(lat))
+        if rc == WF_ENOTREADY:
+            return None
+        del self._npix[ticket]
+        _check(rc)
+        return out, lat.value
+
+    def wait(self, ticket, timeout=120.0, interval=2e-4):
+        import time
+        t0 = time.perf_counter()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.perf_counter() - t0 > timeout:
+                raise TimeoutError(f"request {ticket} not finished after {timeout} s")
+            time.sleep(interval)
+
+    def stats(self):
+        st = wf_server_stats()
+        _check(lib().wf_server_query(self._h, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in wf_server_stats._fields_}
+
+    def close(self):
+        if self._h is not None:
+            lib().wf_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
