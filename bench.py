@@ -43,6 +43,12 @@ def parse():
     ap.add_argument("--batch", type=int, default=64,
                     help="maps of the batched (matrix-core) runs; 0 skips them")
     ap.add_argument("--batch-modes", default="f32,bf16x6,bf16x3")
+    ap.add_argument("--mixed", type=int, default=1,
+                    help="run the uneven batch 32@(128,256) + 16@(256,512) + 8@(512,1024) (0 skips it)")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the Poisson request stream (0 skips serving)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
+    ap.add_argument("--serve-nsides", default="64,128,256,512,1024")
     return ap.parse_args()
 
 
@@ -147,6 +153,13 @@ def main():
         batched = run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside, lmax, K, W,
                               value)
 
+    mixed = {}
+    if args.mixed:
+        mixed = run_mixed(args, np, torch, mwf, synth, dev, K, W)
+    serving = {}
+    if args.serve_seconds > 0:
+        serving = run_serving(args, np, torch, mwf, synth, dev)
+
     # ---- CPU baseline: the FP64 oracle, unchanged, on a bounded sample
     cpu = None
     if args.cpu_sweeps > 0:
@@ -186,6 +199,8 @@ def main():
                              "sweeps": int(len(sched)), "repeats": int(len(lat))},
         "kernels": kern,
         "batched": batched,
+        "mixed_batch": mixed,
+        "serving": serving,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -243,6 +258,142 @@ def run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside,
         out["vs_plain_f64"][name] = mit / plain_value
         log(f"[bench] batched {name}: {mit:.0f} map-it/s ({1e3 * el / K:.2f} ms per sweep of {B} maps)")
     return out
+
+
+def run_mixed(args, np, torch, mwf, synth, dev, K, W):
+    """Uneven batch: 32 maps at (128, 256), 16 at (256, 512), 8 at (512, 1024), the
+    satellite recipe at each nside with N_obs scaled by (512/nside)^2, seeds 0..n-1,
+    FP32 matrix-core path. One task group (one launch per phase for all three
+    shapes) with the launch shape picked by the autotuner, against the three plans
+    solved one after the other."""
+    shapes = [(128, 256, 32), (256, 512, 16), (512, 1024, 8)]
+    plans, ds = [], []
+    for nside, lmax, n in shapes:
+        th, ph = mwf.pixel_angles(nside)
+        model = synth.satellite_model(th, ph, lmax, nobs_scale=(512.0 / nside) ** 2)
+        log(f"[bench] mixed batch: drawing {n} maps at Nside {nside}")
+        alms = np.stack([synth.draw(model, s)["signal_alm"] for s in range(n)]).astype(np.complex64)
+        noise = np.stack([synth.draw(model, s)["noise"] for s in range(n)]).astype(np.float32)
+        p = mwf.Plan(nside, lmax, model["cl"], model["ninv"], mask=~model["mask"], dtype=mwf.WF_F32, max_batch=n)
+        ds.append(p.alm2map(torch.from_numpy(alms).to(dev)) + torch.from_numpy(noise).to(dev))
+        plans.append(p)
+        sched = model["schedule"]
+    lam = np.resize(sched, K)
+    nmaps = [n for _, _, n in shapes]
+    g = mwf.Group(plans, nmaps)
+    ct, nct = g.autotune(ds)
+    if W:
+        g.solve(ds, lam[:W], want_alm=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gw, _ = g.solve(ds, lam, want_alm=False)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    g.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sep = [p.solve(d, lam, want_alm=False)[0] for p, d in zip(plans, ds)]
+    torch.cuda.synchronize()
+    el_sep = time.perf_counter() - t0
+    diff = max(float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
+               for a, b in zip(gw, sep))
+    for p in plans:
+        p.close()
+    total = sum(nmaps)
+    res = {"maps": {f"{n}@({a},{b})": n for a, b, n in shapes}, "sweeps": K, "dtype": "f32",
+           "tile": {"analysis_column_tiles": ct, "synthesis_column_tiles": nct},
+           "map_iters_per_s": total * K / el, "ms_per_sweep": 1e3 * el / K,
+           "separate_plans_map_iters_per_s": total * K / el_sep, "group_vs_separate_rel_l2": diff}
+    log(f"[bench] mixed batch: {res['map_iters_per_s']:.0f} map-it/s grouped, "
+        f"{res['separate_plans_map_iters_per_s']:.0f} separate; tile ({ct}, {nct}); rel diff {diff:.1e}")
+    return res
+
+
+def run_serving(args, np, torch, mwf, synth, dev):
+    """Poisson request stream into the continuous-batching server. Each request:
+    nside uniform over the configured set, lmax = 2 nside, its own galactic cut
+    U[5, 25] deg, noise amplitude sigma0 ~ U[0.5, 5] mK with N_obs of the satellite
+    recipe scaled by (512/nside)^2, its own noise draw, FP32, 30 cooling + 50 final
+    sweeps. Signal maps come from a pool of 4 draws per nside and unit noise from a
+    pool of 4 per nside (scaled per request), drawn before the clock starts so the
+    host keeps pace with the arrival rate. Latency = scheduled arrival -> s_WF in
+    host memory."""
+    import queue
+    import threading
+    nsides = [int(x) for x in args.serve_nsides.split(",")]
+    rate, T = args.serve_rate, args.serve_seconds
+    rs = np.random.default_rng(2024)
+    pools = {}
+    for nside in nsides:
+        lmax = 2 * nside
+        th, ph = mwf.pixel_angles(nside)
+        model = synth.satellite_model(th, ph, lmax, nobs_scale=(512.0 / nside) ** 2, ndisc=0)
+        nobs = (2200.0 ** 2) / model["sigma2"]            # N_obs of the recipe
+        with mwf.Plan(nside, lmax, model["cl"], np.ones(th.size), dtype=mwf.WF_F32, max_batch=4) as p:
+            alms = np.stack([synth.draw(model, s)["signal_alm"] for s in range(4)]).astype(np.complex64)
+            sig = p.alm2map(torch.from_numpy(alms).to(dev)).double().cpu().numpy()
+        unit = np.stack([synth.rng(100 + s, 1).standard_normal(th.size) for s in range(4)])
+        pools[nside] = dict(theta=th, cl=model["cl"], nobs=nobs, sig=sig, unit=unit,
+                            sched=model["schedule"], lmax=lmax)
+        log(f"[bench] serving: pools ready for Nside {nside}")
+    arrivals = np.cumsum(rs.exponential(1.0 / rate, int(2 * rate * T) + 64))
+    arrivals = arrivals[arrivals < T]
+    specs = [dict(nside=int(rs.choice(nsides)), cut=float(rs.uniform(5, 25)), s0=float(rs.uniform(0.5, 5.0)),
+                  sig=int(rs.integers(4)), noi=int(rs.integers(4))) for _ in arrivals]
+
+    def build(sp):
+        P = pools[sp["nside"]]
+        mask = synth.galactic_cut(P["theta"], sp["cut"])
+        sigma2 = (sp["s0"] * 1000.0) ** 2 / P["nobs"]
+        ninv = np.where(mask, 0.0, 1.0 / sigma2)
+        d = P["sig"][sp["sig"]] + np.sqrt(sigma2) * P["unit"][sp["noi"]]
+        return ninv, d
+
+    srv = mwf.Server(hbm_budget=128 << 30, max_slots=64)
+    # one short request per shape first, so lanes and tables exist before the clock
+    for nside in nsides:
+        P = pools[nside]
+        ninv, d = build(dict(nside=nside, cut=10.0, s0=1.0, sig=0, noi=0))
+        srv.wait(srv.submit(nside, P["lmax"], P["cl"], ninv, d, P["sched"][:2]), timeout=300)
+    log(f"[bench] serving: {len(specs)} requests over {T:.0f} s at {rate:.0f}/s")
+    q = queue.Queue(maxsize=16)
+
+    def producer():
+        for sp in specs:
+            q.put((sp, build(sp)))
+    th_prod = threading.Thread(target=producer, daemon=True)
+    th_prod.start()
+    tickets = []
+    t_start = time.perf_counter()
+    lags = []
+    for i, t_arr in enumerate(arrivals):
+        sp, (ninv, d) = q.get()
+        now = time.perf_counter() - t_start
+        if now < t_arr:
+            time.sleep(t_arr - now)
+        P = pools[sp["nside"]]
+        tk = srv.submit(sp["nside"], P["lmax"], P["cl"], ninv, d, P["sched"])
+        lags.append(max(0.0, time.perf_counter() - t_start - t_arr))
+        tickets.append(tk)
+    lat, done_at, sweeps = [], [], 0
+    for i, tk in enumerate(tickets):
+        s_wf, l = srv.wait(tk, timeout=600)
+        lat.append(l + lags[i])
+        sweeps += len(pools[specs[i]["nside"]]["sched"])
+    t_end = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat)
+    res = {"requests": len(tickets), "offered_rate": rate, "seconds": T, "dtype": "f32",
+           "nsides": nsides, "sweeps_per_request": int(len(pools[nsides[0]]["sched"])),
+           "throughput_req_per_s": len(tickets) / t_end, "map_iters_per_s": sweeps / t_end,
+           "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
+                          "max": float(lat.max() * 1e3)},
+           "submit_lag_ms_max": float(max(lags) * 1e3) if lags else 0.0,
+           "peak_slots": st["peak_slots"], "steps": st["steps"], "peak_hbm_gb": st["peak_bytes"] / 1e9}
+    log(f"[bench] serving: {res['throughput_req_per_s']:.1f} req/s, p50 {res['latency_ms']['p50']:.0f} ms, "
+        f"p99 {res['latency_ms']['p99']:.0f} ms, peak slots {st['peak_slots']}")
+    return res
 
 
 def _blas_threads():

@@ -204,7 +204,7 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   // With few maps one launch over all ring pairs fills the GPU better than two
   // back-to-back launches split by transform length.
   const RingClass none{nullptr, 0, 4};
-  const bool split = nmaps >= 4;
+  const bool split = nmaps >= RING_SPLIT_MAPS;
   TIMED(0, MWF_HIP(launch_phase_b(p->dev, a, split ? g.ring_small : none, split ? g.ring_large : g.ring_all,
                                   p->dtype != WF_F64, s)));
   return WF_OK;
@@ -622,28 +622,38 @@ extern "C" int wf_autotune(wf_plan_t p, int32_t nmaps, void* hip_stream, int32_t
 // ---------------------------------------------------------------- task groups
 namespace mwf {
 
-// Block offsets of the four phases (ring, analysis, coefficients, synthesis) of a
-// list of tasks under a tuning; offs holds 4 x (ntasks + 1) entries. Tasks whose
-// gemm flag is 0 get no blocks in the three Legendre phases.
-void task_offsets(const std::vector<const Geometry*>& geos, const std::vector<int>& nmaps, const Tuning& tune,
-                  std::vector<int64_t>& offs, int64_t* nblocks, const std::vector<char>* gemm) {
+// Block offsets of the five phases of a task list (ring pairs of the 512-thread
+// class, ring pairs of the one-wave class, analysis, coefficients, synthesis)
+// under a tuning: offs holds 5 x (ntasks + 1) entries. Tasks whose gemm flag is 0
+// get no blocks in the three Legendre phases. lds receives the dynamic LDS bytes
+// of the two ring launches.
+void task_offsets(const TaskDev* tasks, const std::vector<const Geometry*>& geos, const Tuning& tune,
+                  std::vector<int64_t>& offs, int64_t* nblocks, size_t* lds, const std::vector<char>* gemm) {
   const int nt = (int)geos.size();
-  offs.assign(4 * (size_t)(nt + 1), 0);
-  for (int ph = 0; ph < 4; ++ph) {
+  offs.assign(NPHASE * (size_t)(nt + 1), 0);
+  lds[0] = lds[1] = 0;
+  for (int ph = 0; ph < NPHASE; ++ph) {
     int64_t acc = 0;
     for (int t = 0; t < nt; ++t) {
       offs[ph * (nt + 1) + t] = acc;
       const Geometry& g = *geos[t];
-      const int nm = nmaps[t];
-      if (ph > 0 && gemm && !(*gemm)[t]) continue;   // ring phase only for this task
+      const int nm = tasks[t].nmaps;
+      if (ph >= 2 && gemm && !(*gemm)[t]) continue;   // ring phase only for this task
       switch (ph) {
-        case 0: acc += (int64_t)g.npairs * nm; break;
-        case 1: {
+        case 0:
+        case 1:
+          acc += (int64_t)tasks[t].ring_n[ph] * nm;
+          if (tasks[t].ring_n[ph]) {
+            const RingClass& rc = (ph == 1) ? g.ring_small : (tasks[t].ring_n[1] ? g.ring_large : g.ring_all);
+            lds[ph] = std::max(lds[ph], (size_t)rc.fft_len * sizeof(float2));
+          }
+          break;
+        case 2: {
           const int ct = tune.ana_ct;
           acc += (int64_t)(ct == 1 ? g.n_a128 : g.n_a256) * ((2 * nm + 16 * ct - 1) / (16 * ct));
           break;
         }
-        case 2: acc += g.lmax + 1; break;
+        case 3: acc += g.lmax + 1; break;
         default: acc += (int64_t)g.n_s64 * ((2 * nm + 16 * tune.syn_nct - 1) / (16 * tune.syn_nct));
       }
     }
@@ -669,28 +679,45 @@ TaskDev make_task(wf_plan_s* p, int nmaps, int pb_mode, int sy_mode, double lam,
   t.bcoef = p->bcoef32;
   t.alm_in = nullptr;
   t.alm_out = static_cast<float2*>(alm_out);
-  t.items_a128 = p->geo->items_a128;
-  t.items_a256 = p->geo->items_a256;
-  t.items_s64 = p->geo->items_s64;
+  const Geometry& g = *p->geo;
+  t.items_a128 = g.items_a128;
+  t.items_a256 = g.items_a256;
+  t.items_s64 = g.items_s64;
+  // same ring classes as a plan's own launches: split by transform length from 4 maps on
+  if (nmaps >= RING_SPLIT_MAPS) {
+    t.ring_q[0] = g.ring_large.q;
+    t.ring_n[0] = g.ring_large.count;
+    t.ring_q[1] = g.ring_small.q;
+    t.ring_n[1] = g.ring_small.count;
+  } else {
+    t.ring_q[0] = g.ring_all.q;
+    t.ring_n[0] = g.ring_all.count;
+  }
   return t;
 }
 
-// One step of a task array already on the device: ring phase, then (unless
-// synth_only) analysis, coefficients and synthesis, one launch each.
-int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, int ntasks,
-                   int dtype, const Tuning& tune, size_t lds, bool synth_only, hipStream_t s) {
+// One step of a task array already on the device: the two ring launches, then
+// (unless synth_only) analysis, coefficients and synthesis, one launch each.
+int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const size_t* lds,
+                   int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s) {
+  const int stride = ntasks + 1;
   GroupLaunch g{d_tasks, d_offs, ntasks, 0, nblocks[0]};
-  TIMED(0, MWF_HIP(launch_group_phase_b(g, lds, s)));
+  TIMED(0, {
+    MWF_HIP(launch_group_phase_b(g, 0, lds[0], s));
+    g.offs = d_offs + stride;
+    g.nblocks = nblocks[1];
+    MWF_HIP(launch_group_phase_b(g, 1, lds[1], s));
+  });
   if (synth_only) return WF_OK;
-  g.offs = d_offs + (ntasks + 1);
-  g.nblocks = nblocks[1];
+  g.offs = d_offs + 2 * stride;
+  g.nblocks = nblocks[2];
   TIMED(1, MWF_HIP(launch_group_analysis(g, dtype, tune.ana_ct, s)));
   TIMED(2, {
-    g.offs = d_offs + 2 * (ntasks + 1);
-    g.nblocks = nblocks[2];
-    MWF_HIP(launch_group_coeff(g, 128 * tune.ana_ct, s));
-    g.offs = d_offs + 3 * (ntasks + 1);
+    g.offs = d_offs + 3 * stride;
     g.nblocks = nblocks[3];
+    MWF_HIP(launch_group_coeff(g, 128 * tune.ana_ct, s));
+    g.offs = d_offs + 4 * stride;
+    g.nblocks = nblocks[4];
     MWF_HIP(launch_group_synthesis(g, dtype, tune.syn_nct, 128 * tune.ana_ct, s));
   });
   return WF_OK;
@@ -721,7 +748,6 @@ int wf_group_create(wf_group_t* out, int32_t nplans, const wf_plan_t* plans, con
     }
     gr->plans.push_back(p);
     gr->nmaps.push_back(nmaps[i]);
-    gr->lds_phase_b = std::max(gr->lds_phase_b, (size_t)p->geo->ring_all.fft_len * sizeof(float2));
   }
   gr->tune = plans[0]->tune;
   gr->mem.reset(new DevMem());
@@ -766,17 +792,13 @@ int wf_group_solve(wf_group_t gr, const void* const* d, void* const* s_wf, void*
     gr->d_tasks = nullptr;
     gr->d_offs = nullptr;
     if ((rc = gr->mem->alloc(&gr->d_tasks, host.size()))) return rc;
-    if ((rc = gr->mem->alloc(&gr->d_offs, 4 * (size_t)(nt + 1)))) return rc;
+    if ((rc = gr->mem->alloc(&gr->d_offs, NPHASE * (size_t)(nt + 1)))) return rc;
     gr->d_tasks_cap = host.size();
   }
   std::vector<const Geometry*> geos;
-  std::vector<int> nm;
-  for (int t = 0; t < nt; ++t) {
-    geos.push_back(gr->plans[t]->geo.get());
-    nm.push_back(gr->nmaps[t]);
-  }
+  for (int t = 0; t < nt; ++t) geos.push_back(gr->plans[t]->geo.get());
   std::vector<int64_t> offs;
-  task_offsets(geos, nm, gr->tune, offs, gr->nblocks, nullptr);
+  task_offsets(host.data(), geos, gr->tune, offs, gr->nblocks, gr->lds, nullptr);
   MWF_HIP(hipMemcpy(gr->d_tasks, host.data(), host.size() * sizeof(TaskDev), hipMemcpyHostToDevice));
   MWF_HIP(hipMemcpy(gr->d_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   Timer timer;
@@ -784,8 +806,8 @@ int wf_group_solve(wf_group_t gr, const void* const* d, void* const* s_wf, void*
   timer.s = s;
   TimerScope scope(&timer);
   for (int k = 0; k <= nsweeps; ++k)
-    if ((rc = run_group_step(gr->d_tasks + (size_t)k * nt, gr->d_offs, gr->nblocks, nt, gr->dtype, gr->tune,
-                             gr->lds_phase_b, k == nsweeps, s)))
+    if ((rc = run_group_step(gr->d_tasks + (size_t)k * nt, gr->d_offs, gr->nblocks, gr->lds, nt, gr->dtype,
+                             gr->tune, k == nsweeps, s)))
       return rc;
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));

@@ -213,6 +213,8 @@ struct TaskDev {
   const SlotParam* slots;       // per-map parameters (serving lanes) or null
   int64_t q_stride;
   int64_t cl_stride;
+  const int32_t* ring_q[2];     // ring pairs of the 512-thread (0) and one-wave (1) ring launches
+  int32_t ring_n[2];
 };
 
 struct GroupLaunch {
@@ -227,7 +229,8 @@ hipError_t launch_group_analysis(const GroupLaunch& g, int mode, int ct, hipStre
 hipError_t launch_group_coeff(const GroupLaunch& g, int ana_rb, hipStream_t s);
 hipError_t launch_group_synthesis(const GroupLaunch& g, int mode, int nct, int ana_rb, hipStream_t s);
 // Ring phase over (task, ring pair, map) blocks, float storage and arithmetic.
-hipError_t launch_group_phase_b(const GroupLaunch& g, size_t lds_bytes, hipStream_t s);
+// cls 0: 512-thread workgroups over TaskDev::ring_q[0]; cls 1: one wave per pair over ring_q[1].
+hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, size_t lds_bytes, hipStream_t s);
 
 // Plan-time: which ring pairs ever reach a non-negligible lambda_lm (polar skip).
 hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s);

@@ -387,10 +387,12 @@ __global__ void __launch_bounds__(NT, 4) phase_b_kernel(PlanDev P, PhaseBArgs a,
   phase_b_body<T, C, NT>(P, a, qlist[blockIdx.x], blockIdx.y);
 }
 
-// Task groups (float storage and arithmetic): block b of task t covers ring pair
-// (b - offs[t]) / nmaps and map (b - offs[t]) % nmaps.
-__global__ void __launch_bounds__(512, 4) group_phase_b_kernel(const TaskDev* __restrict__ tasks,
-                                                               const int64_t* __restrict__ offs, int ntasks) {
+// Task groups (float storage and arithmetic): block b of task t covers entry
+// (b - offs[t]) / nmaps of the task's ring-pair list of this class and map
+// (b - offs[t]) % nmaps.
+template <int NT, int CLS>
+__global__ void __launch_bounds__(NT, 4) group_phase_b_kernel(const TaskDev* __restrict__ tasks,
+                                                              const int64_t* __restrict__ offs, int ntasks) {
   int lo = 0, hi = ntasks - 1;
   const int64_t b = blockIdx.x;
   while (lo < hi) {
@@ -410,7 +412,7 @@ __global__ void __launch_bounds__(512, 4) group_phase_b_kernel(const TaskDev* __
   a.map_out = t.map_out;
   a.slots = t.slots;
   a.q_stride = t.q_stride;
-  phase_b_body<float, float, 512>(t.P, a, (int)(local / t.nmaps), (int)(local % t.nmaps));
+  phase_b_body<float, float, NT>(t.P, a, t.ring_q[CLS][local / t.nmaps], (int)(local % t.nmaps));
 }
 
 template <class T, class C, int NT>
@@ -438,17 +440,23 @@ hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, const RingClass& smal
 
 }  // namespace
 
-hipError_t launch_group_phase_b(const GroupLaunch& g, size_t lds_bytes, hipStream_t s) {
-  if (g.nblocks == 0) return hipSuccess;
+template <int NT, int CLS>
+hipError_t group_class(const GroupLaunch& g, size_t lds_bytes, hipStream_t s) {
   static size_t attr_bytes = 0;
   if (lds_bytes > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)group_phase_b_kernel,
+    hipError_t e = hipFuncSetAttribute((const void*)group_phase_b_kernel<NT, CLS>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
     if (e != hipSuccess) return e;
     attr_bytes = lds_bytes;
   }
-  hipLaunchKernelGGL(group_phase_b_kernel, dim3(g.nblocks), dim3(512), lds_bytes, s, g.tasks, g.offs, g.ntasks);
+  hipLaunchKernelGGL((group_phase_b_kernel<NT, CLS>), dim3(g.nblocks), dim3(NT), lds_bytes, s, g.tasks, g.offs,
+                     g.ntasks);
   return hipGetLastError();
+}
+
+hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, size_t lds_bytes, hipStream_t s) {
+  if (g.nblocks == 0) return hipSuccess;
+  return cls == 0 ? group_class<512, 0>(g, lds_bytes, s) : group_class<64, 1>(g, lds_bytes, s);
 }
 
 hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,

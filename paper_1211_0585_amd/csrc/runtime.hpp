@@ -110,12 +110,17 @@ struct wf_plan_s;
 namespace mwf {
 
 int plan_alloc(wf_plan_s* p);
-void task_offsets(const std::vector<const Geometry*>& geos, const std::vector<int>& nmaps, const Tuning& tune,
-                  std::vector<int64_t>& offs, int64_t* nblocks, const std::vector<char>* gemm);
+// Phases of a group step and the batch size from which ring pairs are launched
+// in two classes by transform length (as a plan's own ring launches).
+constexpr int NPHASE = 5;
+constexpr int RING_SPLIT_MAPS = 4;
+
+void task_offsets(const TaskDev* tasks, const std::vector<const Geometry*>& geos, const Tuning& tune,
+                  std::vector<int64_t>& offs, int64_t* nblocks, size_t* lds, const std::vector<char>* gemm);
 TaskDev make_task(wf_plan_s* p, int nmaps, int pb_mode, int sy_mode, double lam, const void* d,
                   void* map_out, void* alm_out);
-int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, int ntasks,
-                   int dtype, const Tuning& tune, size_t lds, bool synth_only, hipStream_t s);
+int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const size_t* lds,
+                   int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s);
 size_t plan_buffer_bytes(int nside, int lmax, int dtype, int nmaps);
 size_t geometry_bytes(int nside, int lmax);
 
@@ -148,11 +153,11 @@ struct wf_group_s {
   std::vector<int32_t> nmaps;
   int dtype = WF_F32;
   mwf::Tuning tune;
-  size_t lds_phase_b = 0;
+  size_t lds[2] = {0, 0};              // dynamic LDS of the two ring launches
   // per solve: one TaskDev array per step (sweeps + final synthesis)
   mwf::TaskDev* d_tasks = nullptr;
   size_t d_tasks_cap = 0;
-  int64_t* d_offs = nullptr;           // [4 phases][ntasks + 1]
-  int64_t nblocks[4] = {0, 0, 0, 0};
+  int64_t* d_offs = nullptr;           // [NPHASE][ntasks + 1]
+  int64_t nblocks[mwf::NPHASE] = {};
   std::unique_ptr<mwf::DevMem> mem;
 };

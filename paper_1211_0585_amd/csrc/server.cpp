@@ -372,9 +372,9 @@ struct wf_server_s {
       int dtype;
       size_t tasks_off, offs_off;
       int ntasks;
-      int64_t nblocks[4];
+      int64_t nblocks[NPHASE];
+      size_t lds[2];
       Tuning tune;
-      size_t lds;
     };
     std::vector<Launch> launches;
     std::vector<Job*> finals;
@@ -387,10 +387,9 @@ struct wf_server_s {
       Launch ln{};
       ln.dtype = dtype;
       ln.ntasks = nt;
-      ln.offs_off = carve(4 * (size_t)(nt + 1) * sizeof(int64_t));
+      ln.offs_off = carve(NPHASE * (size_t)(nt + 1) * sizeof(int64_t));
       ln.tasks_off = carve((size_t)nt * sizeof(TaskDev));
       std::vector<const Geometry*> geos;
-      std::vector<int> nm;
       std::vector<char> gemm;
       for (int t = 0; t < nt; ++t) {
         Lane* L = ls[t];
@@ -424,13 +423,12 @@ struct wf_server_s {
         T.cl_stride = L->lmax + 1;
         reinterpret_cast<TaskDev*>(hb + ln.tasks_off)[t] = T;
         geos.push_back(L->plan->geo.get());
-        nm.push_back(extent);
         gemm.push_back(sweeps ? 1 : 0);
-        ln.lds = std::max(ln.lds, (size_t)L->plan->geo->ring_all.fft_len * sizeof(float2));
       }
       ln.tune = ls[0]->plan->tune;
       std::vector<int64_t> offs;
-      task_offsets(geos, nm, ln.tune, offs, ln.nblocks, &gemm);
+      task_offsets(reinterpret_cast<const TaskDev*>(hb + ln.tasks_off), geos, ln.tune, offs, ln.nblocks, ln.lds,
+                   &gemm);
       std::memcpy(hb + ln.offs_off, offs.data(), offs.size() * sizeof(int64_t));
       launches.push_back(ln);
     }
@@ -440,7 +438,7 @@ struct wf_server_s {
     for (const Launch& ln : launches) {
       const auto* tasks = reinterpret_cast<const TaskDev*>(db + ln.tasks_off);
       const auto* offs = reinterpret_cast<const int64_t*>(db + ln.offs_off);
-      if (int rc = run_group_step(tasks, offs, ln.nblocks, ln.ntasks, ln.dtype, ln.tune, ln.lds, false, stream))
+      if (int rc = run_group_step(tasks, offs, ln.nblocks, ln.lds, ln.ntasks, ln.dtype, ln.tune, false, stream))
         return rc;
     }
     for (Job* j : finals) {
