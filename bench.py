@@ -49,6 +49,8 @@ def parse():
                     help="length of the Poisson request stream (0 skips serving)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
     ap.add_argument("--serve-nsides", default="64,128,256,512,1024")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run N plain 512 MiB device copies (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -110,6 +112,15 @@ def main():
         lat.append(1e3 * (time.perf_counter() - a))
     lat = np.array(lat)
 
+    if args.calibrate_copy:
+        # a copy of known size: 512 MiB read + 512 MiB written per launch
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(args.calibrate_copy):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     # ---- per-kernel durations from HIP events on the launch stream
     tplan = mwf.Plan(nside, lmax, case["cl"], case["ninv"], mask=~case["mask"],
                      flags=mwf.WF_FLAG_TIMING)
@@ -137,14 +148,15 @@ def main():
     totals = {"legendre_analysis": st.ms_analysis, "legendre_synthesis": st.ms_synthesis,
               "ring_fft_update": st.ms_ring}
     dom = max(totals, key=totals.get)
+    traffic = _measured_traffic(dom) if (nside, lmax) == (512, 1024) else None
     if dom == "ring_fft_update":
         ach = kern[dom]["gbs"]
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None}
+                "frac": ach / PEAK_HBM_GBS, "traffic": traffic}
     else:
         ach = kern[dom]["tflops"]
         roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64_TFLOPS, "traffic": traffic,
                 "flops_per_launch": leg_flops}
 
     # ---- batched runs: nmaps independent simulations sharing C_l, N^-1 and mask
@@ -195,8 +207,8 @@ def main():
         "config": {"workload": f"satellite-scale messenger Wiener filter, plain FP64, one map, "
                                f"Nside {nside} lmax {lmax}",
                    "nside": nside, "lmax": lmax, "maps": 1, "path": "plain"},
-        "solve_latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                             "sweeps": int(len(sched)), "repeats": int(len(lat))},
+        "solve_latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                              "sweeps": int(len(sched)), "repeats": int(len(lat))} if len(lat) else None),
         "kernels": kern,
         "batched": batched,
         "mixed_batch": mixed,
@@ -394,6 +406,24 @@ def run_serving(args, np, torch, mwf, synth, dev):
     log(f"[bench] serving: {res['throughput_req_per_s']:.1f} req/s, p50 {res['latency_ms']['p50']:.0f} ms, "
         f"p99 {res['latency_ms']['p99']:.0f} ms, peak slots {st['peak_slots']}")
     return res
+
+
+def _measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE
+    counter runs (scaled by a copy of known size), or None when the kernel sources
+    changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_plain_f64_nside512.json")
+    try:
+        rec = json.load(open(path))
+        h = hashlib.sha256()
+        for f in rec["source_files"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != rec["source_sha256_16"]:
+            return None
+        return float(rec["kernels"][kernel]["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _blas_threads():
