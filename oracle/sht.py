@@ -119,6 +119,27 @@ def alm2map(alm, nside, lmax):
     return ring_synthesis(F, nside, lmax)
 
 
+def map2alm_columns(maps, nside, lmax, ms):
+    """The analysis restricted to a few m: {m: a_lm for l = m..lmax}, each from the
+    same ring sums and Legendre values as map2alm (spot checks of large transforms,
+    where the full Legendre sum over every m would take too long)."""
+    g = healpix.ring_info(nside)
+    G = ring_analysis(maps, nside, lmax)
+    omega = healpix.pixel_area(nside)
+    return {int(m): omega * (lambda_m(lmax, int(m), g["z"]) @ G[:, int(m)]) for m in ms}
+
+
+def alm2map_columns(cols, nside, lmax):
+    """Synthesis of a real field whose alm vanish outside the given m:
+    cols = {m: a_lm for l = m..lmax}. Equals alm2map of the full packed array that
+    holds these columns and zeros elsewhere."""
+    g = healpix.ring_info(nside)
+    F = np.zeros((len(g["z"]), lmax + 1), dtype=np.complex128)
+    for m, a in cols.items():
+        F[:, int(m)] = lambda_m(lmax, int(m), g["z"]).T @ np.asarray(a, dtype=np.complex128)
+    return ring_synthesis(F, nside, lmax)
+
+
 def alm_dot(a, b, lmax):
     """Real inner product of two real-field alm sets:
     sum_l [a_l0 b_l0 + 2 Re sum_{m>0} a_lm conj(b_lm)] (= sum over m=-l..l)."""

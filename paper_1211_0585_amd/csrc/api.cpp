@@ -653,7 +653,7 @@ void task_offsets(const TaskDev* tasks, const std::vector<const Geometry*>& geos
           acc += (int64_t)(ct == 1 ? g.n_a128 : g.n_a256) * ((2 * nm + 16 * ct - 1) / (16 * ct));
           break;
         }
-        case 3: acc += g.lmax + 1; break;
+        case 3: acc += (g.rows_total * nm + COEFF_THREADS - 1) / COEFF_THREADS; break;
         default: acc += (int64_t)g.n_s64 * ((2 * nm + 16 * tune.syn_nct - 1) / (16 * tune.syn_nct));
       }
     }

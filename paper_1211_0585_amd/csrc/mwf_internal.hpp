@@ -165,6 +165,9 @@ hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items
                                          const SynthArgs& a, hipStream_t s);
 
 // Matrix-core (FP32 / BF16x3) Legendre phase for batches stored in float.
+// Threads per workgroup of the matrix-core coefficient kernel (one element each).
+constexpr int COEFF_THREADS = 256;
+
 struct MfmaArgs {
   int32_t mode;             // SynthMode of the coefficient step
   int32_t nmaps;

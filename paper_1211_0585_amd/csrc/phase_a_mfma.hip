@@ -387,52 +387,55 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
 // ------------------------------------------------------------------ coefficients
 // Sum the analysis blocks (FP64), scale by C_l, apply the filter, emit the alm and
 // the synthesis coefficients b = C_l s_lm in the layout [padded row][map][re/im].
-__device__ __forceinline__ void coeff_body(const PlanDev& P, const MfmaArgs& a, const int m) {
-  const int lmax = P.lmax;
-  const int nl = lmax - m + 1;
-  const int64_t row = alm_index(lmax, m, m);
-  const int64_t roff = P.row_off[m];
-  const double* __restrict__ Crow = P.C + roff;
-  const double lam_t_o_all = a.lambda * P.tau * P.omega;
-  const int nb = (P.n_active[m] + a.ana_rb - 1) / a.ana_rb;
+// One thread per element e = r nmaps + map over the padded rows r of every m
+// (rows r = row_off[m] + i, i < lmax - m + 1 + ROW_PAD; padding rows get zeros).
+__device__ __forceinline__ void coeff_elem(const PlanDev& P, const MfmaArgs& a, const int64_t e) {
   const int nm = a.nmaps;
-  for (int e = threadIdx.x; e < (nl + ROW_PAD) * nm; e += blockDim.x) {
-    const int i = e / nm, map = e - i * nm;
-    const double lam_t_o = a.slots ? a.slots[map].lam_t_o : lam_t_o_all;
-    const double* __restrict__ cl_row = P.cl + (a.slots ? map * a.cl_stride : 0);
-    double br = 0.0, bi = 0.0;
-    if (i < nl) {
-      double sr, si;
-      if (a.mode == SY_FROM_ALM) {
-        const float2 v = a.alm_in[(size_t)map * P.nalm + row + i];
-        sr = v.x;
-        si = (m == 0) ? 0.0 : v.y;
-      } else {
-        sr = si = 0.0;
-        for (int k = 0; k < nb; ++k) {
-          const float* pk = a.partial + (((size_t)k * P.nalm + row + i) * nm + map) * 2;
-          sr += pk[0];
-          si += pk[1];
-        }
-        sr *= Crow[i];
-        si *= Crow[i];
-        if (a.mode == SY_FROM_PARTIAL) {
-          const double cl = cl_row[m + i];
-          const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
-          sr *= f;
-          si *= f;
-        }
+  const int64_t r = e / nm;
+  const int map = (int)(e - r * nm);
+  const int lmax = P.lmax;
+  // row_off[m] = m (2 (lmax + ROW_PAD) + 3 - m) / 2: invert, then settle on the table
+  const double B = 2.0 * (lmax + ROW_PAD) + 3.0;
+  int m = (int)(0.5 * (B - sqrt(fmax(B * B - 8.0 * (double)r, 0.0))));
+  m = max(0, min(m, lmax));
+  while (m < lmax && P.row_off[m + 1] <= r) ++m;
+  while (m > 0 && P.row_off[m] > r) --m;
+  const int64_t roff = P.row_off[m];
+  const int i = (int)(r - roff);
+  const int nl = lmax - m + 1;
+  double br = 0.0, bi = 0.0;
+  if (i < nl) {
+    const int64_t row = alm_index(lmax, m, m);
+    const double c = P.C[roff + i];
+    double sr, si;
+    if (a.mode == SY_FROM_ALM) {
+      const float2 v = a.alm_in[(size_t)map * P.nalm + row + i];
+      sr = v.x;
+      si = (m == 0) ? 0.0 : v.y;
+    } else {
+      const int nb = (P.n_active[m] + a.ana_rb - 1) / a.ana_rb;
+      sr = si = 0.0;
+      for (int k = 0; k < nb; ++k) {
+        const float2 pk = *reinterpret_cast<const float2*>(a.partial + (((size_t)k * P.nalm + row + i) * nm + map) * 2);
+        sr += pk.x;
+        si += pk.y;
       }
-      if (a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = make_float2((float)sr, (float)si);
-      br = sr * Crow[i];
-      bi = si * Crow[i];
+      sr *= c;
+      si *= c;
+      if (a.mode == SY_FROM_PARTIAL) {
+        const double lam_t_o = a.slots ? a.slots[map].lam_t_o : a.lambda * P.tau * P.omega;
+        const double cl = (P.cl + (a.slots ? map * a.cl_stride : 0))[m + i];
+        const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
+        sr *= f;
+        si *= f;
+      }
     }
-    if (a.mode != SY_ALM_ONLY) {
-      float* b = a.bcoef + ((size_t)(roff + i) * nm + map) * 2;
-      b[0] = (float)br;
-      b[1] = (float)bi;
-    }
+    if (a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = make_float2((float)sr, (float)si);
+    br = sr * c;
+    bi = si * c;
   }
+  if (a.mode != SY_ALM_ONLY)
+    *reinterpret_cast<float2*>(a.bcoef + ((size_t)r * nm + map) * 2) = make_float2((float)br, (float)bi);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -448,7 +451,10 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
   synthesis_body<NP, NCT>(P, a, items[blockIdx.x], blockIdx.y);
 }
 
-__global__ void mfma_coeff_kernel(PlanDev P, MfmaArgs a) { coeff_body(P, a, blockIdx.x); }
+__global__ void __launch_bounds__(COEFF_THREADS) mfma_coeff_kernel(PlanDev P, MfmaArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * COEFF_THREADS + threadIdx.x;
+  if (e < P.rows_total * a.nmaps) coeff_elem(P, a, e);
+}
 
 // Task groups: block b belongs to the task t with offs[t] <= b < offs[t + 1].
 __device__ __forceinline__ int find_task(const int64_t* __restrict__ offs, int ntasks, int64_t b) {
@@ -499,11 +505,12 @@ __global__ void __launch_bounds__(64) group_synthesis_kernel(const TaskDev* __re
   synthesis_body<NP, NCT>(T.P, task_args(T, ana_rb), T.items_s64[local / ncg], (int)(local % ncg));
 }
 
-__global__ void group_coeff_kernel(const TaskDev* __restrict__ tasks, const int64_t* __restrict__ offs,
+__global__ void __launch_bounds__(COEFF_THREADS) group_coeff_kernel(const TaskDev* __restrict__ tasks, const int64_t* __restrict__ offs,
                                    int ntasks, int ana_rb) {
   const int t = find_task(offs, ntasks, blockIdx.x);
   const TaskDev& T = tasks[t];
-  coeff_body(T.P, task_args(T, ana_rb), (int)(blockIdx.x - offs[t]));
+  const int64_t e = (blockIdx.x - offs[t]) * COEFF_THREADS + threadIdx.x;
+  if (e < T.P.rows_total * T.nmaps) coeff_elem(T.P, task_args(T, ana_rb), e);
 }
 
 template <int NP>
@@ -566,7 +573,9 @@ hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nit
 }
 
 hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(mfma_coeff_kernel, dim3(P.lmax + 1), dim3(256), 0, s, P, a);
+  const int64_t n = P.rows_total * a.nmaps;
+  hipLaunchKernelGGL(mfma_coeff_kernel, dim3((unsigned)((n + COEFF_THREADS - 1) / COEFF_THREADS)),
+                     dim3(COEFF_THREADS), 0, s, P, a);
   return hipGetLastError();
 }
 
@@ -586,7 +595,8 @@ hipError_t launch_group_analysis(const GroupLaunch& g, int mode, int ct, hipStre
 
 hipError_t launch_group_coeff(const GroupLaunch& g, int ana_rb, hipStream_t s) {
   if (g.nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(group_coeff_kernel, dim3(g.nblocks), dim3(256), 0, s, g.tasks, g.offs, g.ntasks, ana_rb);
+  hipLaunchKernelGGL(group_coeff_kernel, dim3(g.nblocks), dim3(COEFF_THREADS), 0, s, g.tasks, g.offs, g.ntasks,
+                     ana_rb);
   return hipGetLastError();
 }
 

@@ -97,10 +97,20 @@ def disc_holes(theta, phi, ndisc, radius_deg, model_seed):
     cphi = g.uniform(0.0, 2.0 * np.pi, ndisc)
     centres = unit_vectors(np.arccos(cz), cphi)
     v = unit_vectors(theta, phi)
-    cosr = np.cos(np.radians(radius_deg))
+    r = np.radians(radius_deg)
+    cosr = np.cos(r)
     hole = np.zeros(theta.size, dtype=bool)
-    for c in centres:
-        hole |= (v @ c) > cosr
+    if np.all(np.diff(theta) >= 0):
+        # RING order sorts pixels by colatitude: only the band |theta - theta_c| <= r
+        # (plus a margin far above rounding) can lie inside a disc
+        ctheta = np.arccos(cz)
+        lo = np.searchsorted(theta, ctheta - r - 1e-6, side="left")
+        hi = np.searchsorted(theta, ctheta + r + 1e-6, side="right")
+        for c, a, b in zip(centres, lo, hi):
+            hole[a:b] |= (v[a:b] @ c) > cosr
+    else:
+        for c in centres:
+            hole |= (v @ c) > cosr
     return hole
 
 

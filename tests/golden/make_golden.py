@@ -3,8 +3,10 @@
 Calls only the FP64 oracle and the seeded input generator: the satellite-scale
 case (seed 0, model seed 0), d = oracle synthesis of the drawn signal + noise,
 then the oracle messenger solve for the first 2 sweeps and for the full
-80-sweep schedule. Stores sampled outputs (seeded pixel and alm indices), the
-norms of the full outputs and their projections on seeded random vectors.
+80-sweep schedule. Stores the norm, first entries and seeded random projections
+of d (so a test can check an input it builds itself), sampled outputs (seeded
+pixel and alm indices), the norms of the full outputs and their projections on
+seeded random vectors.
 
 Run from the repository root:  python tests/golden/make_golden.py
 (about an hour on 8 CPU cores).
@@ -45,7 +47,8 @@ def main():
     theta, phi = healpix.pixel_angles(NSIDE)
     c = synth.satellite_case(theta, phi, LMAX, seed=0)
     d = sht.alm2map(c["signal_alm"], NSIDE, LMAX) + c["noise"]
-    store = {"d_norm": np.linalg.norm(d), "d_head": d[:64].copy()}
+    store = {"d_norm": np.linalg.norm(d), "d_head": d[:64].copy(),
+             "d_proj": np.random.default_rng(77).standard_normal((4, d.size)) @ d}
     print(f"inputs ready ({time.time() - t0:.0f} s)", flush=True)
     sched = c["schedule"]
     s2, a2 = messenger.solve(d, c["ninv"], c["cl"], sched[:2], NSIDE, LMAX)

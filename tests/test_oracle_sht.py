@@ -108,3 +108,46 @@ def test_analysis_inverts_synthesis_approximately():
     back = sht.map2alm(sht.alm2map(a, nside, lmax), nside, lmax)
     rel = np.linalg.norm(back - a) / np.linalg.norm(a)
     assert 1e-6 < rel < 0.05
+
+
+def test_column_analysis_closed_form():
+    """map2alm_columns (used for spot checks of large transforms) against the
+    definition written with closed-form Y_lm (sympy), l <= 4: a_lm = Omega sum_p
+    conj(Y_lm(theta_p, phi_p)) f_p."""
+    nside, lmax = 4, 4
+    theta, phi = healpix.pixel_angles(nside)
+    f = np.random.default_rng(11).standard_normal(theta.size)
+    cols = sht.map2alm_columns(f, nside, lmax, [0, 1, 2, 4])
+    th, ph = sympy.symbols("theta phi", real=True)
+    omega = 4 * np.pi / theta.size
+    for m, got in cols.items():
+        for l in range(m, lmax + 1):
+            y = sympy.lambdify((th, ph), sympy.Ynm(l, m, th, ph).expand(func=True), "numpy")
+            yv = np.asarray(y(theta, phi), dtype=np.complex128) * np.ones_like(theta)
+            want = omega * np.sum(np.conj(yv) * f)
+            assert abs(got[l - m] - want) < 1e-13, (l, m)
+
+
+def test_column_transforms_match_full_transforms():
+    """The column-restricted pair equals the full pair on the same columns, and
+    keeps the exact adjointness: Omega <f, Y a> = <Omega Y^dagger f, a>."""
+    nside, lmax = 8, 20
+    rs = np.random.default_rng(12)
+    f = rs.standard_normal(healpix.npix(nside))
+    ms = [0, 3, 9, 20]
+    full = sht.map2alm(f, nside, lmax)
+    cols = sht.map2alm_columns(f, nside, lmax, ms)
+    for m in ms:
+        i0 = alm_index(lmax, m, m)
+        assert np.allclose(cols[m], full[i0:i0 + lmax - m + 1], rtol=0, atol=1e-13)
+    a = {m: rs.standard_normal(lmax - m + 1) + 1j * rs.standard_normal(lmax - m + 1) for m in ms}
+    a[0] = a[0].real
+    packed = np.zeros(n_alm(lmax), dtype=np.complex128)
+    for m in ms:
+        i0 = alm_index(lmax, m, m)
+        packed[i0:i0 + lmax - m + 1] = a[m]
+    got = sht.alm2map_columns(a, nside, lmax)
+    assert np.allclose(got, sht.alm2map(packed, nside, lmax), rtol=0, atol=1e-12)
+    lhs = healpix.pixel_area(nside) * np.dot(f, got)
+    rhs = sum((1.0 if m == 0 else 2.0) * np.sum(cols[m] * np.conj(a[m])).real for m in ms)
+    assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs))
