@@ -19,9 +19,12 @@
 // ring sum (analysis) or folded into s_lm (synthesis).
 //
 // The sectoral seed lambda_mm = norm_m sin^m(theta) underflows FP64 near the
-// poles: every value carries an integer scale s (value = v 2^(-512 s)); while
-// s > 0 the value is negligible (< 2^-448) and is left out of the sums. A wave
-// runs a cheaper loop without scale checks once none of its rings is scaled.
+// poles: every value carries an integer scale s (value = v 2^(-512 s)). The scale
+// is checked once per chunk of l (|v| > 2^64 with s > 0: v *= 2^-512, s -= 1);
+// a ring whose scale is still positive at the start of a chunk contributes
+// nothing in that chunk (its values are below 2^-448 times the growth of one
+// chunk, far under FP64 resolution of the sums). The recurrence alternates
+// between two registers, so a step is one multiply and one FMA and no moves.
 //
 // Each work item is (m, block of 64 R ring pairs) handled by one wavefront; a
 // lane owns R ring pairs. The analysis reduces over lanes through LDS once per
@@ -97,16 +100,21 @@ __device__ __forceinline__ void init_rings(const PlanDev& P, int m, int blk, int
   }
 }
 
+// Once per chunk: bring large scaled values back by 2^-512. Returns a bit mask of
+// the rings whose scale reached zero in this call.
 template <int R>
-__device__ __forceinline__ void rescale_check(RingState<R>& st) {
+__device__ __forceinline__ int rescale_chunk(RingState<R>& st) {
+  int woke = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (st.sc[r] > 0 && fabs(st.mu1[r]) > BIG_THRESH) {
+    if (st.sc[r] > 0 && fmax(fabs(st.mu1[r]), fabs(st.mu2[r])) > BIG_THRESH) {
       st.mu1[r] *= RESCALE;
       st.mu2[r] *= RESCALE;
       st.sc[r] -= 1;
+      if (st.sc[r] == 0) woke |= 1 << r;
     }
   }
+  return woke;
 }
 
 template <int R>
@@ -125,11 +133,12 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
 
   RingState<R> st;
   init_rings<R>(P, m, blk, lane, nact, st);
+  // S/D of each ring, zero while the ring's values are still scaled
   double Sre[R], Sim[R], Dre[R], Dim[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int q = blk * (LANES * R) + r * LANES + lane;
-    if (q < nact) {
+    if (q < nact && st.sc[r] == 0) {
       const double4 sd = *reinterpret_cast<const double4*>(Gm + (size_t)q * pstride);
       Sre[r] = sd.x;
       Sim[r] = sd.y;
@@ -147,50 +156,19 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
     double are[CHUNK], aim[CHUNK];
 #pragma unroll
     for (int j = 0; j < CHUNK; ++j) are[j] = aim[j] = 0.0;
-    int anysc = 0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) anysc |= st.sc[r];
     const double* Ac = Arow + (l0 - m);
-    if (!wave_any(anysc)) {
 #pragma unroll
-      for (int j = 0; j < CHUNK; ++j) {
-        const double A = Ac[j];
+    for (int j = 0; j < CHUNK; j += 2) {
+      const double A0 = Ac[j], A1 = Ac[j + 1];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
-          st.mu2[r] = st.mu1[r];
-          st.mu1[r] = mu;
-          if (j & 1) {
-            are[j] = fma(mu, Dre[r], are[j]);
-            aim[j] = fma(mu, Dim[r], aim[j]);
-          } else {
-            are[j] = fma(mu, Sre[r], are[j]);
-            aim[j] = fma(mu, Sim[r], aim[j]);
-          }
-        }
-      }
-    } else {
-      double cf[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) cf[r] = st.sc[r] == 0 ? 1.0 : 0.0;
-#pragma unroll
-      for (int j = 0; j < CHUNK; ++j) {
-        const double A = Ac[j];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double mu = fma(A * st.z[r], st.mu1[r], -st.mu2[r]);
-          st.mu2[r] = st.mu1[r];
-          st.mu1[r] = mu;
-          const double me = mu * cf[r];
-          if (j & 1) {
-            are[j] = fma(me, Dre[r], are[j]);
-            aim[j] = fma(me, Dim[r], aim[j]);
-          } else {
-            are[j] = fma(me, Sre[r], are[j]);
-            aim[j] = fma(me, Sim[r], aim[j]);
-          }
-        }
-        if ((j & 3) == 3) rescale_check<R>(st);
+      for (int r = 0; r < R; ++r) {
+        // mu2 <- mu_l (l - m even), then mu1 <- mu_{l+1} (odd)
+        st.mu2[r] = fma(A0 * st.z[r], st.mu1[r], -st.mu2[r]);
+        are[j] = fma(st.mu2[r], Sre[r], are[j]);
+        aim[j] = fma(st.mu2[r], Sim[r], aim[j]);
+        st.mu1[r] = fma(A1 * st.z[r], st.mu2[r], -st.mu1[r]);
+        are[j + 1] = fma(st.mu1[r], Dre[r], are[j + 1]);
+        aim[j + 1] = fma(st.mu1[r], Dim[r], aim[j + 1]);
       }
     }
     // reduce the 32 values over the 64 lanes through LDS
@@ -211,6 +189,22 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
       if (l <= lmax) out[2 * (row + (l - m)) + (v & 1)] = sum;
     }
     __syncthreads();
+    int anysc = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) anysc |= st.sc[r];
+    const int woke = wave_any(anysc) ? rescale_chunk<R>(st) : 0;
+    if (woke) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (woke & (1 << r)) {
+          const int q = blk * (LANES * R) + r * LANES + lane;
+          const double4 sd = *reinterpret_cast<const double4*>(Gm + (size_t)q * pstride);
+          Sre[r] = sd.x;
+          Sim[r] = sd.y;
+          Dre[r] = sd.z;
+          Dim[r] = sd.w;
+        }
+    }
   }
 }
 
@@ -289,48 +283,27 @@ __global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
       A[j] = Arow[l0 - m + j];
       b[j] = brow[l0 - m + j];
     }
-    int anysc = 0;
+    int scaled = 0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) anysc |= st.sc[r];
-    if (!wave_any(anysc)) {
+    for (int r = 0; r < R; ++r) scaled |= (st.sc[r] != 0) << r;
 #pragma unroll
-      for (int j = 0; j < SCH; ++j) {
+    for (int j = 0; j < SCH; j += 2) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double mu = fma(A[j] * st.z[r], st.mu1[r], -st.mu2[r]);
-          st.mu2[r] = st.mu1[r];
-          st.mu1[r] = mu;
-          if (j & 1) {
-            Ore[r] = fma(mu, b[j].x, Ore[r]);
-            Oim[r] = fma(mu, b[j].y, Oim[r]);
-          } else {
-            Ere[r] = fma(mu, b[j].x, Ere[r]);
-            Eim[r] = fma(mu, b[j].y, Eim[r]);
-          }
-        }
+      for (int r = 0; r < R; ++r) {
+        st.mu2[r] = fma(A[j] * st.z[r], st.mu1[r], -st.mu2[r]);          // l - m even
+        Ere[r] = fma(st.mu2[r], b[j].x, Ere[r]);
+        Eim[r] = fma(st.mu2[r], b[j].y, Eim[r]);
+        st.mu1[r] = fma(A[j + 1] * st.z[r], st.mu2[r], -st.mu1[r]);      // odd
+        Ore[r] = fma(st.mu1[r], b[j + 1].x, Ore[r]);
+        Oim[r] = fma(st.mu1[r], b[j + 1].y, Oim[r]);
       }
-    } else {
-      double cf[R];
+    }
+    // a ring still scaled at the chunk start has contributed nothing so far: clear it
+    if (wave_any(scaled)) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) cf[r] = st.sc[r] == 0 ? 1.0 : 0.0;
-#pragma unroll
-      for (int j = 0; j < SCH; ++j) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double mu = fma(A[j] * st.z[r], st.mu1[r], -st.mu2[r]);
-          st.mu2[r] = st.mu1[r];
-          st.mu1[r] = mu;
-          const double me = mu * cf[r];
-          if (j & 1) {
-            Ore[r] = fma(me, b[j].x, Ore[r]);
-            Oim[r] = fma(me, b[j].y, Oim[r]);
-          } else {
-            Ere[r] = fma(me, b[j].x, Ere[r]);
-            Eim[r] = fma(me, b[j].y, Eim[r]);
-          }
-        }
-        if ((j & 3) == 3) rescale_check<R>(st);
-      }
+      for (int r = 0; r < R; ++r)
+        if (scaled & (1 << r)) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
+      rescale_chunk<R>(st);
     }
   }
 
