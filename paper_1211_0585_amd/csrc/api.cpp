@@ -203,10 +203,29 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   const Geometry& g = *p->geo;
   // With few maps one launch over all ring pairs fills the GPU better than two
   // back-to-back launches split by transform length.
-  const RingClass none{nullptr, 0, 4};
-  const bool split = nmaps >= RING_SPLIT_MAPS;
-  TIMED(0, MWF_HIP(launch_phase_b(p->dev, a, split ? g.ring_small : none, split ? g.ring_large : g.ring_all,
-                                  p->dtype != WF_F64, s)));
+  // with few maps, one launch per transform kind fills the GPU better than also
+  // splitting off the short transforms; the two kinds then run side by side (the
+  // Bluestein class on the plan's second stream), since neither alone fills it
+  const int split = nmaps >= RING_SPLIT_MAPS ? 1 : 0;
+  const RingClass* cls = g.ring_cls[split];
+  const bool fp32 = p->dtype != WF_F64;
+  if (split || cls[0].count == 0 || cls[1].count == 0) {
+    TIMED(0, MWF_HIP(launch_phase_b(p->dev, a, cls, fp32, s)));
+    return WF_OK;
+  }
+  if (!p->aux) {
+    MWF_HIP(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+    MWF_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    MWF_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  }
+  TIMED(0, {
+    MWF_HIP(hipEventRecord(p->ev_fork, s));
+    MWF_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
+    MWF_HIP(launch_phase_b_class(p->dev, a, cls[0], 0, fp32, p->aux));
+    MWF_HIP(launch_phase_b_class(p->dev, a, cls[1], 1, fp32, s));
+    MWF_HIP(hipEventRecord(p->ev_join, p->aux));
+    MWF_HIP(hipStreamWaitEvent(s, p->ev_join, 0));
+  });
   return WF_OK;
 }
 
@@ -628,32 +647,30 @@ namespace mwf {
 // get no blocks in the three Legendre phases. lds receives the dynamic LDS bytes
 // of the two ring launches.
 void task_offsets(const TaskDev* tasks, const std::vector<const Geometry*>& geos, const Tuning& tune,
-                  std::vector<int64_t>& offs, int64_t* nblocks, size_t* lds, const std::vector<char>* gemm) {
+                  std::vector<int64_t>& offs, int64_t* nblocks, int* fft_len, const std::vector<char>* gemm) {
   const int nt = (int)geos.size();
   offs.assign(NPHASE * (size_t)(nt + 1), 0);
-  lds[0] = lds[1] = 0;
+  for (int c = 0; c < NRING_CLASSES; ++c) fft_len[c] = 4;
   for (int ph = 0; ph < NPHASE; ++ph) {
     int64_t acc = 0;
     for (int t = 0; t < nt; ++t) {
       offs[ph * (nt + 1) + t] = acc;
       const Geometry& g = *geos[t];
       const int nm = tasks[t].nmaps;
-      if (ph >= 2 && gemm && !(*gemm)[t]) continue;   // ring phase only for this task
-      switch (ph) {
-        case 0:
-        case 1:
-          acc += (int64_t)tasks[t].ring_n[ph] * nm;
-          if (tasks[t].ring_n[ph]) {
-            const RingClass& rc = (ph == 1) ? g.ring_small : (tasks[t].ring_n[1] ? g.ring_large : g.ring_all);
-            lds[ph] = std::max(lds[ph], (size_t)rc.fft_len * sizeof(float2));
-          }
-          break;
-        case 2: {
+      if (ph < NRING_CLASSES) {
+        acc += (int64_t)tasks[t].ring_n[ph] * nm;
+        const int split = nm >= RING_SPLIT_MAPS ? 1 : 0;
+        if (tasks[t].ring_n[ph]) fft_len[ph] = std::max(fft_len[ph], g.ring_cls[split][ph].fft_len);
+        continue;
+      }
+      if (gemm && !(*gemm)[t]) continue;   // ring phase only for this task
+      switch (ph - NRING_CLASSES) {
+        case 0: {
           const int ct = tune.ana_ct;
           acc += (int64_t)(ct == 1 ? g.n_a128 : g.n_a256) * ((2 * nm + 16 * ct - 1) / (16 * ct));
           break;
         }
-        case 3: acc += (g.rows_total * nm + COEFF_THREADS - 1) / COEFF_THREADS; break;
+        case 1: acc += (g.rows_total * nm + COEFF_THREADS - 1) / COEFF_THREADS; break;
         default: acc += (int64_t)g.n_s64 * ((2 * nm + 16 * tune.syn_nct - 1) / (16 * tune.syn_nct));
       }
     }
@@ -683,41 +700,39 @@ TaskDev make_task(wf_plan_s* p, int nmaps, int pb_mode, int sy_mode, double lam,
   t.items_a128 = g.items_a128;
   t.items_a256 = g.items_a256;
   t.items_s64 = g.items_s64;
-  // same ring classes as a plan's own launches: split by transform length from 4 maps on
-  if (nmaps >= RING_SPLIT_MAPS) {
-    t.ring_q[0] = g.ring_large.q;
-    t.ring_n[0] = g.ring_large.count;
-    t.ring_q[1] = g.ring_small.q;
-    t.ring_n[1] = g.ring_small.count;
-  } else {
-    t.ring_q[0] = g.ring_all.q;
-    t.ring_n[0] = g.ring_all.count;
+  // the same ring classes as a plan's own launches
+  const int split = nmaps >= RING_SPLIT_MAPS ? 1 : 0;
+  for (int c = 0; c < NRING_CLASSES; ++c) {
+    t.ring_q[c] = g.ring_cls[split][c].q;
+    t.ring_n[c] = g.ring_cls[split][c].count;
   }
   return t;
 }
 
 // One step of a task array already on the device: the two ring launches, then
 // (unless synth_only) analysis, coefficients and synthesis, one launch each.
-int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const size_t* lds,
+int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const int* fft_len,
                    int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s) {
   const int stride = ntasks + 1;
   GroupLaunch g{d_tasks, d_offs, ntasks, 0, nblocks[0]};
   TIMED(0, {
-    MWF_HIP(launch_group_phase_b(g, 0, lds[0], s));
-    g.offs = d_offs + stride;
-    g.nblocks = nblocks[1];
-    MWF_HIP(launch_group_phase_b(g, 1, lds[1], s));
+    for (int c = 0; c < NRING_CLASSES; ++c) {
+      g.offs = d_offs + c * stride;
+      g.nblocks = nblocks[c];
+      MWF_HIP(launch_group_phase_b(g, c, fft_len[c], s));
+    }
   });
   if (synth_only) return WF_OK;
-  g.offs = d_offs + 2 * stride;
-  g.nblocks = nblocks[2];
+  const int a0 = NRING_CLASSES;
+  g.offs = d_offs + a0 * stride;
+  g.nblocks = nblocks[a0];
   TIMED(1, MWF_HIP(launch_group_analysis(g, dtype, tune.ana_ct, s)));
   TIMED(2, {
-    g.offs = d_offs + 3 * stride;
-    g.nblocks = nblocks[3];
+    g.offs = d_offs + (a0 + 1) * stride;
+    g.nblocks = nblocks[a0 + 1];
     MWF_HIP(launch_group_coeff(g, 128 * tune.ana_ct, s));
-    g.offs = d_offs + 4 * stride;
-    g.nblocks = nblocks[4];
+    g.offs = d_offs + (a0 + 2) * stride;
+    g.nblocks = nblocks[a0 + 2];
     MWF_HIP(launch_group_synthesis(g, dtype, tune.syn_nct, 128 * tune.ana_ct, s));
   });
   return WF_OK;
@@ -798,7 +813,7 @@ int wf_group_solve(wf_group_t gr, const void* const* d, void* const* s_wf, void*
   std::vector<const Geometry*> geos;
   for (int t = 0; t < nt; ++t) geos.push_back(gr->plans[t]->geo.get());
   std::vector<int64_t> offs;
-  task_offsets(host.data(), geos, gr->tune, offs, gr->nblocks, gr->lds, nullptr);
+  task_offsets(host.data(), geos, gr->tune, offs, gr->nblocks, gr->fft_len, nullptr);
   MWF_HIP(hipMemcpy(gr->d_tasks, host.data(), host.size() * sizeof(TaskDev), hipMemcpyHostToDevice));
   MWF_HIP(hipMemcpy(gr->d_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   Timer timer;
@@ -806,7 +821,7 @@ int wf_group_solve(wf_group_t gr, const void* const* d, void* const* s_wf, void*
   timer.s = s;
   TimerScope scope(&timer);
   for (int k = 0; k <= nsweeps; ++k)
-    if ((rc = run_group_step(gr->d_tasks + (size_t)k * nt, gr->d_offs, gr->nblocks, gr->lds, nt, gr->dtype,
+    if ((rc = run_group_step(gr->d_tasks + (size_t)k * nt, gr->d_offs, gr->nblocks, gr->fft_len, nt, gr->dtype,
                              gr->tune, k == nsweeps, s)))
       return rc;
   if (stats) {

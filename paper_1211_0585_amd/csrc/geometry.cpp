@@ -186,27 +186,29 @@ int build_geometry(Geometry& g) {
   if ((rc = M.upload(&g.chirp32, to32(chirp)))) return rc;
   if ((rc = M.upload(&g.blue32, to32(blue)))) return rc;
 
-  // ---- ring classes by transform length
-  std::vector<int32_t> qs_small, qs_large, qs_all(g.npairs);
-  int len_small = 4, len_large = 4;
-  for (int q = 0; q < g.npairs; ++q) {
-    qs_all[q] = q;
-    const int L = pairs[q].log2n >= 0 ? pairs[q].nphi : pairs[q].bl_M;
-    if (L <= SMALL_FFT) {
-      qs_small.push_back(q);
-      len_small = std::max(len_small, L);
-    } else {
-      qs_large.push_back(q);
-      len_large = std::max(len_large, L);
+  // ---- ring launch classes by transform kind and length
+  {
+    std::vector<int32_t> lists[2][NRING_CLASSES];
+    int lens[2][NRING_CLASSES];
+    for (auto& row : lens)
+      for (int& l : row) l = 4;
+    for (int q = 0; q < g.npairs; ++q) {
+      const bool blue = pairs[q].log2n < 0;
+      const int L = blue ? pairs[q].bl_M : pairs[q].nphi;
+      const int c0 = blue ? 0 : 1;                    // few maps: by kind only
+      const int c1 = L <= SMALL_FFT ? 2 : c0;          // batched: short ones apart
+      lists[0][c0].push_back(q);
+      lens[0][c0] = std::max(lens[0][c0], L);
+      lists[1][c1].push_back(q);
+      lens[1][c1] = std::max(lens[1][c1], L);
     }
+    for (int k = 0; k < 2; ++k)
+      for (int c = 0; c < NRING_CLASSES; ++c) {
+        int32_t* d = nullptr;
+        if ((rc = M.upload(&d, lists[k][c]))) return rc;
+        g.ring_cls[k][c] = RingClass{d, (int32_t)lists[k][c].size(), lens[k][c]};
+      }
   }
-  int32_t *d_small = nullptr, *d_large = nullptr, *d_all = nullptr;
-  if ((rc = M.upload(&d_small, qs_small))) return rc;
-  if ((rc = M.upload(&d_large, qs_large))) return rc;
-  if ((rc = M.upload(&d_all, qs_all))) return rc;
-  g.ring_small = RingClass{d_small, (int32_t)qs_small.size(), len_small};
-  g.ring_large = RingClass{d_large, (int32_t)qs_large.size(), len_large};
-  g.ring_all = RingClass{d_all, g.npairs, std::max(len_small, len_large)};
 
   // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range
   PlanDev D{};

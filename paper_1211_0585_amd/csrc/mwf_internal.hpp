@@ -134,8 +134,25 @@ struct RingClass {
   int32_t fft_len;
 };
 
-hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,
-                          const RingClass& large, bool fp32, hipStream_t s);
+// Ring launches: class 0 Bluestein rings and class 1 power-of-two rings (512
+// threads each), class 2 transforms of at most 1024 points (one wave per ring
+// pair; used from RING_SPLIT_MAPS maps on, when classes 0 and 1 hold only the
+// longer transforms).
+constexpr int NRING_CLASSES = 3;
+constexpr int RING_SPLIT_MAPS = 4;
+
+// Dynamic LDS of a ring launch: the data of fft_len points plus their twiddles.
+// (At least 8 KiB: short rings stage 512 partial sums of two complex doubles.)
+inline size_t ring_lds_bytes(int fft_len, size_t elem) {
+  const size_t b = (size_t)fft_len * elem + (size_t)(fft_len / 4) * elem;
+  return b < 8192 ? 8192 : b;
+}
+
+// cls: NRING_CLASSES classes, launched in order (empty ones skipped).
+hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass* cls, bool fp32, hipStream_t s);
+// One class alone (cls: its index, which fixes the workgroup size).
+hipError_t launch_phase_b_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, int cls, bool fp32,
+                                hipStream_t s);
 
 // Phase A (m-parallel): Legendre analysis into per-block partial sums.
 hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,
@@ -216,8 +233,8 @@ struct TaskDev {
   const SlotParam* slots;       // per-map parameters (serving lanes) or null
   int64_t q_stride;
   int64_t cl_stride;
-  const int32_t* ring_q[2];     // ring pairs of the 512-thread (0) and one-wave (1) ring launches
-  int32_t ring_n[2];
+  const int32_t* ring_q[NRING_CLASSES];   // ring pairs of each ring launch class
+  int32_t ring_n[NRING_CLASSES];
 };
 
 struct GroupLaunch {
@@ -232,8 +249,8 @@ hipError_t launch_group_analysis(const GroupLaunch& g, int mode, int ct, hipStre
 hipError_t launch_group_coeff(const GroupLaunch& g, int ana_rb, hipStream_t s);
 hipError_t launch_group_synthesis(const GroupLaunch& g, int mode, int nct, int ana_rb, hipStream_t s);
 // Ring phase over (task, ring pair, map) blocks, float storage and arithmetic.
-// cls 0: 512-thread workgroups over TaskDev::ring_q[0]; cls 1: one wave per pair over ring_q[1].
-hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, size_t lds_bytes, hipStream_t s);
+// Ring launch of class cls over TaskDev::ring_q[cls]; fft_len: the longest transform of the class.
+hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, int fft_len, hipStream_t s);
 
 // Plan-time: which ring pairs ever reach a non-negligible lambda_lm (polar skip).
 hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s);

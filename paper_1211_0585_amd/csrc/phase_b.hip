@@ -25,15 +25,21 @@
 // lengths use Bluestein's chirp-z method: chirp, power-of-two FFT of length
 // M >= 2 n - 1, multiply by the plan-time filter spectrum, inverse FFT, chirp.
 // The FFT arithmetic type C is double for FP64 plans and float for plans that
-// store maps and ring coefficients in float. Rings are launched in two classes:
-// transforms of at most 1024 points run one wave per ring pair, longer ones 512
-// threads, so short polar rings do not leave most of a large workgroup idle.
+// store maps and ring coefficients in float. Ring pairs are launched in classes:
+// Bluestein rings and power-of-two rings separately (512 threads each, LDS sized
+// to the class: the Bluestein length is about twice the ring's), and, from 4 maps
+// on, transforms of at most 1024 points one wave per ring pair, so short polar
+// rings do not leave most of a large workgroup idle. Each workgroup stages the
+// twiddles of its ring's transform length in LDS next to the data.
 #include "mwf_internal.hpp"
 
 namespace mwf {
 namespace {
 
-constexpr int PB_MAXB = 4;   // max radix-4 butterflies per thread (L <= 4 * PB_MAXB * threads)
+// Rings of at most FOLD_PARTS points fold their aliases with FOLD_PARTS / n partial
+// sums per bin (see the loading step of phase_b_body).
+constexpr int FOLD_PARTS = 256;
+
 
 template <class C>
 struct CT;
@@ -103,12 +109,12 @@ __device__ __forceinline__ void dft4(V& v0, V& v1, V& v2, V& v3, S sd) {
   v3 = csub(t1, t3);
 }
 
-// In-place Stockham FFT of length L = 2^lg (4 <= L <= 4 PB_MAXB NT) in LDS, run by
+// In-place Stockham FFT of length L = 2^lg (4 <= L <= 4 MAXB NT) in LDS, run by
 // all NT threads of the workgroup; dir = -1: exp(-2 pi i jk/L), +1: exp(+...). Unnormalised. Radix-4 passes,
 // with one radix-2 pass first when lg is odd. tw[t] = exp(-2 pi i t / tw_len),
-// t < tw_len / 2. Every pass loads all butterfly inputs into registers,
+// t < tw_len / 4 (in LDS). Every pass loads all butterfly inputs into registers,
 // synchronises, then writes the outputs, so a single LDS buffer suffices.
-template <class C, int NT>
+template <class C, int NT, int MAXB>
 __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
                                          const typename CT<C>::V* __restrict__ tw, int tw_len) {
   using V = typename CT<C>::V;
@@ -119,11 +125,11 @@ __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
   int rem = lg;
   while (Ns < L) {
     const bool r2 = (rem & 1) != 0;
-    V v[4 * PB_MAXB];
+    V v[4 * MAXB];
     if (!r2) {
       const int nb = L / 4;
 #pragma unroll
-      for (int b = 0; b < PB_MAXB; ++b) {
+      for (int b = 0; b < MAXB; ++b) {
         const int j = tid + b * NT;
         if (j < nb) {
 #pragma unroll
@@ -132,7 +138,7 @@ __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
       }
       __syncthreads();
 #pragma unroll
-      for (int b = 0; b < PB_MAXB; ++b) {
+      for (int b = 0; b < MAXB; ++b) {
         const int j = tid + b * NT;
         if (j < nb) {
           const int k = j & (Ns - 1);
@@ -153,7 +159,7 @@ __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
     } else {
       const int nb = L / 2;
 #pragma unroll
-      for (int b = 0; b < 2 * PB_MAXB; ++b) {
+      for (int b = 0; b < 2 * MAXB; ++b) {
         const int j = tid + b * NT;
         if (j < nb) {
           v[2 * b] = x[j];
@@ -162,7 +168,7 @@ __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
       }
       __syncthreads();
 #pragma unroll
-      for (int b = 0; b < 2 * PB_MAXB; ++b) {
+      for (int b = 0; b < 2 * MAXB; ++b) {
         const int j = tid + b * NT;
         if (j < nb) {
           const int k = j & (Ns - 1);
@@ -184,7 +190,7 @@ __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
 // DFT of any length n of x[0..n) in place (dir = -1 forward, +1 inverse) by
 // Bluestein's method, using the LDS buffer x[0..M), the chirp exp(-i pi j^2/n)
 // (length n) and the filter spectrum H (length M).
-template <class C, int NT>
+template <class C, int NT, int MAXB>
 __device__ void dft_bluestein(typename CT<C>::V* x, int n, int M, int lgM, int dir,
                               const typename CT<C>::V* __restrict__ chirp,
                               const typename CT<C>::V* __restrict__ H,
@@ -201,10 +207,10 @@ __device__ void dft_bluestein(typename CT<C>::V* x, int n, int M, int lgM, int d
     }
   }
   __syncthreads();
-  fft_pow2<C, NT>(x, lgM, -1, tw, tw_len);
+  fft_pow2<C, NT, MAXB>(x, lgM, -1, tw, tw_len);
   for (int k = tid; k < M; k += NT) x[k] = cmul(x[k], H[k]);
   __syncthreads();
-  fft_pow2<C, NT>(x, lgM, +1, tw, tw_len);
+  fft_pow2<C, NT, MAXB>(x, lgM, +1, tw, tw_len);
   const C invM = (C)1 / (C)M;
   for (int k = tid; k < n; k += NT) {
     V v = cmul(x[k], chirp[k]);
@@ -232,14 +238,16 @@ struct Tabs<float> {
   __device__ static const float2* blue(const PlanDev& P) { return P.bluestein32; }
 };
 
-template <class C, int NT>
-__device__ __forceinline__ void ring_dft(typename CT<C>::V* buf, const RingPair& rp, int dir,
-                                         const PlanDev& P) {
+// The ring's transform, with the twiddles of its length L (n, or the Bluestein M)
+// staged in LDS: twl[t] = exp(-2 pi i t / L), t < L / 4.
+template <class C, int NT, int MAXB>
+__device__ __forceinline__ void ring_dft(typename CT<C>::V* buf, const typename CT<C>::V* twl,
+                                         const RingPair& rp, int dir, const PlanDev& P) {
   if (rp.log2n >= 0) {
-    fft_pow2<C, NT>(buf, rp.log2n, dir, Tabs<C>::tw(P), P.tw_len);
+    fft_pow2<C, NT, MAXB>(buf, rp.log2n, dir, twl, rp.nphi);
   } else {
-    dft_bluestein<C, NT>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, Tabs<C>::chirp(P) + rp.chirp_off,
-                         Tabs<C>::blue(P) + rp.bl_off, Tabs<C>::tw(P), P.tw_len);
+    dft_bluestein<C, NT, MAXB>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, Tabs<C>::chirp(P) + rp.chirp_off,
+                               Tabs<C>::blue(P) + rp.bl_off, twl, rp.bl_M);
   }
 }
 
@@ -254,9 +262,9 @@ struct Vec4<float> {
   using type = float4;
 };
 
-template <class T, class C, int NT>
+template <class T, class C, int NT, int MAXB>
 __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs& a, const int q,
-                                             const int map) {
+                                             const int map, const int buf_elems) {
   using V4 = typename Vec4<T>::type;
   using V = typename CT<C>::V;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
@@ -274,54 +282,146 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
   const T* __restrict__ q_tab = static_cast<const T*>(P.q) + (a.slots ? map * a.q_stride : 0);
 
+  // twiddles of this ring's FFT length into LDS, written at the end of the loading
+  // step (after any partial sums there are consumed) and ordered before their first
+  // use by the barrier that closes that step
+  V* twl = buf + buf_elems;
+  auto stage_twiddles = [&]() {
+    const int L = rp.log2n >= 0 ? n : rp.bl_M;
+    const V* __restrict__ twg = Tabs<C>::tw(P);
+    const int stride = P.tw_len / L;
+    for (int t = tid; t < L / 4; t += NT) twl[t] = twg[(size_t)t * stride];
+  };
+
   // ---- ring values into buf (x = north + i south)
   if (mode & PB_SYNTH) {
     const T* __restrict__ Fp = static_cast<const T*>(a.F) + pbase;
     // exp(i k phi0) for k = tid + s * NT, advanced by one complex multiply
     double2 ph = expipi<double>((int64_t)tid * rp.ph_num, n);
     const double2 step = expipi<double>((int64_t)NT * rp.ph_num, n);
-    for (int k = tid; k < n; k += NT) {
-      double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
-      double s = 1.0;                               // sig^t for m = k + t n
-      for (int m = k; m <= lmax; m += n) {          // m >= 0 with m = k (mod n)
-        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-        double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
-        double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
-        if (m == 0) {
-          fn.y = 0.0;
-          fs.y = 0.0;
-        } else {
-          const double2 phm = make_double2(s * ph.x, s * ph.y);
-          fn = cmul(fn, phm);
-          fs = cmul(fs, phm);
+    if (n > FOLD_PARTS) {
+      // the first positive and negative alias of the next bin are loaded while the
+      // current bin is folded (one bin ahead)
+      V4 pos_nx{}, neg_nx{};
+      {
+        const int k = tid, mn = (k == 0) ? n : n - k;
+        if (k < n && k <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k * 4);
+        if (k < n && mn <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn * 4);
+      }
+      for (int k = tid; k < n; k += NT) {
+        const V4 pos0 = pos_nx, neg0 = neg_nx;
+        {
+          const int k1 = k + NT, mn1 = n - k1;
+          if (k1 < n && k1 <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k1 * 4);
+          if (k1 < n && mn1 <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn1 * 4);
         }
-        bn = cadd(bn, fn);
-        bs = cadd(bs, fs);
-        s *= sig;
+        double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+        double s = 1.0;                               // sig^t for m = k + t n
+        for (int m = k; m <= lmax; m += n) {          // m >= 0 with m = k (mod n)
+          const V4 eo = (m == k) ? pos0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+          double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
+          double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
+          if (m == 0) {
+            fn.y = 0.0;
+            fs.y = 0.0;
+          } else {
+            const double2 phm = make_double2(s * ph.x, s * ph.y);
+            fn = cmul(fn, phm);
+            fs = cmul(fs, phm);
+          }
+          bn = cadd(bn, fn);
+          bs = cadd(bs, fs);
+          s *= sig;
+        }
+        // m < 0 terms: |m| = t n - k (t >= 1), exp(i |m| phi0) = sig^t conj(exp(i k phi0))
+        s = sig;
+        const int mn = (k == 0) ? n : n - k;
+        for (int m = mn; m <= lmax; m += n) {
+          const V4 eo = (m == mn) ? neg0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+          const double2 phm = make_double2(s * ph.x, -s * ph.y);
+          const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
+          const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
+          bn = cadd(bn, cconj(fn));
+          bs = cadd(bs, cconj(fs));
+          s *= sig;
+        }
+        buf[k] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
+        ph = cmul(ph, step);
       }
-      // m < 0 terms: |m| = t n - k (t >= 1), exp(i |m| phi0) = sig^t conj(exp(i k phi0))
-      s = sig;
-      for (int m = (k == 0 ? n : n - k); m <= lmax; m += n) {
-        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-        const double2 phm = make_double2(s * ph.x, -s * ph.y);
-        const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
-        const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
-        bn = cadd(bn, cconj(fn));
-        bs = cadd(bs, cconj(fs));
-        s *= sig;
+    } else {
+      // short rings carry many aliases per bin: G partial sums per bin, each over
+      // every G-th alias, spread over the whole workgroup, then added in a fixed order
+      const int G = FOLD_PARTS / n, np = G * n;
+      const double sigG = (G & 1) ? sig : 1.0;
+      double2* part = reinterpret_cast<double2*>(lds_raw);    // [np][N, S]
+      for (int p = tid; p < np; p += NT) {
+        const int k = p % n, g = p / n;
+        const double2 phk = expipi<double>((int64_t)k * rp.ph_num, n);   // exp(i k phi0)
+        double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+        double s = (g & 1) ? sig : 1.0;               // sig^t, t = g + u G
+        for (int m = k + g * n; m <= lmax; m += G * n) {
+          const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+          double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
+          double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
+          if (m == 0) {
+            fn.y = 0.0;
+            fs.y = 0.0;
+          } else {
+            const double2 phm = make_double2(s * phk.x, s * phk.y);
+            fn = cmul(fn, phm);
+            fs = cmul(fs, phm);
+          }
+          bn = cadd(bn, fn);
+          bs = cadd(bs, fs);
+          s *= sigG;
+        }
+        s = ((g + 1) & 1) ? sig : 1.0;               // negative aliases |m| = t n - k, t = 1 + g + u G
+        for (int m = (g + 1) * n - k; m <= lmax; m += G * n) {
+          const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+          const double2 phm = make_double2(s * phk.x, -s * phk.y);
+          const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
+          const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
+          bn = cadd(bn, cconj(fn));
+          bs = cadd(bs, cconj(fs));
+          s *= sigG;
+        }
+        part[2 * p] = bn;
+        part[2 * p + 1] = bs;
       }
-      buf[k] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
-      ph = cmul(ph, step);
+      __syncthreads();
+      constexpr int KB = (FOLD_PARTS + NT - 1) / NT;   // bins per thread
+      V bk[KB];
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int k = tid + b * NT;
+        if (k < n) {
+          double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+          for (int g = 0; g < G; ++g) {
+            bn = cadd(bn, part[2 * (g * n + k)]);
+            bs = cadd(bs, part[2 * (g * n + k) + 1]);
+          }
+          bk[b] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int k = tid + b * NT;
+        if (k < n) buf[k] = bk[b];
+      }
     }
+    stage_twiddles();
     __syncthreads();
-    ring_dft<C, NT>(buf, rp, +1, P);
+    ring_dft<C, NT, MAXB>(buf, twl, rp, +1, P);
   } else if (mode & PB_READ_MAP) {
     const T* src = static_cast<const T*>(a.map_in) + mbase;
     for (int j = tid; j < n; j += NT)
       buf[j] = CT<C>::make((C)src[rp.start_n + j], equator ? (C)0 : (C)src[rp.start_s + j]);
+    stage_twiddles();
     __syncthreads();
   } else {
     for (int j = tid; j < n; j += NT) buf[j] = CT<C>::make(0, 0);
+    stage_twiddles();
     __syncthreads();
   }
 
@@ -330,21 +430,40 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
     const double lam = a.slots ? a.slots[map].lambda : a.lambda;
     const T* __restrict__ d = static_cast<const T*>(a.d) + mbase;
     T* out = static_cast<T*>(a.map_out) + mbase;
+    // d and tau N^-1 of the next pixel pair are loaded while the current one is updated
+    const bool upd = (mode & PB_UPDATE) != 0;
+    T qn_nx{}, dn_nx{}, qs_nx{}, ds_nx{};
+    if (upd && tid < n) {
+      qn_nx = q_tab[rp.start_n + tid];
+      dn_nx = d[rp.start_n + tid];
+      if (!equator) {
+        qs_nx = q_tab[rp.start_s + tid];
+        ds_nx = d[rp.start_s + tid];
+      }
+    }
     for (int j = tid; j < n; j += NT) {
+      const T qn = qn_nx, dn = dn_nx, qs = qs_nx, ds = ds_nx;
+      const int j1 = j + NT;
+      if (upd && j1 < n) {
+        qn_nx = q_tab[rp.start_n + j1];
+        dn_nx = d[rp.start_n + j1];
+        if (!equator) {
+          qs_nx = q_tab[rp.start_s + j1];
+          ds_nx = d[rp.start_s + j1];
+        }
+      }
       const V xv = buf[j];
       double2 x = make_double2((double)xv.x, (double)xv.y);
       if (mode & PB_WRITE_MAP) {
         out[rp.start_n + j] = (T)x.x;
         if (!equator) out[rp.start_s + j] = (T)x.y;
       }
-      if (mode & PB_UPDATE) {
-        const double qn = (double)q_tab[rp.start_n + j];
-        const double wn = lam * qn / (1.0 + (lam - 1.0) * qn);
-        x.x = x.x + wn * ((double)d[rp.start_n + j] - x.x);
+      if (upd) {
+        const double wn = lam * (double)qn / (1.0 + (lam - 1.0) * (double)qn);
+        x.x = x.x + wn * ((double)dn - x.x);
         if (!equator) {
-          const double qs = (double)q_tab[rp.start_s + j];
-          const double ws = lam * qs / (1.0 + (lam - 1.0) * qs);
-          x.y = x.y + ws * ((double)d[rp.start_s + j] - x.y);
+          const double ws = lam * (double)qs / (1.0 + (lam - 1.0) * (double)qs);
+          x.y = x.y + ws * ((double)ds - x.y);
         }
       }
       if (equator) x.y = 0.0;
@@ -355,7 +474,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
 
   // ---- analysis: forward DFT and unfold into S/D per m
   if (mode & PB_ANALYSIS) {
-    ring_dft<C, NT>(buf, rp, -1, P);
+    ring_dft<C, NT, MAXB>(buf, twl, rp, -1, P);
     T* Gp = static_cast<T*>(a.G) + pbase;
     const double half_omega = 0.5 * P.omega;
     double2 ph = expipi<double>(-(int64_t)tid * rp.ph_num, n);          // exp(-i m phi0)
@@ -381,18 +500,19 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   }
 }
 
-template <class T, class C, int NT>
-__global__ void __launch_bounds__(NT, 4) phase_b_kernel(PlanDev P, PhaseBArgs a,
-                                                        const int32_t* __restrict__ qlist) {
-  phase_b_body<T, C, NT>(P, a, qlist[blockIdx.x], blockIdx.y);
+template <class T, class C, int NT, int MAXB>
+__global__ void __launch_bounds__(NT) phase_b_kernel(PlanDev P, PhaseBArgs a, const int32_t* __restrict__ qlist,
+                                                     int buf_elems) {
+  phase_b_body<T, C, NT, MAXB>(P, a, qlist[blockIdx.x], blockIdx.y, buf_elems);
 }
 
 // Task groups (float storage and arithmetic): block b of task t covers entry
-// (b - offs[t]) / nmaps of the task's ring-pair list of this class and map
+// (b - offs[t]) / nmaps of the task's ring-pair list of class CLS and map
 // (b - offs[t]) % nmaps.
-template <int NT, int CLS>
-__global__ void __launch_bounds__(NT, 4) group_phase_b_kernel(const TaskDev* __restrict__ tasks,
-                                                              const int64_t* __restrict__ offs, int ntasks) {
+template <int NT, int CLS, int MAXB>
+__global__ void __launch_bounds__(NT) group_phase_b_kernel(const TaskDev* __restrict__ tasks,
+                                                           const int64_t* __restrict__ offs, int ntasks,
+                                                           int buf_elems) {
   int lo = 0, hi = ntasks - 1;
   const int64_t b = blockIdx.x;
   while (lo < hi) {
@@ -412,57 +532,94 @@ __global__ void __launch_bounds__(NT, 4) group_phase_b_kernel(const TaskDev* __r
   a.map_out = t.map_out;
   a.slots = t.slots;
   a.q_stride = t.q_stride;
-  phase_b_body<float, float, NT>(t.P, a, t.ring_q[CLS][local / t.nmaps], (int)(local % t.nmaps));
+  phase_b_body<float, float, NT, MAXB>(t.P, a, t.ring_q[CLS][local / t.nmaps], (int)(local % t.nmaps), buf_elems);
+}
+
+// Radix-4 butterflies per thread and pass for a transform of fft_len points.
+int maxb_for(int fft_len, int nt) {
+  const int b = (fft_len + 4 * nt - 1) / (4 * nt);
+  return b <= 1 ? 1 : (b <= 2 ? 2 : (b <= 4 ? 4 : 0));
+}
+
+template <class K>
+hipError_t set_lds(K kernel, size_t lds, size_t* attr) {
+  if (lds > *attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    *attr = lds;
+  }
+  return hipSuccess;
+}
+
+template <class T, class C, int NT, int MAXB>
+hipError_t launch_class_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
+  static size_t attr = 0;
+  const size_t lds = ring_lds_bytes(rc.fft_len, sizeof(typename CT<C>::V));
+  if (hipError_t e = set_lds(phase_b_kernel<T, C, NT, MAXB>, lds, &attr)) return e;
+  hipLaunchKernelGGL((phase_b_kernel<T, C, NT, MAXB>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q,
+                     rc.fft_len);
+  return hipGetLastError();
 }
 
 template <class T, class C, int NT>
 hipError_t launch_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
   if (rc.count == 0) return hipSuccess;
-  static size_t attr_bytes = 0;
-  const size_t lds = rc.fft_len * sizeof(typename CT<C>::V);
-  if (lds > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)phase_b_kernel<T, C, NT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_bytes = lds;
+  switch (maxb_for(rc.fft_len, NT)) {
+    case 1: return launch_class_b<T, C, NT, 1>(P, a, rc, s);
+    case 2: return launch_class_b<T, C, NT, 2>(P, a, rc, s);
+    case 4: return launch_class_b<T, C, NT, 4>(P, a, rc, s);
+    default: return hipErrorInvalidValue;
   }
-  hipLaunchKernelGGL((phase_b_kernel<T, C, NT>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q);
-  return hipGetLastError();
 }
 
 template <class T, class C>
-hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,
-                    const RingClass& large, hipStream_t s) {
-  hipError_t e = launch_class<T, C, 512>(P, a, large, s);
-  if (e != hipSuccess) return e;
-  return launch_class<T, C, 64>(P, a, small, s);
+hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, const RingClass* cls, hipStream_t s) {
+  hipError_t e = launch_class<T, C, 512>(P, a, cls[0], s);
+  if (e == hipSuccess) e = launch_class<T, C, 512>(P, a, cls[1], s);
+  if (e == hipSuccess) e = launch_class<T, C, 64>(P, a, cls[2], s);
+  return e;
+}
+
+template <int NT, int CLS, int MAXB>
+hipError_t group_class_b(const GroupLaunch& g, int fft_len, hipStream_t s) {
+  static size_t attr = 0;
+  const size_t lds = ring_lds_bytes(fft_len, sizeof(float2));
+  if (hipError_t e = set_lds(group_phase_b_kernel<NT, CLS, MAXB>, lds, &attr)) return e;
+  hipLaunchKernelGGL((group_phase_b_kernel<NT, CLS, MAXB>), dim3(g.nblocks), dim3(NT), lds, s, g.tasks, g.offs,
+                     g.ntasks, fft_len);
+  return hipGetLastError();
+}
+
+template <int NT, int CLS>
+hipError_t group_class(const GroupLaunch& g, int fft_len, hipStream_t s) {
+  switch (maxb_for(fft_len, NT)) {
+    case 1: return group_class_b<NT, CLS, 1>(g, fft_len, s);
+    case 2: return group_class_b<NT, CLS, 2>(g, fft_len, s);
+    case 4: return group_class_b<NT, CLS, 4>(g, fft_len, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
-template <int NT, int CLS>
-hipError_t group_class(const GroupLaunch& g, size_t lds_bytes, hipStream_t s) {
-  static size_t attr_bytes = 0;
-  if (lds_bytes > attr_bytes) {
-    hipError_t e = hipFuncSetAttribute((const void*)group_phase_b_kernel<NT, CLS>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-    if (e != hipSuccess) return e;
-    attr_bytes = lds_bytes;
-  }
-  hipLaunchKernelGGL((group_phase_b_kernel<NT, CLS>), dim3(g.nblocks), dim3(NT), lds_bytes, s, g.tasks, g.offs,
-                     g.ntasks);
-  return hipGetLastError();
-}
-
-hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, size_t lds_bytes, hipStream_t s) {
+hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, int fft_len, hipStream_t s) {
   if (g.nblocks == 0) return hipSuccess;
-  return cls == 0 ? group_class<512, 0>(g, lds_bytes, s) : group_class<64, 1>(g, lds_bytes, s);
+  switch (cls) {
+    case 0: return group_class<512, 0>(g, fft_len, s);
+    case 1: return group_class<512, 1>(g, fft_len, s);
+    default: return group_class<64, 2>(g, fft_len, s);
+  }
 }
 
-hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& small,
-                          const RingClass& large, bool fp32, hipStream_t s) {
-  return fp32 ? launch_t<float, float>(P, a, small, large, s)
-              : launch_t<double, double>(P, a, small, large, s);
+hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass* cls, bool fp32, hipStream_t s) {
+  return fp32 ? launch_t<float, float>(P, a, cls, s) : launch_t<double, double>(P, a, cls, s);
+}
+
+hipError_t launch_phase_b_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, int cls, bool fp32,
+                                hipStream_t s) {
+  if (cls < 2)
+    return fp32 ? launch_class<float, float, 512>(P, a, rc, s) : launch_class<double, double, 512>(P, a, rc, s);
+  return fp32 ? launch_class<float, float, 64>(P, a, rc, s) : launch_class<double, double, 64>(P, a, rc, s);
 }
 
 }  // namespace mwf

@@ -78,7 +78,9 @@ struct Geometry {
   WorkItem* items_a256 = nullptr;
   WorkItem* items_s64 = nullptr;       // matrix-core synthesis, 64 ring pairs
   int n_ana = 0, n_syn = 0, n_a128 = 0, n_a256 = 0, n_s64 = 0;
-  RingClass ring_small{}, ring_large{}, ring_all{};
+  // ring launch classes: [0] one or few maps (Bluestein, power of two), [1] from
+  // RING_SPLIT_MAPS maps on (long Bluestein, long power of two, short)
+  RingClass ring_cls[2][NRING_CLASSES]{};
   DevMem mem;
 };
 
@@ -110,16 +112,15 @@ struct wf_plan_s;
 namespace mwf {
 
 int plan_alloc(wf_plan_s* p);
-// Phases of a group step and the batch size from which ring pairs are launched
-// in two classes by transform length (as a plan's own ring launches).
-constexpr int NPHASE = 5;
-constexpr int RING_SPLIT_MAPS = 4;
+// Phases of a group step: the ring launch classes, then analysis, coefficients
+// and synthesis.
+constexpr int NPHASE = NRING_CLASSES + 3;
 
 void task_offsets(const TaskDev* tasks, const std::vector<const Geometry*>& geos, const Tuning& tune,
-                  std::vector<int64_t>& offs, int64_t* nblocks, size_t* lds, const std::vector<char>* gemm);
+                  std::vector<int64_t>& offs, int64_t* nblocks, int* fft_len, const std::vector<char>* gemm);
 TaskDev make_task(wf_plan_s* p, int nmaps, int pb_mode, int sy_mode, double lam, const void* d,
                   void* map_out, void* alm_out);
-int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const size_t* lds,
+int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const int* fft_len,
                    int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s);
 size_t plan_buffer_bytes(int nside, int lmax, int dtype, int nmaps);
 size_t geometry_bytes(int nside, int lmax);
@@ -146,6 +147,18 @@ struct wf_plan_s {
   float* bcoef32 = nullptr;            // matrix cores: [rows_total][batch][2]
   mwf::PlanDev dev{};
   mwf::DevMem mem;
+  // second stream for ring classes that run side by side (default priority),
+  // with the fork / join events; created on first use
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  ~wf_plan_s() {
+    if (aux) {
+      hipStreamSynchronize(aux);
+      hipStreamDestroy(aux);
+    }
+    if (ev_fork) hipEventDestroy(ev_fork);
+    if (ev_join) hipEventDestroy(ev_join);
+  }
 };
 
 struct wf_group_s {
@@ -153,7 +166,7 @@ struct wf_group_s {
   std::vector<int32_t> nmaps;
   int dtype = WF_F32;
   mwf::Tuning tune;
-  size_t lds[2] = {0, 0};              // dynamic LDS of the two ring launches
+  int fft_len[mwf::NRING_CLASSES] = {};  // longest transform of each ring launch class
   // per solve: one TaskDev array per step (sweeps + final synthesis)
   mwf::TaskDev* d_tasks = nullptr;
   size_t d_tasks_cap = 0;

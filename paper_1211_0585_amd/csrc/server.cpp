@@ -373,7 +373,7 @@ struct wf_server_s {
       size_t tasks_off, offs_off;
       int ntasks;
       int64_t nblocks[NPHASE];
-      size_t lds[2];
+      int fft_len[NRING_CLASSES];
       Tuning tune;
     };
     std::vector<Launch> launches;
@@ -427,8 +427,8 @@ struct wf_server_s {
       }
       ln.tune = ls[0]->plan->tune;
       std::vector<int64_t> offs;
-      task_offsets(reinterpret_cast<const TaskDev*>(hb + ln.tasks_off), geos, ln.tune, offs, ln.nblocks, ln.lds,
-                   &gemm);
+      task_offsets(reinterpret_cast<const TaskDev*>(hb + ln.tasks_off), geos, ln.tune, offs, ln.nblocks,
+                   ln.fft_len, &gemm);
       std::memcpy(hb + ln.offs_off, offs.data(), offs.size() * sizeof(int64_t));
       launches.push_back(ln);
     }
@@ -438,7 +438,7 @@ struct wf_server_s {
     for (const Launch& ln : launches) {
       const auto* tasks = reinterpret_cast<const TaskDev*>(db + ln.tasks_off);
       const auto* offs = reinterpret_cast<const int64_t*>(db + ln.offs_off);
-      if (int rc = run_group_step(tasks, offs, ln.nblocks, ln.lds, ln.ntasks, ln.dtype, ln.tune, false, stream))
+      if (int rc = run_group_step(tasks, offs, ln.nblocks, ln.fft_len, ln.ntasks, ln.dtype, ln.tune, false, stream))
         return rc;
     }
     for (Job* j : finals) {
