@@ -236,6 +236,7 @@ def run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside,
         if d is None:
             d = plan.alm2map(torch.from_numpy(alms).to(dev)) + torch.from_numpy(noise).to(dev)
             torch.cuda.synchronize()
+        tile = plan.autotune(B)          # also cached for the timing plan below
         if W:
             plan.solve(d, lams(W), want_alm=False)
         torch.cuda.synchronize()
@@ -257,6 +258,7 @@ def run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside,
         useful = CON_FLOPS * units * B                   # per Legendre launch (one direction)
         executed = useful * MFMA_PRODUCTS[name]
         res = {"map_iters_per_s": mit, "ms_per_sweep": 1e3 * el / K,
+               "tile": {"analysis_column_tiles": tile[0], "synthesis_column_tiles": tile[1]},
                "ms_legendre_analysis": ana, "ms_legendre_synthesis": syn, "ms_ring_fft_update": ring,
                "useful_tflops_analysis": useful / (ana * 1e-3) / 1e12,
                "executed_mfma_tflops_analysis": executed / (ana * 1e-3) / 1e12,

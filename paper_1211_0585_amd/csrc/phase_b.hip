@@ -196,28 +196,54 @@ __device__ void dft_bluestein(typename CT<C>::V* x, int n, int M, int lgM, int d
                               const typename CT<C>::V* __restrict__ H,
                               const typename CT<C>::V* __restrict__ tw, int tw_len) {
   using V = typename CT<C>::V;
+  constexpr int NK = 4 * MAXB;     // M <= 4 MAXB NT
+  constexpr int NJ = 2 * MAXB;     // n <= M / 2
   const int tid = threadIdx.x;
-  for (int j = tid; j < M; j += NT) {
-    if (j < n) {
-      V v = x[j];
-      if (dir > 0) v = cconj(v);     // inverse DFT = conj(DFT(conj(x)))
-      x[j] = cmul(v, chirp[j]);
-    } else {
-      x[j] = CT<C>::make(0, 0);
+  // chirp and filter spectrum into registers before any of them is needed
+  V cj[NJ], hk[NK];
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int j = tid + u * NT;
+    if (j < n) cj[u] = chirp[j];
+  }
+#pragma unroll
+  for (int u = 0; u < NK; ++u) {
+    const int k = tid + u * NT;
+    if (k < M) hk[u] = H[k];
+  }
+#pragma unroll
+  for (int u = 0; u < NK; ++u) {
+    const int j = tid + u * NT;
+    if (j < M) {
+      if (u < NJ && j < n) {
+        V v = x[j];
+        if (dir > 0) v = cconj(v);     // inverse DFT = conj(DFT(conj(x)))
+        x[j] = cmul(v, cj[u < NJ ? u : 0]);
+      } else {
+        x[j] = CT<C>::make(0, 0);
+      }
     }
   }
   __syncthreads();
   fft_pow2<C, NT, MAXB>(x, lgM, -1, tw, tw_len);
-  for (int k = tid; k < M; k += NT) x[k] = cmul(x[k], H[k]);
+#pragma unroll
+  for (int u = 0; u < NK; ++u) {
+    const int k = tid + u * NT;
+    if (k < M) x[k] = cmul(x[k], hk[u]);
+  }
   __syncthreads();
   fft_pow2<C, NT, MAXB>(x, lgM, +1, tw, tw_len);
   const C invM = (C)1 / (C)M;
-  for (int k = tid; k < n; k += NT) {
-    V v = cmul(x[k], chirp[k]);
-    v.x *= invM;
-    v.y *= invM;
-    if (dir > 0) v = cconj(v);
-    x[k] = v;
+#pragma unroll
+  for (int u = 0; u < NJ; ++u) {
+    const int k = tid + u * NT;
+    if (k < n) {
+      V v = cmul(x[k], cj[u]);
+      v.x *= invM;
+      v.y *= invM;
+      if (dir > 0) v = cconj(v);
+      x[k] = v;
+    }
   }
   __syncthreads();
 }
@@ -239,17 +265,21 @@ struct Tabs<float> {
 };
 
 // The ring's transform, with the twiddles of its length L (n, or the Bluestein M)
-// staged in LDS: twl[t] = exp(-2 pi i t / L), t < L / 4.
-template <class C, int NT, int MAXB>
+// staged in LDS: twl[t] = exp(-2 pi i t / L), t < L / 4. KIND 0: the launch holds
+// only power-of-two rings, 1: only Bluestein rings, 2: both.
+template <class C, int NT, int MAXB, int KIND>
 __device__ __forceinline__ void ring_dft(typename CT<C>::V* buf, const typename CT<C>::V* twl,
                                          const RingPair& rp, int dir, const PlanDev& P) {
-  if (rp.log2n >= 0) {
+  if (KIND == 0 || (KIND == 2 && rp.log2n >= 0)) {
     fft_pow2<C, NT, MAXB>(buf, rp.log2n, dir, twl, rp.nphi);
   } else {
     dft_bluestein<C, NT, MAXB>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, Tabs<C>::chirp(P) + rp.chirp_off,
                                Tabs<C>::blue(P) + rp.bl_off, twl, rp.bl_M);
   }
 }
+
+// Kind of transforms in a ring launch class (see ring_dft).
+constexpr int class_kind(int cls) { return cls == 0 ? 1 : (cls == 1 ? 0 : 2); }
 
 template <class T>
 struct Vec4;
@@ -262,7 +292,7 @@ struct Vec4<float> {
   using type = float4;
 };
 
-template <class T, class C, int NT, int MAXB>
+template <class T, class C, int NT, int MAXB, int KIND>
 __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs& a, const int q,
                                              const int map, const int buf_elems) {
   using V4 = typename Vec4<T>::type;
@@ -412,7 +442,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
     }
     stage_twiddles();
     __syncthreads();
-    ring_dft<C, NT, MAXB>(buf, twl, rp, +1, P);
+    ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, +1, P);
   } else if (mode & PB_READ_MAP) {
     const T* src = static_cast<const T*>(a.map_in) + mbase;
     for (int j = tid; j < n; j += NT)
@@ -474,7 +504,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
 
   // ---- analysis: forward DFT and unfold into S/D per m
   if (mode & PB_ANALYSIS) {
-    ring_dft<C, NT, MAXB>(buf, twl, rp, -1, P);
+    ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, -1, P);
     T* Gp = static_cast<T*>(a.G) + pbase;
     const double half_omega = 0.5 * P.omega;
     double2 ph = expipi<double>(-(int64_t)tid * rp.ph_num, n);          // exp(-i m phi0)
@@ -500,10 +530,10 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   }
 }
 
-template <class T, class C, int NT, int MAXB>
+template <class T, class C, int NT, int MAXB, int CLS>
 __global__ void __launch_bounds__(NT) phase_b_kernel(PlanDev P, PhaseBArgs a, const int32_t* __restrict__ qlist,
                                                      int buf_elems) {
-  phase_b_body<T, C, NT, MAXB>(P, a, qlist[blockIdx.x], blockIdx.y, buf_elems);
+  phase_b_body<T, C, NT, MAXB, class_kind(CLS)>(P, a, qlist[blockIdx.x], blockIdx.y, buf_elems);
 }
 
 // Task groups (float storage and arithmetic): block b of task t covers entry
@@ -532,7 +562,8 @@ __global__ void __launch_bounds__(NT) group_phase_b_kernel(const TaskDev* __rest
   a.map_out = t.map_out;
   a.slots = t.slots;
   a.q_stride = t.q_stride;
-  phase_b_body<float, float, NT, MAXB>(t.P, a, t.ring_q[CLS][local / t.nmaps], (int)(local % t.nmaps), buf_elems);
+  phase_b_body<float, float, NT, MAXB, class_kind(CLS)>(t.P, a, t.ring_q[CLS][local / t.nmaps],
+                                                        (int)(local % t.nmaps), buf_elems);
 }
 
 // Radix-4 butterflies per thread and pass for a transform of fft_len points.
@@ -551,32 +582,33 @@ hipError_t set_lds(K kernel, size_t lds, size_t* attr) {
   return hipSuccess;
 }
 
-template <class T, class C, int NT, int MAXB>
+template <class T, class C, int NT, int MAXB, int CLS>
 hipError_t launch_class_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
   static size_t attr = 0;
   const size_t lds = ring_lds_bytes(rc.fft_len, sizeof(typename CT<C>::V));
-  if (hipError_t e = set_lds(phase_b_kernel<T, C, NT, MAXB>, lds, &attr)) return e;
-  hipLaunchKernelGGL((phase_b_kernel<T, C, NT, MAXB>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q,
+  if (hipError_t e = set_lds(phase_b_kernel<T, C, NT, MAXB, CLS>, lds, &attr)) return e;
+  hipLaunchKernelGGL((phase_b_kernel<T, C, NT, MAXB, CLS>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q,
                      rc.fft_len);
   return hipGetLastError();
 }
 
-template <class T, class C, int NT>
+template <class T, class C, int CLS>
 hipError_t launch_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
   if (rc.count == 0) return hipSuccess;
+  constexpr int NT = CLS < 2 ? 512 : 64;
   switch (maxb_for(rc.fft_len, NT)) {
-    case 1: return launch_class_b<T, C, NT, 1>(P, a, rc, s);
-    case 2: return launch_class_b<T, C, NT, 2>(P, a, rc, s);
-    case 4: return launch_class_b<T, C, NT, 4>(P, a, rc, s);
+    case 1: return launch_class_b<T, C, NT, 1, CLS>(P, a, rc, s);
+    case 2: return launch_class_b<T, C, NT, 2, CLS>(P, a, rc, s);
+    case 4: return launch_class_b<T, C, NT, 4, CLS>(P, a, rc, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <class T, class C>
 hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, const RingClass* cls, hipStream_t s) {
-  hipError_t e = launch_class<T, C, 512>(P, a, cls[0], s);
-  if (e == hipSuccess) e = launch_class<T, C, 512>(P, a, cls[1], s);
-  if (e == hipSuccess) e = launch_class<T, C, 64>(P, a, cls[2], s);
+  hipError_t e = launch_class<T, C, 0>(P, a, cls[0], s);
+  if (e == hipSuccess) e = launch_class<T, C, 1>(P, a, cls[1], s);
+  if (e == hipSuccess) e = launch_class<T, C, 2>(P, a, cls[2], s);
   return e;
 }
 
@@ -617,9 +649,11 @@ hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass
 
 hipError_t launch_phase_b_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, int cls, bool fp32,
                                 hipStream_t s) {
-  if (cls < 2)
-    return fp32 ? launch_class<float, float, 512>(P, a, rc, s) : launch_class<double, double, 512>(P, a, rc, s);
-  return fp32 ? launch_class<float, float, 64>(P, a, rc, s) : launch_class<double, double, 64>(P, a, rc, s);
+  switch (cls) {
+    case 0: return fp32 ? launch_class<float, float, 0>(P, a, rc, s) : launch_class<double, double, 0>(P, a, rc, s);
+    case 1: return fp32 ? launch_class<float, float, 1>(P, a, rc, s) : launch_class<double, double, 1>(P, a, rc, s);
+    default: return fp32 ? launch_class<float, float, 2>(P, a, rc, s) : launch_class<double, double, 2>(P, a, rc, s);
+  }
 }
 
 }  // namespace mwf
