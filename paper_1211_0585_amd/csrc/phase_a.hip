@@ -70,6 +70,16 @@ __device__ __forceinline__ void sectoral_seed(int m, double sin_t, double norm, 
 
 __device__ __forceinline__ int wave_any(int pred) { return __any(pred); }
 
+// a + b over lanes l and l + 32 with the halves exchanged (v_permlane32_swap): lanes
+// 0..31 return a[l] + a[l + 32], lanes 32..63 return b[l - 32] + b[l].
+__device__ __forceinline__ double fold_halves(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
 template <int R>
 struct RingState {
   double z[R], mu1[R], mu2[R];
@@ -121,7 +131,7 @@ template <int R>
 __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
     PlanDev P, const WorkItem* __restrict__ items, const double* __restrict__ G,
     double2* __restrict__ partial) {
-  __shared__ double red[2 * CHUNK][LANES + 1];
+  __shared__ double red[2 * CHUNK][LANES / 2 + 1];
   const WorkItem it = items[blockIdx.x];
   const int m = it.m, blk = it.blk, map = blockIdx.y;
   const int lane = threadIdx.x;
@@ -171,20 +181,24 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
         aim[j + 1] = fma(st.mu1[r], Dim[r], aim[j + 1]);
       }
     }
-    // reduce the 32 values over the 64 lanes through LDS
+    // reduce the 32 values (v = 2 j + re/im) over the 64 lanes: first lanes l and
+    // l + 32 in registers, the lower half keeping values 0..15 and the upper half
+    // 16..31, then the remaining 32 lanes through LDS
 #pragma unroll
-    for (int j = 0; j < CHUNK; ++j) {
-      red[2 * j][lane] = are[j];
-      red[2 * j + 1][lane] = aim[j];
+    for (int i = 0; i < 16; ++i) {
+      const int ja = i >> 1, jb = 8 + (i >> 1);
+      const double va = (i & 1) ? aim[ja] : are[ja];
+      const double vb = (i & 1) ? aim[jb] : are[jb];
+      red[i + ((lane >> 5) << 4)][lane & 31] = fold_halves(va, vb);
     }
     __syncthreads();
-    const int v = lane & 31;
-    const int h = (lane >> 5) * 32;
+    const int v = lane >> 1;
+    const int h = (lane & 1) * 16;
     double sum = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < 32; ++k) sum += red[v][h + k];
-    sum += __shfl_xor(sum, 32);
-    if (lane < 32) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) sum += red[v][h + k];
+    sum += __shfl_xor(sum, 1);
+    if ((lane & 1) == 0) {
       const int l = l0 + (v >> 1);
       if (l <= lmax) out[2 * (row + (l - m)) + (v & 1)] = sum;
     }
