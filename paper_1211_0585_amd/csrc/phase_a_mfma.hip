@@ -80,20 +80,33 @@ __device__ __forceinline__ Ring ring_init(const PlanDev& P, int m, int q, int na
   return r;
 }
 
-// Advance MCH steps from l0 and hand each value (zero while scaled) to emit(j, value).
+// Advance MCH steps from l0 and hand each value to emit(j, value). A ring still
+// scaled at the start of the chunk emits zeros for the whole chunk; the scale is
+// checked once at its end. The recurrence alternates between mu2 and mu1, so a
+// step is one multiply and one FMA.
 template <class Emit>
 __device__ __forceinline__ void ring_steps(Ring& r, const double* __restrict__ Ac, Emit emit) {
-  const double cf = r.sc == 0 ? 1.0 : 0.0;
+  const bool scaled = r.sc != 0;
+  if (__any(scaled)) {
 #pragma unroll
-  for (int j = 0; j < MCH; ++j) {
-    const double mu = fma(Ac[j] * r.z, r.mu1, -r.mu2);
-    r.mu2 = r.mu1;
-    r.mu1 = mu;
-    emit(j, mu * cf);
-    if ((j & 3) == 3 && r.sc > 0 && fabs(r.mu1) > BIG_THRESH) {
+    for (int j = 0; j < MCH; j += 2) {
+      r.mu2 = fma(Ac[j] * r.z, r.mu1, -r.mu2);
+      emit(j, scaled ? 0.0 : r.mu2);
+      r.mu1 = fma(Ac[j + 1] * r.z, r.mu2, -r.mu1);
+      emit(j + 1, scaled ? 0.0 : r.mu1);
+    }
+    if (scaled && fmax(fabs(r.mu1), fabs(r.mu2)) > BIG_THRESH) {
       r.mu1 *= RESCALE;
       r.mu2 *= RESCALE;
       r.sc -= 1;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < MCH; j += 2) {
+      r.mu2 = fma(Ac[j] * r.z, r.mu1, -r.mu2);
+      emit(j, r.mu2);
+      r.mu1 = fma(Ac[j + 1] * r.z, r.mu2, -r.mu1);
+      emit(j + 1, r.mu1);
     }
   }
 }
