@@ -172,7 +172,7 @@ int wf_pixel_angles(int32_t nside, double* theta, double* phi);
 /*
  * wf_autotune -- time every launch shape of the matrix-core Legendre kernels
  * (analysis: 1 or 2 column tiles per workgroup; synthesis: 1, 2 or 4 column tiles
- * per wave) on this plan at nmaps maps, keep the fastest in the plan, record it
+ * per wave, or 8 for WF_F32) on this plan at nmaps maps, keep the fastest in the plan, record it
  * in the process-wide cache (and in opts.tune_cache if given) so that later plans
  * of the same shape start with it. Overwrites the plan's work buffers (run it
  * before a solve, not between the calls of one). Waits for its own launches.
@@ -213,7 +213,7 @@ int wf_group_solve(wf_group_t group, const void* const* d, void* const* s_wf,
 
 /*
  * wf_group_autotune -- time two-sweep group solves over every launch shape (6
- * combinations) and keep the fastest for this group. Overwrites s_wf.
+ * combinations, 8 for WF_F32) and keep the fastest for this group. Overwrites s_wf.
  */
 int wf_group_autotune(wf_group_t group, const void* const* d, void* const* s_wf,
                       void* hip_stream, int32_t* ana_ct, int32_t* syn_nct);

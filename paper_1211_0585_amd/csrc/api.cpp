@@ -58,7 +58,7 @@ void load_tuning_file(const char* cache_path) {
     std::string key;
     Tuning t;
     if (ss >> key >> t.ana_ct >> t.syn_nct && (t.ana_ct == 1 || t.ana_ct == 2) &&
-        (t.syn_nct == 1 || t.syn_nct == 2 || t.syn_nct == 4))
+        (t.syn_nct == 1 || t.syn_nct == 2 || t.syn_nct == 4 || t.syn_nct == 8))
       g_tune[key] = t;
   }
 }
@@ -617,7 +617,8 @@ extern "C" int wf_autotune(wf_plan_t p, int32_t nmaps, void* hip_stream, int32_t
     }
   }
   tbest = 1e30f;
-  for (int nct : {1, 2, 4}) {
+  for (int nct : {1, 2, 4, 8}) {
+    if (nct == 8 && p->dtype != WF_F32) continue;   // one wave over 128 columns: FP32 only
     MfmaArgs ma = mfma_args(p, SY_FROM_PARTIAL, nmaps, 1.0, nullptr, nullptr);
     float ms;
     if ((rc = time_min(s, 3, [&] {
@@ -840,7 +841,8 @@ int wf_group_autotune(wf_group_t gr, const void* const* d, void* const* s_wf, vo
   Tuning best = gr->tune;
   float tbest = 1e30f;
   for (int ct : {1, 2})
-    for (int nct : {1, 2, 4}) {
+    for (int nct : {1, 2, 4, 8}) {
+      if (nct == 8 && gr->dtype != WF_F32) continue;
       gr->tune.ana_ct = ct;
       gr->tune.syn_nct = nct;
       float ms;

@@ -548,8 +548,14 @@ hipError_t syn_np(const PlanDev& P, const WorkItem* items, int nitems, int nct, 
     hipLaunchKernelGGL((mfma_synthesis_kernel<NP, 1>), grid, dim3(64), 0, s, P, items, a);
   else if (nct == 2)
     hipLaunchKernelGGL((mfma_synthesis_kernel<NP, 2>), grid, dim3(64), 0, s, P, items, a);
-  else
+  else if (nct == 4)
     hipLaunchKernelGGL((mfma_synthesis_kernel<NP, 4>), grid, dim3(64), 0, s, P, items, a);
+  else if constexpr (NP == 1) {
+    if (nct != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((mfma_synthesis_kernel<NP, 8>), grid, dim3(64), 0, s, P, items, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -570,9 +576,16 @@ hipError_t gsyn_np(const GroupLaunch& g, int nct, int ana_rb, hipStream_t s) {
   else if (nct == 2)
     hipLaunchKernelGGL((group_synthesis_kernel<NP, 2>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
                        ana_rb);
-  else
+  else if (nct == 4)
     hipLaunchKernelGGL((group_synthesis_kernel<NP, 4>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
                        ana_rb);
+  else if constexpr (NP == 1) {
+    if (nct != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((group_synthesis_kernel<NP, 8>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
+                       ana_rb);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -98,7 +98,7 @@ RingGeo ring_geometry(int n, int i);
 // Launch-shape choices of the matrix-core kernels (see the autotuner).
 struct Tuning {
   int ana_ct = 2;    // column tiles per analysis workgroup (ring block 128 ct)
-  int syn_nct = 2;   // column tiles per synthesis wave
+  int syn_nct = 2;   // column tiles per synthesis wave (8 for FP32 only)
 };
 
 bool lookup_tuning(const std::string& key, Tuning* t);

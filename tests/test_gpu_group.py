@@ -91,7 +91,7 @@ def test_group_autotune_and_resolve(torch_dev, cases):
     g = mwf.Group(plans, [c["nmaps"] for c in cases])
     ct, nct = g.autotune(ds)
     _log(f"group autotune: ana_ct {ct} syn_nct {nct}")
-    assert ct in (1, 2) and nct in (1, 2, 4)
+    assert ct in (1, 2) and nct in (1, 2, 4, 8)
     w1, a1 = g.solve(ds, LAMS)
     w2, a2 = g.solve(ds, LAMS)   # a repeated solve reuses the task table
     torch.cuda.synchronize()
@@ -112,7 +112,7 @@ def test_plan_autotune_keeps_results(torch_dev, cases):
         p.sync()
         w0 = w0.cpu().numpy()
         ct, nct = p.autotune()
-        assert ct in (1, 2) and nct in (1, 2, 4)
+        assert ct in (1, 2) and nct in (1, 2, 4, 8)
         w1, a1 = p.solve(d, LAMS)
         p.sync()
         e = rel_l2(w1.cpu().numpy(), w0)
