@@ -62,8 +62,16 @@ enum { WF_F64 = 0, WF_F32 = 1, WF_BF16X3 = 2, WF_BF16X6 = 3 };
 
 /* Plan flags. WF_FLAG_TIMING: record HIP events around every kernel launch of a
  * solve on the caller's stream and report the summed durations in wf_stats; the
- * solve then waits for its own completion before returning. */
-enum { WF_FLAG_TIMING = 1 };
+ * solve then waits for its own completion before returning.
+ * WF_FLAG_CHI2: every solve also records, for each map and each sweep k, the chi^2
+ * of the iterate after that sweep (Sect. 3's convergence monitor, at lambda = 1):
+ *   chi2_k = sum_lm w_m |s_lm|^2 / C_l + sum_p N^-1_p (d_p - s_p)^2,
+ * w_m = 1 for m = 0 and 2 for m > 0, modes with C_l = 0 left out, s_p the synthesis
+ * of s_lm; read with wf_chi2 (wf_stats.chi2_last holds map 0's last value, at the
+ * cost of a synchronisation). The terms are accumulated by FP64 atomics, so their
+ * last bits depend on the order of the additions. Plan solves only (not groups or
+ * serving). */
+enum { WF_FLAG_TIMING = 1, WF_FLAG_CHI2 = 2 };
 
 typedef struct wf_plan_s* wf_plan_t;
 typedef struct wf_group_s* wf_group_t;
@@ -84,6 +92,7 @@ typedef struct {
   double ms_synthesis;   /* summed duration of the filter + Legendre synthesis launches */
   int32_t n_ring, n_analysis, n_synthesis;   /* number of launches of each kind        */
   int32_t pad_;
+  double chi2_last;      /* WF_FLAG_CHI2: chi^2 of map 0 after the last sweep, else 0     */
 } wf_stats;
 
 /*
@@ -119,6 +128,14 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl,
 int wf_solve(wf_plan_t plan, const void* d, void* s_wf, void* s_alm,
              const double* lambda, int32_t nsweeps, void* hip_stream,
              wf_stats* stats);
+
+/*
+ * wf_chi2 -- the chi^2 history of the last solve on a plan created with WF_FLAG_CHI2:
+ *   nmaps, nsweeps  those of that solve (checked)
+ *   out             host, nmaps * nsweeps doubles: out[map * nsweeps + k] = chi2_k
+ * Waits for the solve. Errors: WF_EINVAL (no such solve, other sizes), WF_EDEVICE.
+ */
+int wf_chi2(wf_plan_t plan, int32_t nmaps, int32_t nsweeps, double* out);
 
 /*
  * wf_solve_batch -- wf_solve for nmaps independent data maps that share the

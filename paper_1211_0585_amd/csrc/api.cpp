@@ -190,8 +190,10 @@ struct TimerScope {
 
 // ---------------------------------------------------------------- plan-level launches
 int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, const void* d,
-                const void* map_in, void* map_out) {
+                const void* map_in, void* map_out, double* chi2 = nullptr) {
   PhaseBArgs a{};
+  a.chi2 = chi2;
+  a.chi2_stride = 2 * (int64_t)p->chi2_cap;
   a.mode = mode;
   a.nmaps = nmaps;
   a.lambda = lam;
@@ -265,10 +267,12 @@ int run_analysis(wf_plan_s* p, hipStream_t s, int nmaps) {
 }
 
 int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, const void* alm_in,
-                  void* alm_out) {
+                  void* alm_out, double* chi2 = nullptr) {
   const Geometry& g = *p->geo;
   if (p->dtype != WF_F64) {
-    const MfmaArgs ma = mfma_args(p, mode, nmaps, lam, alm_in, alm_out);
+    MfmaArgs ma = mfma_args(p, mode, nmaps, lam, alm_in, alm_out);
+    ma.chi2 = chi2;
+    ma.chi2_stride = 2 * (int64_t)p->chi2_cap;
     TIMED(2, {
       MWF_HIP(launch_mfma_coeff(p->dev, ma, s));
       if (mode != SY_ALM_ONLY)
@@ -285,6 +289,8 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, 
   a.alm_out = static_cast<double2*>(alm_out);
   a.F = static_cast<double*>(p->F);
   a.bcoef = p->bcoef;
+  a.chi2 = chi2;
+  a.chi2_stride = 2 * (int64_t)p->chi2_cap;
   TIMED(2, {
     MWF_HIP(launch_legendre_coeff(p->dev, a, s));
     if (mode != SY_ALM_ONLY) MWF_HIP(launch_legendre_synthesis_f64(p->dev, g.items_syn, g.n_syn, a, s));
@@ -438,7 +444,7 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
   if (opts) {
     if (!valid_dtype(opts->dtype)) return fail(WF_EINVAL, "unknown dtype");
     if (opts->max_batch < 0) return fail(WF_EINVAL, "max_batch must be >= 0");
-    if (opts->flags & ~WF_FLAG_TIMING) return fail(WF_EINVAL, "unknown flags");
+    if (opts->flags & ~(WF_FLAG_TIMING | WF_FLAG_CHI2)) return fail(WF_EINVAL, "unknown flags");
   }
   const int dtype = opts ? opts->dtype : WF_F64;
   const int64_t npix = 12LL * nside * nside;
@@ -522,19 +528,58 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
   timer.on = (p->flags & WF_FLAG_TIMING) != 0;
   timer.s = s;
   TimerScope scope(&timer);
+  // chi^2 history (WF_FLAG_CHI2): [map][2 k] prior term, [map][2 k + 1] data term of iterate k
+  const bool chi = (p->flags & WF_FLAG_CHI2) != 0;
+  if (chi) {
+    if (nsweeps > p->chi2_cap) {
+      if ((rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * 2 * nsweeps))) return rc;
+      p->chi2_cap = nsweeps;
+    }
+    MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * 2 * p->chi2_cap * sizeof(double), s));
+    p->chi2_nsweeps = nsweeps;
+    p->chi2_nmaps = nmaps;
+  }
+  auto slot = [&](int k, int term) { return chi ? p->chi2_buf + 2 * k + term : nullptr; };
   for (int k = 0; k < nsweeps; ++k) {
     const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
-    if ((rc = run_phase_b(p, s, mode, nmaps, lambda[k], d, nullptr, nullptr))) return rc;
+    if ((rc = run_phase_b(p, s, mode, nmaps, lambda[k], d, nullptr, nullptr, k > 0 ? slot(k - 1, 1) : nullptr)))
+      return rc;
     if ((rc = run_analysis(p, s, nmaps))) return rc;
     void* alm_out = (k == nsweeps - 1) ? s_alm : nullptr;
-    if ((rc = run_synthesis(p, s, SY_FROM_PARTIAL, nmaps, lambda[k], nullptr, alm_out))) return rc;
+    if ((rc = run_synthesis(p, s, SY_FROM_PARTIAL, nmaps, lambda[k], nullptr, alm_out, slot(k, 0)))) return rc;
   }
-  if ((rc = run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr, s_wf))) return rc;
+  if ((rc = run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP | (chi ? PB_CHI2 : 0), nmaps, 1.0, chi ? d : nullptr, nullptr,
+                        s_wf, slot(nsweeps - 1, 1))))
+    return rc;
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->sweeps_done = nsweeps;
     if ((rc = timer.collect(stats))) return rc;
+    if (chi) {
+      double last[2];
+      MWF_HIP(hipMemcpyAsync(last, p->chi2_buf + 2 * (nsweeps - 1), sizeof(last), hipMemcpyDeviceToHost, s));
+      MWF_HIP(hipStreamSynchronize(s));
+      stats->chi2_last = last[0] + last[1] / p->tau;
+    }
   }
+  return WF_OK;
+}
+
+int wf_chi2(wf_plan_t p, int32_t nmaps, int32_t nsweeps, double* out) {
+  if (!p || !out) return fail(WF_EINVAL, "plan and out must not be NULL");
+  if (!(p->flags & WF_FLAG_CHI2) || p->chi2_nsweeps == 0)
+    return fail(WF_EINVAL, "no solve with WF_FLAG_CHI2 has run on this plan");
+  if (nmaps != p->chi2_nmaps || nsweeps != p->chi2_nsweeps)
+    return fail(WF_EINVAL, "nmaps and nsweeps must be those of the last solve (" + std::to_string(p->chi2_nmaps) +
+                               ", " + std::to_string(p->chi2_nsweeps) + ")");
+  std::vector<double> raw((size_t)nmaps * 2 * p->chi2_cap);
+  MWF_HIP(hipStreamSynchronize(p->last_stream));
+  MWF_HIP(hipMemcpy(raw.data(), p->chi2_buf, raw.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < nmaps; ++i)
+    for (int k = 0; k < nsweeps; ++k) {
+      const double* r = raw.data() + (size_t)i * 2 * p->chi2_cap + 2 * k;
+      out[(size_t)i * nsweeps + k] = r[0] + r[1] / p->tau;
+    }
   return WF_OK;
 }
 

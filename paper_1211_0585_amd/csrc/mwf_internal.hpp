@@ -99,7 +99,8 @@ enum PhaseBMode : int32_t {
   PB_UPDATE = 2,      // t = s + w (d - s)
   PB_ANALYSIS = 4,    // forward ring DFT, write G (S/D per m)
   PB_WRITE_MAP = 8,   // write the synthesised map (before the update)
-  PB_READ_MAP = 16    // take the ring values from `map_in` instead of a synthesis
+  PB_READ_MAP = 16,   // take the ring values from `map_in` instead of a synthesis
+  PB_CHI2 = 32        // with PB_SYNTH and a chi2 pointer: read d and tau N^-1 for the data term
 };
 
 // Pointers are in the plan's storage type (double, or float for the FP32 / BF16x3 paths).
@@ -124,7 +125,18 @@ struct PhaseBArgs {
   void* map_out;          // [map][npix]
   const SlotParam* slots; // null: mode, lambda and P.q shared by all maps
   int64_t q_stride;       // with slots: elements between the tau N^-1 rows of two maps
+  double* chi2;           // null, or where map 0 adds sum tau N^-1 (d - s)^2 of the synthesised s
+  int64_t chi2_stride;    // doubles between the chi2 entries of two maps
 };
+
+// Sum of v over each wave, added to *dst by one FP64 atomic per wave (no LDS: the
+// ring phase of the longest FP64 transforms uses all of it). Every lane of the wave
+// must call it.
+__device__ __forceinline__ void block_sum_add(double v, double* dst) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  if ((threadIdx.x & 63) == 0 && v != 0.0) atomicAdd(dst, v);
+}
 
 // Ring pairs launched together: a device list of pair indices and the largest
 // FFT length (power-of-two n, or the Bluestein M) among them.
@@ -174,6 +186,8 @@ struct SynthArgs {
   double2* alm_out;         // [map][nalm] or null
   double2* bcoef;           // [map][rows_total] C_l s_lm in the padded row layout
   double* F;                // [map][pair][m][4]
+  double* chi2;             // null, or where map 0 adds sum_lm w_m |s_lm|^2 / C_l (SY_FROM_PARTIAL)
+  int64_t chi2_stride;
 };
 
 // Sum of partials, filter and C scaling (one launch over all (l, m, map)).
@@ -199,6 +213,8 @@ struct MfmaArgs {
   float2* alm_out;          // [map][nalm] or null
   const SlotParam* slots;   // null: lambda and P.cl, P.tau shared by all maps
   int64_t cl_stride;        // with slots: entries between the C_l rows of two maps
+  double* chi2;             // as SynthArgs::chi2
+  int64_t chi2_stride;
 };
 
 // ct: column tiles (16 columns) per analysis workgroup, 1 or 2 (ring block 128 ct);

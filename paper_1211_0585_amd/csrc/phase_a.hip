@@ -238,6 +238,8 @@ __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
   const double* __restrict__ Crow = P.C + roff;
   const double lam_t_o = a.lambda * P.tau * P.omega;
   const int nb = P.nblk[m];
+  const bool chi = a.chi2 != nullptr && a.mode == SY_FROM_PARTIAL;
+  double chi_acc = 0.0;
   for (int i = threadIdx.x; i < nl + CHUNK; i += blockDim.x) {
     double2 b = make_double2(0.0, 0.0);
     if (i < nl) {
@@ -259,6 +261,8 @@ __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
           const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
           alm.x *= f;
           alm.y *= f;
+          // chi^2 prior term of the new iterate: w_m |s_lm|^2 / C_l (w = 1 at m = 0, else 2)
+          if (chi && cl > 0.0) chi_acc += (m == 0 ? 1.0 : 2.0) * (alm.x * alm.x + alm.y * alm.y) / cl;
         }
       }
       if (a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = alm;
@@ -266,6 +270,7 @@ __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
     }
     if (a.mode != SY_ALM_ONLY) a.bcoef[(size_t)map * P.rows_total + roff + i] = b;
   }
+  if (chi) block_sum_add(chi_acc, a.chi2 + map * a.chi2_stride);
 }
 
 constexpr int SCH = 8;   // synthesis steps per coefficient chunk

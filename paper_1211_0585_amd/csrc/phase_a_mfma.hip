@@ -402,7 +402,7 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
 // the synthesis coefficients b = C_l s_lm in the layout [padded row][map][re/im].
 // One thread per element e = r nmaps + map over the padded rows r of every m
 // (rows r = row_off[m] + i, i < lmax - m + 1 + ROW_PAD; padding rows get zeros).
-__device__ __forceinline__ void coeff_elem(const PlanDev& P, const MfmaArgs& a, const int64_t e) {
+__device__ __forceinline__ void coeff_elem(const PlanDev& P, const MfmaArgs& a, const int64_t e, double* chi_acc) {
   const int nm = a.nmaps;
   const int64_t r = e / nm;
   const int map = (int)(e - r * nm);
@@ -441,6 +441,7 @@ __device__ __forceinline__ void coeff_elem(const PlanDev& P, const MfmaArgs& a, 
         const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
         sr *= f;
         si *= f;
+        if (cl > 0.0) *chi_acc = (m == 0 ? 1.0 : 2.0) * (sr * sr + si * si) / cl;
       }
     }
     if (a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = make_float2((float)sr, (float)si);
@@ -464,9 +465,29 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
   synthesis_body<NP, NCT>(P, a, items[blockIdx.x], blockIdx.y);
 }
 
+// chi^2 prior term of the elements of one workgroup, added per map: through an LDS
+// slot per map when the maps fit in one workgroup, else one global atomic per element.
+__device__ __forceinline__ void coeff_chi2(const MfmaArgs& a, int64_t e, bool valid, double v) {
+  __shared__ double macc[COEFF_THREADS];
+  const int nm = a.nmaps;
+  const int map = (int)(e % nm);
+  if (nm <= COEFF_THREADS) {
+    if (threadIdx.x < nm) macc[threadIdx.x] = 0.0;
+    __syncthreads();
+    if (valid && v != 0.0) atomicAdd(&macc[map], v);
+    __syncthreads();
+    if ((int)threadIdx.x < nm && macc[threadIdx.x] != 0.0) atomicAdd(a.chi2 + threadIdx.x * a.chi2_stride, macc[threadIdx.x]);
+  } else if (valid && v != 0.0) {
+    atomicAdd(a.chi2 + map * a.chi2_stride, v);
+  }
+}
+
 __global__ void __launch_bounds__(COEFF_THREADS) mfma_coeff_kernel(PlanDev P, MfmaArgs a) {
   const int64_t e = (int64_t)blockIdx.x * COEFF_THREADS + threadIdx.x;
-  if (e < P.rows_total * a.nmaps) coeff_elem(P, a, e);
+  const bool valid = e < P.rows_total * a.nmaps;
+  double v = 0.0;
+  if (valid) coeff_elem(P, a, e, &v);
+  if (a.chi2 != nullptr && a.mode == SY_FROM_PARTIAL) coeff_chi2(a, e, valid, v);
 }
 
 // Task groups: block b belongs to the task t with offs[t] <= b < offs[t + 1].
@@ -523,7 +544,8 @@ __global__ void __launch_bounds__(COEFF_THREADS) group_coeff_kernel(const TaskDe
   const int t = find_task(offs, ntasks, blockIdx.x);
   const TaskDev& T = tasks[t];
   const int64_t e = (blockIdx.x - offs[t]) * COEFF_THREADS + threadIdx.x;
-  if (e < T.P.rows_total * T.nmaps) coeff_elem(T.P, task_args(T, ana_rb), e);
+  double v = 0.0;
+  if (e < T.P.rows_total * T.nmaps) coeff_elem(T.P, task_args(T, ana_rb), e, &v);
 }
 
 template <int NP>

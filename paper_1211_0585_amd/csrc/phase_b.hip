@@ -456,12 +456,15 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   }
 
   // ---- map output and the messenger update (Eq. 3)
+  // chi^2 data term of the synthesised iterate (block-uniform)
+  const bool chi = a.chi2 != nullptr && (mode & PB_SYNTH) && (mode & (PB_UPDATE | PB_CHI2));
+  double chi_acc = 0.0;
   if (mode & (PB_WRITE_MAP | PB_UPDATE)) {
     const double lam = a.slots ? a.slots[map].lambda : a.lambda;
     const T* __restrict__ d = static_cast<const T*>(a.d) + mbase;
     T* out = static_cast<T*>(a.map_out) + mbase;
     // d and tau N^-1 of the next pixel pair are loaded while the current one is updated
-    const bool upd = (mode & PB_UPDATE) != 0;
+    const bool upd = (mode & PB_UPDATE) != 0 || chi;
     T qn_nx{}, dn_nx{}, qs_nx{}, ds_nx{};
     if (upd && tid < n) {
       qn_nx = q_tab[rp.start_n + tid];
@@ -488,7 +491,15 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
         out[rp.start_n + j] = (T)x.x;
         if (!equator) out[rp.start_s + j] = (T)x.y;
       }
-      if (upd) {
+      if (chi) {
+        const double rn = (double)dn - x.x;
+        chi_acc += (double)qn * rn * rn;
+        if (!equator) {
+          const double rs = (double)ds - x.y;
+          chi_acc += (double)qs * rs * rs;
+        }
+      }
+      if (mode & PB_UPDATE) {
         const double wn = lam * (double)qn / (1.0 + (lam - 1.0) * (double)qn);
         x.x = x.x + wn * ((double)dn - x.x);
         if (!equator) {
@@ -501,6 +512,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
     }
     __syncthreads();
   }
+  if (chi) block_sum_add(chi_acc, a.chi2 + map * a.chi2_stride);
 
   // ---- analysis: forward DFT and unfold into S/D per m
   if (mode & PB_ANALYSIS) {

@@ -11,7 +11,7 @@ import numpy as np
 
 WF_OK, WF_EINVAL, WF_ENOMEM, WF_EDEVICE, WF_EUNSUPPORTED, WF_EBUSY, WF_ENOTREADY = 0, -1, -2, -3, -4, -5, -6
 WF_F64, WF_F32, WF_BF16X3, WF_BF16X6 = 0, 1, 2, 3
-WF_FLAG_TIMING = 1
+WF_FLAG_TIMING, WF_FLAG_CHI2 = 1, 2
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmwf.so")
 
@@ -44,6 +44,7 @@ _SIGS = [
     ("wf_server_poll", _c.c_int, [_c.c_void_p, _c.c_uint64, _c.c_void_p, _c.POINTER(_c.c_double)]),
     ("wf_server_query", _c.c_int, [_c.c_void_p, _c.c_void_p]),
     ("wf_server_destroy", None, [_c.c_void_p]),
+    ("wf_chi2", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p]),
     ("wf_sync", _c.c_int, [_c.c_void_p]),
     ("wf_destroy", None, [_c.c_void_p]),
     ("wf_strerror", _c.c_char_p, [_c.c_int]),
@@ -90,7 +91,7 @@ class wf_stats(ctypes.Structure):
                 ("ms_ring", ctypes.c_double), ("ms_analysis", ctypes.c_double),
                 ("ms_synthesis", ctypes.c_double), ("n_ring", ctypes.c_int32),
                 ("n_analysis", ctypes.c_int32), ("n_synthesis", ctypes.c_int32),
-                ("pad_", ctypes.c_int32)]
+                ("pad_", ctypes.c_int32), ("chi2_last", ctypes.c_double)]
 
 
 def footprint(nside, lmax, dtype=WF_F64, nmaps=1):
@@ -197,6 +198,12 @@ class Plan:
                                     lam.ctypes.data, lam.size, _stream_handle(stream), ctypes.byref(st)))
         self.last_stats = st
         return s_wf, s_alm
+
+    def chi2(self, nmaps, nsweeps):
+        """chi^2 after every sweep of the last solve (plan flag WF_FLAG_CHI2): [nmaps, nsweeps]."""
+        out = np.empty((nmaps, nsweeps))
+        _check(lib().wf_chi2(self.handle, nmaps, nsweeps, out.ctypes.data))
+        return out
 
     def map2alm(self, maps, alm=None, stream=None):
         import torch

@@ -71,7 +71,7 @@ def test_plan_rejects_bad_values():
     assert _plan_rc(nside, lmax, cl, ninv, mask=np.zeros(npix))[0] == mwf.WF_EINVAL  # all masked
     opts = mwf.wf_plan_opts(7, 1, 0, None)
     assert _plan_rc(nside, lmax, cl, ninv, opts=opts)[0] == mwf.WF_EINVAL
-    opts = mwf.wf_plan_opts(0, 1, 3, None)
+    opts = mwf.wf_plan_opts(0, 1, 4, None)   # unknown flag bit
     assert _plan_rc(nside, lmax, cl, ninv, opts=opts)[0] == mwf.WF_EINVAL
 
 
