@@ -20,8 +20,8 @@
 // one exp(i k phi0).
 //
 // Ring lengths are 4 i (polar caps) or 4 nside (belt). Powers of two use an
-// in-place Stockham FFT (radix 4, plus one radix-2 pass for odd log2 n) whose
-// butterflies are staged in registers between two barriers per pass; other
+// in-place Stockham FFT (radix 8, with radix-4 passes for log2 n not a multiple
+// of 3) whose butterflies are staged in registers between two barriers per pass; other
 // lengths use Bluestein's chirp-z method: chirp, power-of-two FFT of length
 // M >= 2 n - 1, multiply by the plan-time filter spectrum, inverse FFT, chirp.
 // The FFT arithmetic type C is double for FP64 plans and float for plans that
@@ -109,81 +109,146 @@ __device__ __forceinline__ void dft4(V& v0, V& v1, V& v2, V& v3, S sd) {
   v3 = csub(t1, t3);
 }
 
-// In-place Stockham FFT of length L = 2^lg (4 <= L <= 4 MAXB NT) in LDS, run by
-// all NT threads of the workgroup; dir = -1: exp(-2 pi i jk/L), +1: exp(+...). Unnormalised. Radix-4 passes,
-// with one radix-2 pass first when lg is odd. tw[t] = exp(-2 pi i t / tw_len),
-// t < tw_len / 4 (in LDS). Every pass loads all butterfly inputs into registers,
-// synchronises, then writes the outputs, so a single LDS buffer suffices.
+// Radix-8 DFT of v[0..7] in registers (sd = -1 forward, +1 inverse): two radix-4
+// DFTs of the even and odd inputs, joined with the eighth roots of unity.
+template <class V, class S>
+__device__ __forceinline__ void dft8(V* v, S sd) {
+  V e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+  V o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+  dft4(e0, e1, e2, e3, sd);
+  dft4(o0, o1, o2, o3, sd);
+  const S c = (S)0.70710678118654752440;
+  // o1 *= exp(sd i pi/4) = c (1 + i sd), o2 *= i sd, o3 *= exp(3 sd i pi/4) = c (-1 + i sd)
+  V t1, t3;
+  t1.x = c * (o1.x - sd * o1.y);
+  t1.y = c * (o1.y + sd * o1.x);
+  t3.x = c * (-o3.x - sd * o3.y);
+  t3.y = c * (sd * o3.x - o3.y);
+  const V t2 = cmul_is(o2, sd);
+  v[0] = cadd(e0, o0);
+  v[4] = csub(e0, o0);
+  v[1] = cadd(e1, t1);
+  v[5] = csub(e1, t1);
+  v[2] = cadd(e2, t2);
+  v[6] = csub(e2, t2);
+  v[3] = cadd(e3, t3);
+  v[7] = csub(e3, t3);
+}
+
+// One radix-R pass (R = 2, 4 or 8) of an in-place Stockham FFT of length L in LDS,
+// after Ns points have been combined: butterfly j (j < L / R, k = j mod Ns) takes
+// x[j + r L / R], r < R, multiplies input r by w^r with w = exp(dir 2 pi i k / (R Ns)),
+// takes its radix-R DFT and writes output r to x[(j - k) R + k + r Ns]. NBF
+// butterflies per thread; all inputs are read into registers before the barrier
+// that precedes the writes, so a single buffer suffices. tw[t] = exp(-2 pi i t /
+// tw_len), t < tw_len / 4.
+template <class C, int NT, int R, int NBF>
+__device__ __forceinline__ void stockham_pass(typename CT<C>::V* x, int L, int Ns, int dir,
+                                              const typename CT<C>::V* __restrict__ tw, int tw_len) {
+  using V = typename CT<C>::V;
+  const int tid = threadIdx.x;
+  const C sd = (C)dir;
+  const int nb = L / R;
+  V v[R * NBF];
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int j = tid + b * NT;
+    if (j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[R * b + r] = x[j + r * nb];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int j = tid + b * NT;
+    if (j < nb) {
+      const int k = j & (Ns - 1);
+      V* u = v + R * b;
+      if (Ns > 1) {
+        const int t1 = k * (tw_len / (Ns * R));
+        V w = tw[t1];
+        if (dir > 0) w.y = -w.y;
+        if (R == 2) {
+          u[1] = cmul(u[1], w);
+        } else if (R == 4) {
+          const V w2 = cmul(w, w), w3 = cmul(w2, w);
+          u[1] = cmul(u[1], w);
+          u[2] = cmul(u[2], w2);
+          u[3] = cmul(u[3], w3);
+        } else {
+          // w^2 (index 2 t1 < tw_len / 4) and w^4 from the table, the latter past a
+          // quarter turn as -i tw[t - tw_len / 4]; the other powers at most two
+          // products deep
+          const int q4 = tw_len / 4, t4 = 4 * t1;
+          V w2 = tw[2 * t1];
+          V w4 = tw[t4 < q4 ? t4 : t4 - q4];
+          if (t4 >= q4) w4 = CT<C>::make(w4.y, -w4.x);
+          if (dir > 0) {
+            w2.y = -w2.y;
+            w4.y = -w4.y;
+          }
+          const V w3 = cmul(w, w2);
+          u[1] = cmul(u[1], w);
+          u[2] = cmul(u[2], w2);
+          u[3] = cmul(u[3], w3);
+          u[4] = cmul(u[4], w4);
+          u[5] = cmul(u[5], cmul(w, w4));
+          u[6] = cmul(u[6], cmul(w2, w4));
+          u[7] = cmul(u[7], cmul(w3, w4));
+        }
+      }
+      if (R == 2) {
+        const V a0 = u[0];
+        u[0] = cadd(a0, u[1]);
+        u[1] = csub(a0, u[1]);
+      } else if (R == 4) {
+        dft4(u[0], u[1], u[2], u[3], sd);
+      } else {
+        dft8(u, sd);
+      }
+      const int idx = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[idx + r * Ns] = u[r];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place Stockham FFT of length L = 2^lg (2 <= L <= 4 MAXB NT) in LDS, run by
+// all NT threads of the workgroup; dir = -1: exp(-2 pi i jk/L), +1: exp(+...).
+// Unnormalised. Radix-8 passes as far as lg allows, the remainder of lg mod 3
+// taken by radix-4 passes (or one radix-2 pass for L = 2), the smaller radices
+// first. tw[t] = exp(-2 pi i t / tw_len), t < tw_len / 4 (in LDS). The caller
+// synchronises before the call; the last pass ends with a barrier.
 template <class C, int NT, int MAXB>
 __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
                                          const typename CT<C>::V* __restrict__ tw, int tw_len) {
-  using V = typename CT<C>::V;
+  constexpr int NB8 = (MAXB + 1) / 2;   // radix-8 butterflies per thread: L / 8 <= NB8 NT
   const int L = 1 << lg;
-  const int tid = threadIdx.x;
-  const C sd = (C)dir;
-  int Ns = 1;
-  int rem = lg;
-  while (Ns < L) {
-    const bool r2 = (rem & 1) != 0;
-    V v[4 * MAXB];
-    if (!r2) {
-      const int nb = L / 4;
-#pragma unroll
-      for (int b = 0; b < MAXB; ++b) {
-        const int j = tid + b * NT;
-        if (j < nb) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) v[4 * b + r] = x[j + r * nb];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < MAXB; ++b) {
-        const int j = tid + b * NT;
-        if (j < nb) {
-          const int k = j & (Ns - 1);
-          V w = tw[k * (tw_len / (Ns * 4))];
-          if (dir > 0) w.y = -w.y;
-          const V w2 = cmul(w, w), w3 = cmul(w2, w);
-          V a0 = v[4 * b], a1 = cmul(v[4 * b + 1], w), a2 = cmul(v[4 * b + 2], w2), a3 = cmul(v[4 * b + 3], w3);
-          dft4(a0, a1, a2, a3, sd);
-          const int idx = (j - k) * 4 + k;
-          x[idx] = a0;
-          x[idx + Ns] = a1;
-          x[idx + 2 * Ns] = a2;
-          x[idx + 3 * Ns] = a3;
-        }
-      }
-      Ns *= 4;
-      rem -= 2;
+  int n8 = lg / 3, n4 = 0, n2 = 0;
+  if (lg % 3 == 2) {
+    n4 = 1;
+  } else if (lg % 3 == 1) {
+    if (n8 > 0) {
+      n8 -= 1;
+      n4 = 2;
     } else {
-      const int nb = L / 2;
-#pragma unroll
-      for (int b = 0; b < 2 * MAXB; ++b) {
-        const int j = tid + b * NT;
-        if (j < nb) {
-          v[2 * b] = x[j];
-          v[2 * b + 1] = x[j + nb];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < 2 * MAXB; ++b) {
-        const int j = tid + b * NT;
-        if (j < nb) {
-          const int k = j & (Ns - 1);
-          V w = tw[k * (tw_len / (Ns * 2))];
-          if (dir > 0) w.y = -w.y;
-          const V a0 = v[2 * b], a1 = cmul(v[2 * b + 1], w);
-          const int idx = (j - k) * 2 + k;
-          x[idx] = cadd(a0, a1);
-          x[idx + Ns] = csub(a0, a1);
-        }
-      }
-      Ns *= 2;
-      rem -= 1;
+      n2 = 1;
     }
-    __syncthreads();
+  }
+  int Ns = 1;
+  if (n2) {
+    stockham_pass<C, NT, 2, 2 * MAXB>(x, L, Ns, dir, tw, tw_len);
+    Ns *= 2;
+  }
+  for (int p = 0; p < n4; ++p) {
+    stockham_pass<C, NT, 4, MAXB>(x, L, Ns, dir, tw, tw_len);
+    Ns *= 4;
+  }
+  for (int p = 0; p < n8; ++p) {
+    stockham_pass<C, NT, 8, NB8>(x, L, Ns, dir, tw, tw_len);
+    Ns *= 8;
   }
 }
 
