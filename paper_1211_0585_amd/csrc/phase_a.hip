@@ -27,10 +27,11 @@
 // between two registers, so a step is one multiply and one FMA and no moves.
 //
 // Each work item is (m, block of 64 R ring pairs) handled by one wavefront; a
-// lane owns R ring pairs. The analysis reduces over lanes through LDS once per
-// chunk of 16 values of l and writes one partial sum per block; a small kernel
-// sums the partials of each (l, m), applies the filter and scales by C; the
-// synthesis reads those coefficients as wave-uniform (scalar) values per chunk.
+// lane owns R ring pairs. The recurrence coefficients (and, in the synthesis, the
+// filtered a_lm) are fetched 64 values of l ahead with one vector load and read
+// from LDS. The analysis reduces over lanes through LDS once per chunk of 16
+// values of l and writes one partial sum per block; a small kernel sums the
+// partials of each (l, m), applies the filter and scales by C for the synthesis.
 #include "mwf_internal.hpp"
 
 namespace mwf {
@@ -127,6 +128,8 @@ __device__ __forceinline__ int rescale_chunk(RingState<R>& st) {
   return woke;
 }
 
+constexpr int LTILE = 64;  // values of l per prefetched coefficient tile (one per lane)
+
 template <int R>
 __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
     PlanDev P, const WorkItem* __restrict__ items, const double* __restrict__ G,
@@ -162,11 +165,31 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
   double* out = reinterpret_cast<double*>(partial + ((size_t)map * P.nblk_max + blk) * P.nalm);
   const int64_t row = alm_index(lmax, m, m);
 
+  // recurrence coefficients of LTILE values of l: lane i loads l = base + i one
+  // tile ahead, the tile in use is read from LDS (the same address in every lane).
+  // The loads are unconditional, with the index clamped to nl (the first entry of
+  // the row's zero padding), so that no wait for them lands inside the loop.
+  __shared__ double sA[LTILE];
+  const int nl = lmax - m + 1;
+  auto tile_a = [&](int i) { return Arow[min(i, nl)]; };
+  sA[lane] = tile_a(lane);
+  // every load issued so far (ring seeds, S/D, tile 0) completes here, so the loop
+  // body waits on nothing but its own LDS reads
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  double An = tile_a(LTILE + lane);
+
   for (int l0 = m; l0 <= lmax; l0 += CHUNK) {
+    const int t0 = (l0 - m) & (LTILE - 1);
+    if (t0 == 0 && l0 > m) {
+      sA[lane] = An;      // the previous tile's last readers passed the barrier below
+      __syncthreads();
+      An = tile_a(l0 - m + LTILE + lane);
+    }
     double are[CHUNK], aim[CHUNK];
 #pragma unroll
     for (int j = 0; j < CHUNK; ++j) are[j] = aim[j] = 0.0;
-    const double* Ac = Arow + (l0 - m);
+    const double* Ac = sA + t0;
 #pragma unroll
     for (int j = 0; j < CHUNK; j += 2) {
       const double A0 = Ac[j], A1 = Ac[j + 1];
@@ -218,6 +241,9 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
           Dre[r] = sd.z;
           Dim[r] = sd.w;
         }
+      // (rare) complete these loads here rather than at their first use, where the
+      // wait would also cover the tile prefetch
+      __builtin_amdgcn_s_waitcnt(0);
     }
   }
 }
@@ -287,20 +313,46 @@ __global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
   const double2* __restrict__ brow = a.bcoef + (size_t)map * P.rows_total + roff;
 
   const int nact = P.n_active[m];
+  const int nl = lmax - m + 1;
+  // coefficients of LTILE values of l: lane i loads l = base + i one tile ahead,
+  // the tile in use is read from LDS (the same address in every lane). The loads
+  // are unconditional, with the index clamped to nl (the first entry of the row's
+  // zero padding: A is zero there and the coefficient kernel writes zeros past
+  // lmax), so that no wait for them lands inside the loop.
+  __shared__ double sA[LTILE];
+  __shared__ double2 sb[LTILE];
+  auto tile_a = [&](int i) { return Arow[min(i, nl)]; };
+  auto tile_b = [&](int i) { return brow[min(i, nl)]; };
   RingState<R> st;
   init_rings<R>(P, m, blk, lane, nact, st);
+  sA[lane] = tile_a(lane);
+  sb[lane] = tile_b(lane);
+  // every load issued so far (ring seeds, tile 0) completes here, so the loop body
+  // waits on nothing but its own LDS reads
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  double An = tile_a(LTILE + lane);
+  double2 bn = tile_b(LTILE + lane);
   double Ere[R], Eim[R], Ore[R], Oim[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
 
   for (int l0 = m; l0 <= lmax; l0 += SCH) {
-    // wave-uniform coefficients of this chunk (scalar loads)
+    const int t0 = (l0 - m) & (LTILE - 1);
+    if (t0 == 0 && l0 > m) {
+      __syncthreads();
+      sA[lane] = An;
+      sb[lane] = bn;
+      __syncthreads();
+      An = tile_a(l0 - m + LTILE + lane);
+      bn = tile_b(l0 - m + LTILE + lane);
+    }
     double A[SCH];
     double2 b[SCH];
 #pragma unroll
     for (int j = 0; j < SCH; ++j) {
-      A[j] = Arow[l0 - m + j];
-      b[j] = brow[l0 - m + j];
+      A[j] = sA[t0 + j];
+      b[j] = sb[t0 + j];
     }
     int scaled = 0;
 #pragma unroll
