@@ -755,29 +755,30 @@ TaskDev make_task(wf_plan_s* p, int nmaps, int pb_mode, int sy_mode, double lam,
   return t;
 }
 
-// One step of a task array already on the device: the two ring launches, then
-// (unless synth_only) analysis, coefficients and synthesis, one launch each.
-int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const int* fft_len,
+// One step of a task array (host memory; the entries travel as kernel arguments):
+// the ring launches, then (unless synth_only) analysis, coefficients and synthesis,
+// one launch each (per part of at most GROUP_MAX_TASKS tasks).
+int run_group_step(const TaskDev* tasks, const int64_t* offs, const int64_t* nblocks, const int* fft_len,
                    int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s) {
   const int stride = ntasks + 1;
-  GroupLaunch g{d_tasks, d_offs, ntasks, 0, nblocks[0]};
+  GroupLaunch g{tasks, offs, ntasks, 0, nblocks[0]};
   TIMED(0, {
     for (int c = 0; c < NRING_CLASSES; ++c) {
-      g.offs = d_offs + c * stride;
+      g.offs = offs + c * stride;
       g.nblocks = nblocks[c];
       MWF_HIP(launch_group_phase_b(g, c, fft_len[c], s));
     }
   });
   if (synth_only) return WF_OK;
   const int a0 = NRING_CLASSES;
-  g.offs = d_offs + a0 * stride;
+  g.offs = offs + a0 * stride;
   g.nblocks = nblocks[a0];
   TIMED(1, MWF_HIP(launch_group_analysis(g, dtype, tune.ana_ct, s)));
   TIMED(2, {
-    g.offs = d_offs + (a0 + 1) * stride;
+    g.offs = offs + (a0 + 1) * stride;
     g.nblocks = nblocks[a0 + 1];
     MWF_HIP(launch_group_coeff(g, 128 * tune.ana_ct, s));
-    g.offs = d_offs + (a0 + 2) * stride;
+    g.offs = offs + (a0 + 2) * stride;
     g.nblocks = nblocks[a0 + 2];
     MWF_HIP(launch_group_synthesis(g, dtype, tune.syn_nct, 128 * tune.ana_ct, s));
   });
@@ -810,8 +811,13 @@ int wf_group_create(wf_group_t* out, int32_t nplans, const wf_plan_t* plans, con
     gr->plans.push_back(p);
     gr->nmaps.push_back(nmaps[i]);
   }
+  gr->order.resize(nplans);
+  for (int i = 0; i < nplans; ++i) gr->order[i] = i;
+  std::stable_sort(gr->order.begin(), gr->order.end(), [&](int a, int b) {
+    const int la = gr->plans[a]->geo->lmax, lb = gr->plans[b]->geo->lmax;
+    return la != lb ? la > lb : gr->nmaps[a] > gr->nmaps[b];
+  });
   gr->tune = plans[0]->tune;
-  gr->mem.reset(new DevMem());
   *out = gr;
   return WF_OK;
 }
@@ -835,10 +841,11 @@ int wf_group_solve(wf_group_t gr, const void* const* d, void* const* s_wf, void*
   // one task array per step: sweeps 0..nsweeps-1, then the final synthesis
   std::vector<TaskDev> host((size_t)(nsweeps + 1) * nt);
   for (int k = 0; k <= nsweeps; ++k)
-    for (int t = 0; t < nt; ++t) {
+    for (int i = 0; i < nt; ++i) {
+      const int t = gr->order[i];
       wf_plan_s* p = gr->plans[t];
       p->last_stream = s;
-      TaskDev& T = host[(size_t)k * nt + t];
+      TaskDev& T = host[(size_t)k * nt + i];
       if (k < nsweeps) {
         const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
         T = make_task(p, gr->nmaps[t], mode, SY_FROM_PARTIAL, lambda[k], d[t], nullptr,
@@ -847,27 +854,16 @@ int wf_group_solve(wf_group_t gr, const void* const* d, void* const* s_wf, void*
         T = make_task(p, gr->nmaps[t], PB_SYNTH | PB_WRITE_MAP, SY_FROM_PARTIAL, 1.0, nullptr, s_wf[t], nullptr);
       }
     }
-  MWF_HIP(hipStreamSynchronize(s));   // an earlier solve may still read the task arrays
-  if (host.size() > gr->d_tasks_cap) {
-    gr->mem.reset(new DevMem());
-    gr->d_tasks = nullptr;
-    gr->d_offs = nullptr;
-    if ((rc = gr->mem->alloc(&gr->d_tasks, host.size()))) return rc;
-    if ((rc = gr->mem->alloc(&gr->d_offs, NPHASE * (size_t)(nt + 1)))) return rc;
-    gr->d_tasks_cap = host.size();
-  }
   std::vector<const Geometry*> geos;
-  for (int t = 0; t < nt; ++t) geos.push_back(gr->plans[t]->geo.get());
+  for (int i = 0; i < nt; ++i) geos.push_back(gr->plans[gr->order[i]]->geo.get());
   std::vector<int64_t> offs;
   task_offsets(host.data(), geos, gr->tune, offs, gr->nblocks, gr->fft_len, nullptr);
-  MWF_HIP(hipMemcpy(gr->d_tasks, host.data(), host.size() * sizeof(TaskDev), hipMemcpyHostToDevice));
-  MWF_HIP(hipMemcpy(gr->d_offs, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   Timer timer;
   timer.on = (gr->plans[0]->flags & WF_FLAG_TIMING) != 0;
   timer.s = s;
   TimerScope scope(&timer);
   for (int k = 0; k <= nsweeps; ++k)
-    if ((rc = run_group_step(gr->d_tasks + (size_t)k * nt, gr->d_offs, gr->nblocks, gr->fft_len, nt, gr->dtype,
+    if ((rc = run_group_step(host.data() + (size_t)k * nt, offs.data(), gr->nblocks, gr->fft_len, nt, gr->dtype,
                              gr->tune, k == nsweeps, s)))
       return rc;
   if (stats) {

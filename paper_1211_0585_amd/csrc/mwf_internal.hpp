@@ -253,13 +253,55 @@ struct TaskDev {
   int32_t ring_n[NRING_CLASSES];
 };
 
+// One phase of a task group, described on the host: the tasks and, per task, the
+// first block of the launch (offs[t] <= block < offs[t + 1], offs[ntasks] blocks).
 struct GroupLaunch {
-  const TaskDev* tasks;     // device
-  const int64_t* offs;      // device, ntasks + 1 block offsets
+  const TaskDev* tasks;     // host
+  const int64_t* offs;      // host, ntasks + 1 block offsets
   int32_t ntasks;
   int32_t pad_;
   int64_t nblocks;
 };
+
+// What a group kernel receives, by value: up to GROUP_MAX_TASKS tasks and their block
+// offsets (relative to the launch). Passing the task entries as kernel arguments,
+// not through a device table, lets the compiler treat their pointers as global and
+// emit global rather than flat memory instructions; it also needs no upload. A
+// group with more tasks is launched in several parts.
+constexpr int GROUP_MAX_TASKS = 8;
+struct GroupArgs {
+  TaskDev t[GROUP_MAX_TASKS];
+  int64_t offs[GROUP_MAX_TASKS + 1];
+  int32_t ntasks;
+  int32_t pad_;
+};
+static_assert(sizeof(GroupArgs) <= 3584, "group kernel arguments must stay well under 4 KiB");
+
+// The task of block b: offs[t] <= b < offs[t + 1].
+__device__ __forceinline__ int group_task_of(const GroupArgs& g, int64_t b) {
+  int lo = 0, hi = g.ntasks - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.offs[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Launches a phase of a group in parts of at most GROUP_MAX_TASKS tasks:
+// launch(args, nblocks) for each part with blocks.
+template <class F>
+hipError_t for_each_group_part(const GroupLaunch& g, F launch) {
+  for (int t0 = 0; t0 < g.ntasks; t0 += GROUP_MAX_TASKS) {
+    const int n = g.ntasks - t0 < GROUP_MAX_TASKS ? g.ntasks - t0 : GROUP_MAX_TASKS;
+    GroupArgs a{};
+    a.ntasks = n;
+    for (int i = 0; i < n; ++i) a.t[i] = g.tasks[t0 + i];
+    for (int i = 0; i <= n; ++i) a.offs[i] = g.offs[t0 + i] - g.offs[t0];
+    if (a.offs[n] == 0) continue;
+    if (hipError_t e = launch(a, a.offs[n])) return e;
+  }
+  return hipSuccess;
+}
 
 hipError_t launch_group_analysis(const GroupLaunch& g, int mode, int ct, hipStream_t s);
 hipError_t launch_group_coeff(const GroupLaunch& g, int ana_rb, hipStream_t s);

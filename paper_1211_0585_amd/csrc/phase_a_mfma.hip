@@ -490,16 +490,6 @@ __global__ void __launch_bounds__(COEFF_THREADS) mfma_coeff_kernel(PlanDev P, Mf
   if (a.chi2 != nullptr && a.mode == SY_FROM_PARTIAL) coeff_chi2(a, e, valid, v);
 }
 
-// Task groups: block b belongs to the task t with offs[t] <= b < offs[t + 1].
-__device__ __forceinline__ int find_task(const int64_t* __restrict__ offs, int ntasks, int64_t b) {
-  int lo = 0, hi = ntasks - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (offs[mid] <= b) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ MfmaArgs task_args(const TaskDev& t, int ana_rb) {
   MfmaArgs a{};
   a.mode = t.sy_mode;
@@ -518,32 +508,28 @@ __device__ __forceinline__ MfmaArgs task_args(const TaskDev& t, int ana_rb) {
 }
 
 template <int NP, int CT>
-__global__ void __launch_bounds__(128 * CT) group_analysis_kernel(const TaskDev* __restrict__ tasks,
-                                                                  const int64_t* __restrict__ offs, int ntasks) {
-  const int t = find_task(offs, ntasks, blockIdx.x);
-  const TaskDev& T = tasks[t];
-  const int64_t local = blockIdx.x - offs[t];
+__global__ void __launch_bounds__(128 * CT) group_analysis_kernel(GroupArgs g) {
+  const int t = group_task_of(g, blockIdx.x);
+  const TaskDev& T = g.t[t];
+  const int64_t local = blockIdx.x - g.offs[t];
   const int ncg = (2 * T.nmaps + 16 * CT - 1) / (16 * CT);
   const WorkItem* items = CT == 1 ? T.items_a128 : T.items_a256;
   analysis_body<NP, CT>(T.P, task_args(T, 128 * CT), items[local / ncg], (int)(local % ncg));
 }
 
 template <int NP, int NCT>
-__global__ void __launch_bounds__(64) group_synthesis_kernel(const TaskDev* __restrict__ tasks,
-                                                             const int64_t* __restrict__ offs, int ntasks,
-                                                             int ana_rb) {
-  const int t = find_task(offs, ntasks, blockIdx.x);
-  const TaskDev& T = tasks[t];
-  const int64_t local = blockIdx.x - offs[t];
+__global__ void __launch_bounds__(64) group_synthesis_kernel(GroupArgs g, int ana_rb) {
+  const int t = group_task_of(g, blockIdx.x);
+  const TaskDev& T = g.t[t];
+  const int64_t local = blockIdx.x - g.offs[t];
   const int ncg = (2 * T.nmaps + 16 * NCT - 1) / (16 * NCT);
   synthesis_body<NP, NCT>(T.P, task_args(T, ana_rb), T.items_s64[local / ncg], (int)(local % ncg));
 }
 
-__global__ void __launch_bounds__(COEFF_THREADS) group_coeff_kernel(const TaskDev* __restrict__ tasks, const int64_t* __restrict__ offs,
-                                   int ntasks, int ana_rb) {
-  const int t = find_task(offs, ntasks, blockIdx.x);
-  const TaskDev& T = tasks[t];
-  const int64_t e = (blockIdx.x - offs[t]) * COEFF_THREADS + threadIdx.x;
+__global__ void __launch_bounds__(COEFF_THREADS) group_coeff_kernel(GroupArgs g, int ana_rb) {
+  const int t = group_task_of(g, blockIdx.x);
+  const TaskDev& T = g.t[t];
+  const int64_t e = (blockIdx.x - g.offs[t]) * COEFF_THREADS + threadIdx.x;
   double v = 0.0;
   if (e < T.P.rows_total * T.nmaps) coeff_elem(T.P, task_args(T, ana_rb), e, &v);
 }
@@ -583,32 +569,29 @@ hipError_t syn_np(const PlanDev& P, const WorkItem* items, int nitems, int nct, 
 
 template <int NP>
 hipError_t gana_np(const GroupLaunch& g, int ct, hipStream_t s) {
-  if (ct == 1)
-    hipLaunchKernelGGL((group_analysis_kernel<NP, 1>), dim3(g.nblocks), dim3(128), 0, s, g.tasks, g.offs, g.ntasks);
-  else
-    hipLaunchKernelGGL((group_analysis_kernel<NP, 2>), dim3(g.nblocks), dim3(256), 0, s, g.tasks, g.offs, g.ntasks);
-  return hipGetLastError();
+  return for_each_group_part(g, [&](const GroupArgs& a, int64_t nb) {
+    if (ct == 1)
+      hipLaunchKernelGGL((group_analysis_kernel<NP, 1>), dim3(nb), dim3(128), 0, s, a);
+    else
+      hipLaunchKernelGGL((group_analysis_kernel<NP, 2>), dim3(nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+  });
 }
 
 template <int NP>
 hipError_t gsyn_np(const GroupLaunch& g, int nct, int ana_rb, hipStream_t s) {
-  if (nct == 1)
-    hipLaunchKernelGGL((group_synthesis_kernel<NP, 1>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
-                       ana_rb);
-  else if (nct == 2)
-    hipLaunchKernelGGL((group_synthesis_kernel<NP, 2>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
-                       ana_rb);
-  else if (nct == 4)
-    hipLaunchKernelGGL((group_synthesis_kernel<NP, 4>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
-                       ana_rb);
-  else if constexpr (NP == 1) {
-    if (nct != 8) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((group_synthesis_kernel<NP, 8>), dim3(g.nblocks), dim3(64), 0, s, g.tasks, g.offs, g.ntasks,
-                       ana_rb);
-  } else {
-    return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  if (nct != 1 && nct != 2 && nct != 4 && !(NP == 1 && nct == 8)) return hipErrorInvalidValue;
+  return for_each_group_part(g, [&](const GroupArgs& a, int64_t nb) {
+    if (nct == 1)
+      hipLaunchKernelGGL((group_synthesis_kernel<NP, 1>), dim3(nb), dim3(64), 0, s, a, ana_rb);
+    else if (nct == 2)
+      hipLaunchKernelGGL((group_synthesis_kernel<NP, 2>), dim3(nb), dim3(64), 0, s, a, ana_rb);
+    else if (nct == 4)
+      hipLaunchKernelGGL((group_synthesis_kernel<NP, 4>), dim3(nb), dim3(64), 0, s, a, ana_rb);
+    else if constexpr (NP == 1)
+      hipLaunchKernelGGL((group_synthesis_kernel<NP, 8>), dim3(nb), dim3(64), 0, s, a, ana_rb);
+    return hipGetLastError();
+  });
 }
 
 }  // namespace
@@ -643,9 +626,10 @@ hipError_t launch_group_analysis(const GroupLaunch& g, int mode, int ct, hipStre
 
 hipError_t launch_group_coeff(const GroupLaunch& g, int ana_rb, hipStream_t s) {
   if (g.nblocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(group_coeff_kernel, dim3(g.nblocks), dim3(COEFF_THREADS), 0, s, g.tasks, g.offs, g.ntasks,
-                     ana_rb);
-  return hipGetLastError();
+  return for_each_group_part(g, [&](const GroupArgs& a, int64_t nb) {
+    hipLaunchKernelGGL(group_coeff_kernel, dim3(nb), dim3(COEFF_THREADS), 0, s, a, ana_rb);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_group_synthesis(const GroupLaunch& g, int mode, int nct, int ana_rb, hipStream_t s) {

@@ -617,17 +617,10 @@ __global__ void __launch_bounds__(NT) phase_b_kernel(PlanDev P, PhaseBArgs a, co
 // (b - offs[t]) / nmaps of the task's ring-pair list of class CLS and map
 // (b - offs[t]) % nmaps.
 template <int NT, int CLS, int MAXB>
-__global__ void __launch_bounds__(NT) group_phase_b_kernel(const TaskDev* __restrict__ tasks,
-                                                           const int64_t* __restrict__ offs, int ntasks,
-                                                           int buf_elems) {
-  int lo = 0, hi = ntasks - 1;
-  const int64_t b = blockIdx.x;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (offs[mid] <= b) lo = mid; else hi = mid - 1;
-  }
-  const TaskDev& t = tasks[lo];
-  const int64_t local = b - offs[lo];
+__global__ void __launch_bounds__(NT) group_phase_b_kernel(GroupArgs g, int buf_elems) {
+  const int lo = group_task_of(g, blockIdx.x);
+  const TaskDev& t = g.t[lo];
+  const int64_t local = blockIdx.x - g.offs[lo];
   PhaseBArgs a{};
   a.mode = t.pb_mode;
   a.nmaps = t.nmaps;
@@ -694,9 +687,10 @@ hipError_t group_class_b(const GroupLaunch& g, int fft_len, hipStream_t s) {
   static size_t attr = 0;
   const size_t lds = ring_lds_bytes(fft_len, sizeof(float2));
   if (hipError_t e = set_lds(group_phase_b_kernel<NT, CLS, MAXB>, lds, &attr)) return e;
-  hipLaunchKernelGGL((group_phase_b_kernel<NT, CLS, MAXB>), dim3(g.nblocks), dim3(NT), lds, s, g.tasks, g.offs,
-                     g.ntasks, fft_len);
-  return hipGetLastError();
+  return for_each_group_part(g, [&](const GroupArgs& a, int64_t nb) {
+    hipLaunchKernelGGL((group_phase_b_kernel<NT, CLS, MAXB>), dim3(nb), dim3(NT), lds, s, a, fft_len);
+    return hipGetLastError();
+  });
 }
 
 template <int NT, int CLS>

@@ -120,7 +120,8 @@ void task_offsets(const TaskDev* tasks, const std::vector<const Geometry*>& geos
                   std::vector<int64_t>& offs, int64_t* nblocks, int* fft_len, const std::vector<char>* gemm);
 TaskDev make_task(wf_plan_s* p, int nmaps, int pb_mode, int sy_mode, double lam, const void* d,
                   void* map_out, void* alm_out);
-int run_group_step(const TaskDev* d_tasks, const int64_t* d_offs, const int64_t* nblocks, const int* fft_len,
+// tasks and offs ([NPHASE][ntasks + 1]) in host memory; see GroupLaunch.
+int run_group_step(const TaskDev* tasks, const int64_t* offs, const int64_t* nblocks, const int* fft_len,
                    int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s);
 size_t plan_buffer_bytes(int nside, int lmax, int dtype, int nmaps);
 size_t geometry_bytes(int nside, int lmax);
@@ -166,13 +167,11 @@ struct wf_plan_s {
 struct wf_group_s {
   std::vector<wf_plan_t> plans;
   std::vector<int32_t> nmaps;
+  // launch order of the tasks: descending lmax, then descending map count, so the
+  // longest Legendre work items of the group are dispatched first
+  std::vector<int> order;
   int dtype = WF_F32;
   mwf::Tuning tune;
   int fft_len[mwf::NRING_CLASSES] = {};  // longest transform of each ring launch class
-  // per solve: one TaskDev array per step (sweeps + final synthesis)
-  mwf::TaskDev* d_tasks = nullptr;
-  size_t d_tasks_cap = 0;
-  int64_t* d_offs = nullptr;           // [NPHASE][ntasks + 1]
   int64_t nblocks[mwf::NPHASE] = {};
-  std::unique_ptr<mwf::DevMem> mem;
 };

@@ -436,8 +436,10 @@ struct wf_server_s {
     MWF_HIP(hipMemcpyAsync(db, hb, off, hipMemcpyHostToDevice, stream));
     MWF_HIP(hipEventRecord(stage_ev[r], stream));
     for (const Launch& ln : launches) {
-      const auto* tasks = reinterpret_cast<const TaskDev*>(db + ln.tasks_off);
-      const auto* offs = reinterpret_cast<const int64_t*>(db + ln.offs_off);
+      // the task entries travel as kernel arguments (copied at launch); the slot
+      // parameters they point to are read from the device copy of the block
+      const auto* tasks = reinterpret_cast<const TaskDev*>(hb + ln.tasks_off);
+      const auto* offs = reinterpret_cast<const int64_t*>(hb + ln.offs_off);
       if (int rc = run_group_step(tasks, offs, ln.nblocks, ln.fft_len, ln.ntasks, ln.dtype, ln.tune, false, stream))
         return rc;
     }

@@ -139,3 +139,32 @@ def test_group_rejects_bad_input(torch_dev, cases):
     assert e.value.code == mwf.WF_EINVAL
     for p in (p64, p32, pbf):
         p.close()
+
+
+def test_group_of_more_tasks_than_one_launch_holds(torch_dev):
+    """A group larger than the tasks one launch carries runs each phase in parts;
+    every member must still equal its plan solved alone."""
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    shapes = [(8, 16, 1), (16, 32, 2), (8, 12, 3), (16, 24, 1), (32, 64, 1), (8, 16, 2), (16, 32, 1),
+              (8, 10, 1), (16, 20, 2), (8, 16, 1), (32, 40, 1)]
+    plans, ds = [], []
+    for i, (nside, lmax, nm) in enumerate(shapes):
+        c = small_band_inputs(nside, lmax, seed=200 + i)
+        plans.append(mwf.Plan(nside, lmax, c["cl"], c["ninv"], dtype=mwf.WF_F32, max_batch=nm))
+        d = np.stack([small_band_inputs(nside, lmax, seed=300 + 10 * i + j)["d"] for j in range(nm)])
+        ds.append(torch.from_numpy(d.astype(np.float32)).cuda())
+    g = mwf.Group(plans, [s[2] for s in shapes])
+    gw, ga = g.solve(ds, LAMS)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, p in enumerate(plans):
+        sw, sa = p.solve(ds[i], LAMS)
+        p.sync()
+        e = rel_l2(gw[i].cpu().numpy(), sw.cpu().numpy())
+        worst = max(worst, e)
+        assert e <= 1e-6, (i, shapes[i], e)
+    _log(f"group of {len(shapes)} tasks vs separate: worst {worst:.2e}")
+    g.close()
+    for p in plans:
+        p.close()
