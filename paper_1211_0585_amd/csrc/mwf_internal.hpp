@@ -153,10 +153,47 @@ struct RingClass {
 constexpr int NRING_CLASSES = 3;
 constexpr int RING_SPLIT_MAPS = 4;
 
-// Dynamic LDS of a ring launch: the data of fft_len points plus their twiddles.
-// (At least 8 KiB: short rings stage 512 partial sums of two complex doubles.)
+// Pass schedule of the in-place Stockham FFT of 2^lg points (lg >= 1): n2 radix-2,
+// n4 radix-4 and n8 radix-8 passes in that order (radix 8 as far as lg allows).
+__host__ __device__ inline void fft_schedule(int lg, int* n2, int* n4, int* n8) {
+  *n8 = lg / 3;
+  *n4 = 0;
+  *n2 = 0;
+  if (lg % 3 == 2) {
+    *n4 = 1;
+  } else if (lg % 3 == 1) {
+    if (*n8 > 0) {
+      *n8 -= 1;
+      *n4 = 2;
+    } else {
+      *n2 = 1;
+    }
+  }
+}
+
+// Entries of one per-pass twiddle table set of a 2^lg-point FFT: the sum of Ns over
+// the passes that multiply by twiddles (Ns > 1), Ns the points combined before the pass.
+__host__ __device__ inline int fft_twiddle_entries(int lg) {
+  int n2, n4, n8;
+  fft_schedule(lg, &n2, &n4, &n8);
+  int ns = 1, e = 0;
+  for (int p = 0; p < n2; ++p, ns *= 2) e += ns > 1 ? ns : 0;
+  for (int p = 0; p < n4; ++p, ns *= 4) e += ns > 1 ? ns : 0;
+  for (int p = 0; p < n8; ++p, ns *= 8) e += ns > 1 ? ns : 0;
+  return e;
+}
+
+// Points of the FFT buffer in LDS including the padding of the layout between
+// passes (one element after every 16).
+__host__ __device__ inline int fft_padded(int len) { return len + (len >> 4); }
+
+// Dynamic LDS of a ring launch: the padded data of fft_len points plus the twiddle
+// table of its passes (w per pass; the powers of w are formed by products). (At
+// least 8 KiB: short rings stage 512 partial sums of two complex doubles.)
 inline size_t ring_lds_bytes(int fft_len, size_t elem) {
-  const size_t b = (size_t)fft_len * elem + (size_t)(fft_len / 4) * elem;
+  int lg = 0;
+  while ((1 << lg) < fft_len) ++lg;
+  const size_t b = ((size_t)fft_padded(fft_len) + (size_t)fft_twiddle_entries(lg)) * elem;
   return b < 8192 ? 8192 : b;
 }
 

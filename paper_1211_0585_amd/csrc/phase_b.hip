@@ -30,7 +30,9 @@
 // to the class: the Bluestein length is about twice the ring's), and, from 4 maps
 // on, transforms of at most 1024 points one wave per ring pair, so short polar
 // rings do not leave most of a large workgroup idle. Each workgroup stages the
-// twiddles of its ring's transform length in LDS next to the data.
+// twiddles of its ring's transform in LDS next to the data, one table per pass
+// read by consecutive lanes at consecutive entries, and the data sit in a padded
+// layout between passes: both keep the passes' LDS accesses off shared banks.
 #include "mwf_internal.hpp"
 
 namespace mwf {
@@ -137,25 +139,30 @@ __device__ __forceinline__ void dft8(V* v, S sd) {
 
 // One radix-R pass (R = 2, 4 or 8) of an in-place Stockham FFT of length L in LDS,
 // after Ns points have been combined: butterfly j (j < L / R, k = j mod Ns) takes
-// x[j + r L / R], r < R, multiplies input r by w^r with w = exp(dir 2 pi i k / (R Ns)),
-// takes its radix-R DFT and writes output r to x[(j - k) R + k + r Ns]. NBF
-// butterflies per thread; all inputs are read into registers before the barrier
-// that precedes the writes, so a single buffer suffices. tw[t] = exp(-2 pi i t /
-// tw_len), t < tw_len / 4.
+// input r < R from element j + r L / R, multiplies it by w^r with w = exp(dir 2 pi i
+// k / (R Ns)), takes its radix-R DFT and writes output r to element (j - k) R + k +
+// r Ns. NBF butterflies per thread; all inputs are read into registers before the
+// barrier that precedes the writes, so one buffer suffices and the layout may change
+// from pass to pass: element e sits at e (plain) or at fft_padded-style e + e / 16
+// (pad_in / pad_out), the padding that spreads the strided writes of the early
+// passes over the LDS banks. wk[k] = exp(-2 pi i k / (R Ns)), k < Ns: this pass's
+// twiddles, read by consecutive lanes at consecutive entries; the other powers are
+// products of it (at most three deep).
 template <class C, int NT, int R, int NBF>
-__device__ __forceinline__ void stockham_pass(typename CT<C>::V* x, int L, int Ns, int dir,
-                                              const typename CT<C>::V* __restrict__ tw, int tw_len) {
+__device__ __forceinline__ void stockham_pass(typename CT<C>::V* x, int L, int Ns, int dir, bool pad_in,
+                                              bool pad_out, const typename CT<C>::V* __restrict__ wk) {
   using V = typename CT<C>::V;
   const int tid = threadIdx.x;
   const C sd = (C)dir;
   const int nb = L / R;
+  auto at = [](int e, bool pad) { return pad ? e + (e >> 4) : e; };
   V v[R * NBF];
 #pragma unroll
   for (int b = 0; b < NBF; ++b) {
     const int j = tid + b * NT;
     if (j < nb) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[R * b + r] = x[j + r * nb];
+      for (int r = 0; r < R; ++r) v[R * b + r] = x[at(j + r * nb, pad_in)];
     }
   }
   __syncthreads();
@@ -166,36 +173,20 @@ __device__ __forceinline__ void stockham_pass(typename CT<C>::V* x, int L, int N
       const int k = j & (Ns - 1);
       V* u = v + R * b;
       if (Ns > 1) {
-        const int t1 = k * (tw_len / (Ns * R));
-        V w = tw[t1];
+        V w = wk[k];
         if (dir > 0) w.y = -w.y;
-        if (R == 2) {
-          u[1] = cmul(u[1], w);
-        } else if (R == 4) {
-          const V w2 = cmul(w, w), w3 = cmul(w2, w);
-          u[1] = cmul(u[1], w);
+        u[1] = cmul(u[1], w);
+        if (R >= 4) {
+          const V w2 = cmul(w, w), w3 = cmul(w, w2);
           u[2] = cmul(u[2], w2);
           u[3] = cmul(u[3], w3);
-        } else {
-          // w^2 (index 2 t1 < tw_len / 4) and w^4 from the table, the latter past a
-          // quarter turn as -i tw[t - tw_len / 4]; the other powers at most two
-          // products deep
-          const int q4 = tw_len / 4, t4 = 4 * t1;
-          V w2 = tw[2 * t1];
-          V w4 = tw[t4 < q4 ? t4 : t4 - q4];
-          if (t4 >= q4) w4 = CT<C>::make(w4.y, -w4.x);
-          if (dir > 0) {
-            w2.y = -w2.y;
-            w4.y = -w4.y;
+          if (R == 8) {
+            const V w4 = cmul(w2, w2);
+            u[4] = cmul(u[4], w4);
+            u[5] = cmul(u[5], cmul(w, w4));
+            u[6] = cmul(u[6], cmul(w2, w4));
+            u[7] = cmul(u[7], cmul(w3, w4));
           }
-          const V w3 = cmul(w, w2);
-          u[1] = cmul(u[1], w);
-          u[2] = cmul(u[2], w2);
-          u[3] = cmul(u[3], w3);
-          u[4] = cmul(u[4], w4);
-          u[5] = cmul(u[5], cmul(w, w4));
-          u[6] = cmul(u[6], cmul(w2, w4));
-          u[7] = cmul(u[7], cmul(w3, w4));
         }
       }
       if (R == 2) {
@@ -209,7 +200,7 @@ __device__ __forceinline__ void stockham_pass(typename CT<C>::V* x, int L, int N
       }
       const int idx = (j - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) x[idx + r * Ns] = u[r];
+      for (int r = 0; r < R; ++r) x[at(idx + r * Ns, pad_out)] = u[r];
     }
   }
   __syncthreads();
@@ -217,38 +208,59 @@ __device__ __forceinline__ void stockham_pass(typename CT<C>::V* x, int L, int N
 
 // In-place Stockham FFT of length L = 2^lg (2 <= L <= 4 MAXB NT) in LDS, run by
 // all NT threads of the workgroup; dir = -1: exp(-2 pi i jk/L), +1: exp(+...).
-// Unnormalised. Radix-8 passes as far as lg allows, the remainder of lg mod 3
-// taken by radix-4 passes (or one radix-2 pass for L = 2), the smaller radices
-// first. tw[t] = exp(-2 pi i t / tw_len), t < tw_len / 4 (in LDS). The caller
-// synchronises before the call; the last pass ends with a barrier.
+// Unnormalised. Passes as fft_schedule gives them (radix 8 as far as lg allows, the
+// smaller radices first). Input and output are in the plain layout; between passes
+// the data sit in the padded one, so the buffer holds fft_padded(L) elements. wt:
+// the per-pass twiddle tables in pass order (fft_twiddle_entries(lg) entries, see
+// stage_ring_twiddles). The caller synchronises before the call; the last pass ends
+// with a barrier.
 template <class C, int NT, int MAXB>
 __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
-                                         const typename CT<C>::V* __restrict__ tw, int tw_len) {
+                                         const typename CT<C>::V* __restrict__ wt) {
   constexpr int NB8 = (MAXB + 1) / 2;   // radix-8 butterflies per thread: L / 8 <= NB8 NT
   const int L = 1 << lg;
-  int n8 = lg / 3, n4 = 0, n2 = 0;
-  if (lg % 3 == 2) {
-    n4 = 1;
-  } else if (lg % 3 == 1) {
-    if (n8 > 0) {
-      n8 -= 1;
-      n4 = 2;
-    } else {
-      n2 = 1;
-    }
-  }
-  int Ns = 1;
+  int n2, n4, n8;
+  fft_schedule(lg, &n2, &n4, &n8);
+  const int last = n2 + n4 + n8 - 1;
+  int Ns = 1, p = 0, off = 0;
+  auto next = [&](int R) {
+    off += Ns > 1 ? Ns : 0;
+    Ns *= R;
+    ++p;
+  };
   if (n2) {
-    stockham_pass<C, NT, 2, 2 * MAXB>(x, L, Ns, dir, tw, tw_len);
-    Ns *= 2;
+    stockham_pass<C, NT, 2, 2 * MAXB>(x, L, Ns, dir, p > 0, p < last, wt + off);
+    next(2);
   }
-  for (int p = 0; p < n4; ++p) {
-    stockham_pass<C, NT, 4, MAXB>(x, L, Ns, dir, tw, tw_len);
-    Ns *= 4;
+  for (int q = 0; q < n4; ++q) {
+    stockham_pass<C, NT, 4, MAXB>(x, L, Ns, dir, p > 0, p < last, wt + off);
+    next(4);
   }
-  for (int p = 0; p < n8; ++p) {
-    stockham_pass<C, NT, 8, NB8>(x, L, Ns, dir, tw, tw_len);
-    Ns *= 8;
+  for (int q = 0; q < n8; ++q) {
+    stockham_pass<C, NT, 8, NB8>(x, L, Ns, dir, p > 0, p < last, wt + off);
+    next(8);
+  }
+}
+
+// The per-pass twiddle tables of a 2^lg-point transform into wt (LDS), from the plan's
+// table glob[t] = exp(-2 pi i t / glob_len), t < glob_len / 2: for each pass with
+// Ns > 1, wt[off + k] = exp(-2 pi i k / (R Ns)) = glob[k glob_len / (R Ns)], k < Ns.
+// Written by all threads; the caller's next barrier orders them before use.
+template <class C, int NT>
+__device__ __forceinline__ void stage_ring_twiddles(typename CT<C>::V* wt, int lg,
+                                                    const typename CT<C>::V* __restrict__ glob, int glob_len) {
+  int n2, n4, n8;
+  fft_schedule(lg, &n2, &n4, &n8);
+  const int np = n2 + n4 + n8;
+  int Ns = 1, off = 0;
+  for (int p = 0; p < np; ++p) {
+    const int R = p < n2 ? 2 : (p < n2 + n4 ? 4 : 8);
+    if (Ns > 1) {
+      const int stride = glob_len / (R * Ns);
+      for (int k = threadIdx.x; k < Ns; k += NT) wt[off + k] = glob[(size_t)k * stride];
+      off += Ns;
+    }
+    Ns *= R;
   }
 }
 
@@ -259,7 +271,7 @@ template <class C, int NT, int MAXB>
 __device__ void dft_bluestein(typename CT<C>::V* x, int n, int M, int lgM, int dir,
                               const typename CT<C>::V* __restrict__ chirp,
                               const typename CT<C>::V* __restrict__ H,
-                              const typename CT<C>::V* __restrict__ tw, int tw_len) {
+                              const typename CT<C>::V* __restrict__ wt) {
   using V = typename CT<C>::V;
   constexpr int NK = 4 * MAXB;     // M <= 4 MAXB NT
   constexpr int NJ = 2 * MAXB;     // n <= M / 2
@@ -290,14 +302,14 @@ __device__ void dft_bluestein(typename CT<C>::V* x, int n, int M, int lgM, int d
     }
   }
   __syncthreads();
-  fft_pow2<C, NT, MAXB>(x, lgM, -1, tw, tw_len);
+  fft_pow2<C, NT, MAXB>(x, lgM, -1, wt);
 #pragma unroll
   for (int u = 0; u < NK; ++u) {
     const int k = tid + u * NT;
     if (k < M) x[k] = cmul(x[k], hk[u]);
   }
   __syncthreads();
-  fft_pow2<C, NT, MAXB>(x, lgM, +1, tw, tw_len);
+  fft_pow2<C, NT, MAXB>(x, lgM, +1, wt);
   const C invM = (C)1 / (C)M;
 #pragma unroll
   for (int u = 0; u < NJ; ++u) {
@@ -336,10 +348,10 @@ template <class C, int NT, int MAXB, int KIND>
 __device__ __forceinline__ void ring_dft(typename CT<C>::V* buf, const typename CT<C>::V* twl,
                                          const RingPair& rp, int dir, const PlanDev& P) {
   if (KIND == 0 || (KIND == 2 && rp.log2n >= 0)) {
-    fft_pow2<C, NT, MAXB>(buf, rp.log2n, dir, twl, rp.nphi);
+    fft_pow2<C, NT, MAXB>(buf, rp.log2n, dir, twl);
   } else {
     dft_bluestein<C, NT, MAXB>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, Tabs<C>::chirp(P) + rp.chirp_off,
-                               Tabs<C>::blue(P) + rp.bl_off, twl, rp.bl_M);
+                               Tabs<C>::blue(P) + rp.bl_off, twl);
   }
 }
 
@@ -377,15 +389,14 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
   const T* __restrict__ q_tab = static_cast<const T*>(P.q) + (a.slots ? map * a.q_stride : 0);
 
-  // twiddles of this ring's FFT length into LDS, written at the end of the loading
-  // step (after any partial sums there are consumed) and ordered before their first
-  // use by the barrier that closes that step
-  V* twl = buf + buf_elems;
+  // per-pass twiddles of this ring's transform length into LDS (after the padded
+  // data buffer), written at the end of the loading step (after any partial sums
+  // there are consumed) and ordered before their first use by the barrier that
+  // closes that step
+  V* twl = buf + fft_padded(buf_elems);
   auto stage_twiddles = [&]() {
-    const int L = rp.log2n >= 0 ? n : rp.bl_M;
-    const V* __restrict__ twg = Tabs<C>::tw(P);
-    const int stride = P.tw_len / L;
-    for (int t = tid; t < L / 4; t += NT) twl[t] = twg[(size_t)t * stride];
+    const int lg = rp.log2n >= 0 ? rp.log2n : __ffs(rp.bl_M) - 1;
+    stage_ring_twiddles<C, NT>(twl, lg, Tabs<C>::tw(P), P.tw_len);
   };
 
   // ---- ring values into buf (x = north + i south)
