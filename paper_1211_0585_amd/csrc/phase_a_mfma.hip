@@ -291,21 +291,30 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
 #pragma unroll
       for (int eo = 0; eo < 2; ++eo) acc[qt][ct][eo] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
+  // FP32: B fragments of a chunk are loaded one chunk ahead (a chunk's MFMAs give
+  // them time to arrive). The loads are unconditional: columns past the last map are
+  // clamped to it (their results are never stored) and rows past lmax read the zero
+  // padding of the row (the next chunk of the last one ends at most 63 rows past it).
+  float bv[F32 ? 2 : 1][4][F32 ? NCT : 1];
+  auto load_b = [&](int l0, float (&dst)[F32 ? 2 : 1][4][F32 ? NCT : 1]) {
+#pragma unroll
+    for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const int rr = 4 * kk + (lane >> 4);
+          const int colg = min(cg * CW + ct * 16 + (lane & 15), ncols - 1);
+          dst[pp][kk][ct] = brow[(size_t)(l0 - m + 2 * rr + pp) * ncols + colg];
+        }
+  };
+  if constexpr (F32) load_b(m, bv);
+
   for (int l0 = m; l0 <= lmax; l0 += CHL) {
     const double* Ac = Arow + (l0 - m);
     if constexpr (F32) {
-      // B fragments of the whole chunk first: their latency hides behind the recurrence
-      float bv[2][4][NCT];
-#pragma unroll
-      for (int pp = 0; pp < 2; ++pp)
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-          for (int ct = 0; ct < NCT; ++ct) {
-            const int rr = 4 * kk + (lane >> 4);
-            const int colg = cg * CW + ct * 16 + (lane & 15);
-            bv[pp][kk][ct] = colg < ncols ? brow[(size_t)(l0 - m + 2 * rr + pp) * ncols + colg] : 0.0f;
-          }
+      float bn[2][4][NCT];
+      load_b(l0 + CHL, bn);
       ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][lane] = (float)v; });
       __syncthreads();
 #pragma unroll
@@ -322,6 +331,12 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
                   __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[pp][kk][ct], acc[qt][ct][pp], 0, 0, 0);
           }
         }
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+          for (int ct = 0; ct < NCT; ++ct) bv[pp][kk][ct] = bn[pp][kk][ct];
     } else {
       // B fragments straight from global: lane holds rows k8..k8+7 of one column
       const int k8 = 8 * (lane >> 4);
