@@ -129,12 +129,14 @@ __device__ __forceinline__ int rescale_chunk(RingState<R>& st) {
 }
 
 constexpr int LTILE = 64;  // values of l per prefetched coefficient tile (one per lane)
+constexpr int ACH = 16;    // analysis: values of l per cross-lane reduction (and scale check)
+static_assert(LTILE % ACH == 0 && (2 * ACH) <= LANES, "analysis chunking");
 
 template <int R>
 __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
     PlanDev P, const WorkItem* __restrict__ items, const double* __restrict__ G,
     double2* __restrict__ partial) {
-  __shared__ double red[2 * CHUNK][LANES / 2 + 1];
+  __shared__ double red[2 * ACH][LANES / 2 + 1];
   const WorkItem it = items[blockIdx.x];
   const int m = it.m, blk = it.blk, map = blockIdx.y;
   const int lane = threadIdx.x;
@@ -179,19 +181,19 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
   __syncthreads();
   double An = tile_a(LTILE + lane);
 
-  for (int l0 = m; l0 <= lmax; l0 += CHUNK) {
+  for (int l0 = m; l0 <= lmax; l0 += ACH) {
     const int t0 = (l0 - m) & (LTILE - 1);
     if (t0 == 0 && l0 > m) {
       sA[lane] = An;      // the previous tile's last readers passed the barrier below
       __syncthreads();
       An = tile_a(l0 - m + LTILE + lane);
     }
-    double are[CHUNK], aim[CHUNK];
+    double are[ACH], aim[ACH];
 #pragma unroll
-    for (int j = 0; j < CHUNK; ++j) are[j] = aim[j] = 0.0;
+    for (int j = 0; j < ACH; ++j) are[j] = aim[j] = 0.0;
     const double* Ac = sA + t0;
 #pragma unroll
-    for (int j = 0; j < CHUNK; j += 2) {
+    for (int j = 0; j < ACH; j += 2) {
       const double A0 = Ac[j], A1 = Ac[j + 1];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -204,24 +206,27 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
         aim[j + 1] = fma(st.mu1[r], Dim[r], aim[j + 1]);
       }
     }
-    // reduce the 32 values (v = 2 j + re/im) over the 64 lanes: first lanes l and
-    // l + 32 in registers, the lower half keeping values 0..15 and the upper half
-    // 16..31, then the remaining 32 lanes through LDS
+    // reduce the NV = 2 ACH values (v = 2 j + re/im) over the 64 lanes: first lanes
+    // l and l + 32 in registers, the lower half keeping values 0..NV/2-1 and the
+    // upper half the rest, then the remaining 32 lanes through LDS, LPV lanes per
+    // value each adding 32 / LPV entries, and LPV - 1 shuffles
+    constexpr int NV = 2 * ACH, LPV = LANES / NV;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int ja = i >> 1, jb = 8 + (i >> 1);
+    for (int i = 0; i < ACH; ++i) {
+      const int ja = i >> 1, jb = ACH / 2 + (i >> 1);
       const double va = (i & 1) ? aim[ja] : are[ja];
       const double vb = (i & 1) ? aim[jb] : are[jb];
-      red[i + ((lane >> 5) << 4)][lane & 31] = fold_halves(va, vb);
+      red[i + (lane >> 5) * ACH][lane & 31] = fold_halves(va, vb);
     }
     __syncthreads();
-    const int v = lane >> 1;
-    const int h = (lane & 1) * 16;
+    const int v = lane / LPV;
+    const int h = (lane % LPV) * (32 / LPV);
     double sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) sum += red[v][h + k];
-    sum += __shfl_xor(sum, 1);
-    if ((lane & 1) == 0) {
+    for (int k = 0; k < 32 / LPV; ++k) sum += red[v][h + k];
+#pragma unroll
+    for (int x = 1; x < LPV; x <<= 1) sum += __shfl_xor(sum, x);
+    if (lane % LPV == 0) {
       const int l = l0 + (v >> 1);
       if (l <= lmax) out[2 * (row + (l - m)) + (v & 1)] = sum;
     }
