@@ -260,7 +260,7 @@ int run_analysis(wf_plan_s* p, hipStream_t s, int nmaps) {
   if (p->dtype != WF_F64) {
     TIMED(1, if (int rc = launch_mfma_ana(p, p->tune, nmaps, s)) return rc);
   } else {
-    TIMED(1, MWF_HIP(launch_legendre_analysis_f64(p->dev, g.items_ana, g.n_ana, nmaps,
+    TIMED(1, MWF_HIP(launch_legendre_analysis_f64(p->dev, g.items_ana, g.bins_ana, g.nbins_ana, nmaps,
                                                   static_cast<const double*>(p->G), p->partial, s)));
   }
   return WF_OK;
@@ -293,7 +293,7 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, 
   a.chi2_stride = 2 * (int64_t)p->chi2_cap;
   TIMED(2, {
     MWF_HIP(launch_legendre_coeff(p->dev, a, s));
-    if (mode != SY_ALM_ONLY) MWF_HIP(launch_legendre_synthesis_f64(p->dev, g.items_syn, g.n_syn, a, s));
+    if (mode != SY_ALM_ONLY) MWF_HIP(launch_legendre_synthesis_f64(p->dev, g.items_syn, g.bins_syn, g.nbins_syn, a, s));
   });
   return WF_OK;
 }

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <map>
+#include <queue>
 #include <tuple>
 
 #include "runtime.hpp"
@@ -219,23 +220,35 @@ int build_geometry(Geometry& g) {
   D.A = g.A;
   D.row_off = g.row_off;
   D.norm_m = g.norm;
+  std::vector<uint16_t> wake((size_t)(lmax + 1) * g.npairs);
   {
-    uint8_t* d_reach = nullptr;
+    uint16_t* d_wake = nullptr;
     DevMem tmp;
-    if ((rc = tmp.alloc(&d_reach, (size_t)(lmax + 1) * g.npairs))) return rc;
-    MWF_HIP(launch_reach(D, d_reach, nullptr));
-    std::vector<uint8_t> reach((size_t)(lmax + 1) * g.npairs);
-    MWF_HIP(hipMemcpy(reach.data(), d_reach, reach.size(), hipMemcpyDeviceToHost));
+    if ((rc = tmp.alloc(&d_wake, wake.size()))) return rc;
+    MWF_HIP(launch_reach(D, d_wake, nullptr));
+    MWF_HIP(hipMemcpy(wake.data(), d_wake, wake.size() * sizeof(uint16_t), hipMemcpyDeviceToHost));
     g.n_active.assign(lmax + 1, 0);
     g.units_active = 0;
     for (int m = 0; m <= lmax; ++m) {
       int na = 0;
       for (int q = 0; q < g.npairs; ++q)
-        if (reach[(size_t)m * g.npairs + q]) na = q + 1;
+        if (wake[(size_t)m * g.npairs + q] != WAKE_NEVER) na = q + 1;
       g.n_active[m] = na;
       g.units_active += (int64_t)na * (lmax - m + 1);
     }
   }
+  // estimated cost of an FP64 work item of rb ring pairs, in steps of l: steps with a
+  // still-scaled ring in the block take the rescale path of every chunk
+  auto item_cost = [&](const WorkItem& w, int rb, int scaled_cost) {
+    const int nl = lmax - w.m + 1;
+    int scaled = 0;
+    const int q1 = std::min(g.n_active[w.m], (w.blk + 1) * rb);
+    for (int q = w.blk * rb; q < q1; ++q) {
+      const uint16_t wk = wake[(size_t)w.m * g.npairs + q];
+      if (wk != WAKE_NEVER) scaled = std::max(scaled, std::min((int)wk, nl));
+    }
+    return (int64_t)4 * (nl - scaled) + (int64_t)scaled_cost * scaled + 4 * FP64_ITEM_COST_L;
+  };
   auto make_items = [&](int rb) {
     std::vector<WorkItem> items;
     for (int m = 0; m <= lmax; ++m) {
@@ -252,15 +265,48 @@ int build_geometry(Geometry& g) {
     if (items.empty()) items.push_back({0, 0});
     return items;
   };
+  // FP64 lists: one bin per wave of a launch (FP64_WAVES_PER_SIMD per SIMD, at most one
+  // per item); items, most costly first, each go to the least-loaded bin; bins are
+  // stored in turn, with off[b] .. off[b + 1] the items of bin b
+  auto pack_bins = [&](int rb, int scaled_cost, std::vector<int32_t>* off) {
+    std::vector<WorkItem> items = make_items(rb);
+    std::vector<int64_t> cost(items.size());
+    for (size_t i = 0; i < items.size(); ++i) cost[i] = item_cost(items[i], rb, scaled_cost);
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    const int nb = std::max(1, std::min((int)items.size(), FP64_WAVES_PER_SIMD * 4 * g.n_cu));
+    std::vector<std::vector<int>> bins(nb);
+    using Load = std::pair<int64_t, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> least;
+    for (int b = 0; b < nb; ++b) least.push({0, b});
+    for (int i : order) {
+      const Load l = least.top();
+      least.pop();
+      bins[l.second].push_back(i);
+      least.push({l.first + cost[i], l.second});
+    }
+    std::vector<WorkItem> packed;
+    off->assign(1, 0);
+    for (const auto& b : bins) {
+      for (int i : b) packed.push_back(items[i]);
+      off->push_back((int32_t)packed.size());
+    }
+    return packed;
+  };
   g.ring_block_ana = ana_ring_block(g.npairs);
   g.ring_block_syn = ana_ring_block(g.npairs);
   g.nblk_max_ana = (g.npairs + g.ring_block_ana - 1) / g.ring_block_ana;
   std::vector<int32_t> nblk(lmax + 1);
   for (int m = 0; m <= lmax; ++m) nblk[m] = (g.n_active[m] + g.ring_block_ana - 1) / g.ring_block_ana;
-  const auto ia = make_items(g.ring_block_ana), is = make_items(g.ring_block_syn);
+  std::vector<int32_t> bins_ana, bins_syn;
+  const auto ia = pack_bins(g.ring_block_ana, FP64_SCALED_COST_ANA, &bins_ana);
+  const auto is = pack_bins(g.ring_block_syn, FP64_SCALED_COST_SYN, &bins_syn);
   const auto i128 = make_items(128), i256 = make_items(256), i64 = make_items(64);
   g.n_ana = (int)ia.size();
   g.n_syn = (int)is.size();
+  g.nbins_ana = (int)bins_ana.size() - 1;
+  g.nbins_syn = (int)bins_syn.size() - 1;
   g.n_a128 = (int)i128.size();
   g.n_a256 = (int)i256.size();
   g.n_s64 = (int)i64.size();
@@ -268,6 +314,8 @@ int build_geometry(Geometry& g) {
   if ((rc = M.upload(&g.nblk_ana, nblk))) return rc;
   if ((rc = M.upload(&g.items_ana, ia))) return rc;
   if ((rc = M.upload(&g.items_syn, is))) return rc;
+  if ((rc = M.upload(&g.bins_ana, bins_ana))) return rc;
+  if ((rc = M.upload(&g.bins_syn, bins_syn))) return rc;
   if ((rc = M.upload(&g.items_a128, i128))) return rc;
   if ((rc = M.upload(&g.items_a256, i256))) return rc;
   if ((rc = M.upload(&g.items_s64, i64))) return rc;
@@ -316,6 +364,8 @@ int get_geometry(int nside, int lmax, std::shared_ptr<Geometry>* out) {
   }
   auto g = std::make_shared<Geometry>();
   g->device = dev;
+  MWF_HIP(hipDeviceGetAttribute(&g->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (g->n_cu <= 0) g->n_cu = 1;
   g->nside = nside;
   g->lmax = lmax;
   const int rc = build_geometry(*g);

@@ -52,6 +52,16 @@ constexpr int CHUNK = 16;            // l-steps per reduction chunk in phase A (
 constexpr int MCH = 32;              // l-steps per staged chunk on the matrix-core path
 constexpr int ROW_PAD = 64;          // zero padding after each per-m row of A / C / coefficients
 constexpr int LANES = 64;            // wavefront width on CDNA
+// FP64 Legendre launches: work items packed at plan time into FP64_WAVES_PER_SIMD
+// bins per SIMD, one wave per bin, by estimated cost in steps of l: a step costs 1,
+// or FP64_SCALED_COST_{ANA,SYN} / 4 while a ring of the item is still scaled (the
+// rescale path runs once per chunk: 16 steps in the analysis, 8 in the synthesis),
+// and an item FP64_ITEM_COST_L more for its set-up. (Weights from timing the kernels.)
+constexpr int FP64_WAVES_PER_SIMD = 3;
+constexpr int FP64_SCALED_COST_ANA = 5;
+constexpr int FP64_SCALED_COST_SYN = 6;
+constexpr int FP64_ITEM_COST_L = 32;
+constexpr uint16_t WAKE_NEVER = 0xffff;
 
 // Work item of the m-parallel phase: one m and one block of ring pairs.
 struct WorkItem {
@@ -203,9 +213,10 @@ hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass
 hipError_t launch_phase_b_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, int cls, bool fp32,
                                 hipStream_t s);
 
-// Phase A (m-parallel): Legendre analysis into per-block partial sums.
-hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,
-                                        int nmaps, const double* G, double2* partial,
+// Phase A (m-parallel): Legendre analysis into per-block partial sums. One wave per
+// bin: wave w runs items[bins[w] .. bins[w + 1]) (nbins bins).
+hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, const int32_t* bins,
+                                        int nbins, int nmaps, const double* G, double2* partial,
                                         hipStream_t s);
 
 enum SynthMode : int32_t {
@@ -229,8 +240,8 @@ struct SynthArgs {
 
 // Sum of partials, filter and C scaling (one launch over all (l, m, map)).
 hipError_t launch_legendre_coeff(const PlanDev& P, const SynthArgs& a, hipStream_t s);
-hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
-                                         const SynthArgs& a, hipStream_t s);
+hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, const int32_t* bins,
+                                         int nbins, const SynthArgs& a, hipStream_t s);
 
 // Matrix-core (FP32 / BF16x3) Legendre phase for batches stored in float.
 // Threads per workgroup of the matrix-core coefficient kernel (one element each).
@@ -347,7 +358,8 @@ hipError_t launch_group_synthesis(const GroupLaunch& g, int mode, int nct, int a
 // Ring launch of class cls over TaskDev::ring_q[cls]; fft_len: the longest transform of the class.
 hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, int fft_len, hipStream_t s);
 
-// Plan-time: which ring pairs ever reach a non-negligible lambda_lm (polar skip).
-hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s);
+// Plan-time, per (m, ring pair): where lambda_lm leaves the scaled range, or WAKE_NEVER
+// (polar skip and the cost of the FP64 work items).
+hipError_t launch_reach(const PlanDev& P, uint16_t* wake, hipStream_t s);
 
 }  // namespace mwf

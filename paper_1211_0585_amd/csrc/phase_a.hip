@@ -134,121 +134,126 @@ static_assert(LTILE % ACH == 0 && (2 * ACH) <= LANES, "analysis chunking");
 
 template <int R>
 __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
-    PlanDev P, const WorkItem* __restrict__ items, const double* __restrict__ G,
-    double2* __restrict__ partial) {
+    PlanDev P, const WorkItem* __restrict__ items, const int32_t* __restrict__ bins,
+    const double* __restrict__ G, double2* __restrict__ partial) {
   __shared__ double red[2 * ACH][LANES / 2 + 1];
-  const WorkItem it = items[blockIdx.x];
-  const int m = it.m, blk = it.blk, map = blockIdx.y;
-  const int lane = threadIdx.x;
-  const int lmax = P.lmax;
-  const int nact = P.n_active[m];
-  const double* __restrict__ Arow = P.A + P.row_off[m];
-  const size_t pstride = (size_t)(lmax + 1) * 4;
-  const double* Gm = G + (size_t)map * P.npairs * pstride + (size_t)m * 4;
-
-  RingState<R> st;
-  init_rings<R>(P, m, blk, lane, nact, st);
-  // S/D of each ring, zero while the ring's values are still scaled
-  double Sre[R], Sim[R], Dre[R], Dim[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int q = blk * (LANES * R) + r * LANES + lane;
-    if (q < nact && st.sc[r] == 0) {
-      const double4 sd = *reinterpret_cast<const double4*>(Gm + (size_t)q * pstride);
-      Sre[r] = sd.x;
-      Sim[r] = sd.y;
-      Dre[r] = sd.z;
-      Dim[r] = sd.w;
-    } else {
-      Sre[r] = Sim[r] = Dre[r] = Dim[r] = 0.0;
-    }
-  }
-
-  double* out = reinterpret_cast<double*>(partial + ((size_t)map * P.nblk_max + blk) * P.nalm);
-  const int64_t row = alm_index(lmax, m, m);
-
-  // recurrence coefficients of LTILE values of l: lane i loads l = base + i one
-  // tile ahead, the tile in use is read from LDS (the same address in every lane).
-  // The loads are unconditional, with the index clamped to nl (the first entry of
-  // the row's zero padding), so that no wait for them lands inside the loop.
   __shared__ double sA[LTILE];
-  const int nl = lmax - m + 1;
-  auto tile_a = [&](int i) { return Arow[min(i, nl)]; };
-  sA[lane] = tile_a(lane);
-  // every load issued so far (ring seeds, S/D, tile 0) completes here, so the loop
-  // body waits on nothing but its own LDS reads
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  double An = tile_a(LTILE + lane);
+  const int map = blockIdx.y;
+  // this wave's bin of work items (packed at plan time)
+  const int k_end = bins[blockIdx.x + 1];
+  for (int k = bins[blockIdx.x]; k < k_end; ++k) {
+    const WorkItem it = items[k];
+    const int m = it.m, blk = it.blk;
+    const int lane = threadIdx.x;
+    const int lmax = P.lmax;
+    const int nact = P.n_active[m];
+    const double* __restrict__ Arow = P.A + P.row_off[m];
+    const size_t pstride = (size_t)(lmax + 1) * 4;
+    const double* Gm = G + (size_t)map * P.npairs * pstride + (size_t)m * 4;
 
-  for (int l0 = m; l0 <= lmax; l0 += ACH) {
-    const int t0 = (l0 - m) & (LTILE - 1);
-    if (t0 == 0 && l0 > m) {
-      sA[lane] = An;      // the previous tile's last readers passed the barrier below
-      __syncthreads();
-      An = tile_a(l0 - m + LTILE + lane);
-    }
-    double are[ACH], aim[ACH];
+    RingState<R> st;
+    init_rings<R>(P, m, blk, lane, nact, st);
+    // S/D of each ring, zero while the ring's values are still scaled
+    double Sre[R], Sim[R], Dre[R], Dim[R];
 #pragma unroll
-    for (int j = 0; j < ACH; ++j) are[j] = aim[j] = 0.0;
-    const double* Ac = sA + t0;
-#pragma unroll
-    for (int j = 0; j < ACH; j += 2) {
-      const double A0 = Ac[j], A1 = Ac[j + 1];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        // mu2 <- mu_l (l - m even), then mu1 <- mu_{l+1} (odd)
-        st.mu2[r] = fma(A0 * st.z[r], st.mu1[r], -st.mu2[r]);
-        are[j] = fma(st.mu2[r], Sre[r], are[j]);
-        aim[j] = fma(st.mu2[r], Sim[r], aim[j]);
-        st.mu1[r] = fma(A1 * st.z[r], st.mu2[r], -st.mu1[r]);
-        are[j + 1] = fma(st.mu1[r], Dre[r], are[j + 1]);
-        aim[j + 1] = fma(st.mu1[r], Dim[r], aim[j + 1]);
+    for (int r = 0; r < R; ++r) {
+      const int q = blk * (LANES * R) + r * LANES + lane;
+      if (q < nact && st.sc[r] == 0) {
+        const double4 sd = *reinterpret_cast<const double4*>(Gm + (size_t)q * pstride);
+        Sre[r] = sd.x;
+        Sim[r] = sd.y;
+        Dre[r] = sd.z;
+        Dim[r] = sd.w;
+      } else {
+        Sre[r] = Sim[r] = Dre[r] = Dim[r] = 0.0;
       }
     }
-    // reduce the NV = 2 ACH values (v = 2 j + re/im) over the 64 lanes: first lanes
-    // l and l + 32 in registers, the lower half keeping values 0..NV/2-1 and the
-    // upper half the rest, then the remaining 32 lanes through LDS, LPV lanes per
-    // value each adding 32 / LPV entries, and LPV - 1 shuffles
-    constexpr int NV = 2 * ACH, LPV = LANES / NV;
-#pragma unroll
-    for (int i = 0; i < ACH; ++i) {
-      const int ja = i >> 1, jb = ACH / 2 + (i >> 1);
-      const double va = (i & 1) ? aim[ja] : are[ja];
-      const double vb = (i & 1) ? aim[jb] : are[jb];
-      red[i + (lane >> 5) * ACH][lane & 31] = fold_halves(va, vb);
-    }
+
+    double* out = reinterpret_cast<double*>(partial + ((size_t)map * P.nblk_max + blk) * P.nalm);
+    const int64_t row = alm_index(lmax, m, m);
+
+    // recurrence coefficients of LTILE values of l: lane i loads l = base + i one
+    // tile ahead, the tile in use is read from LDS (the same address in every lane).
+    // The loads are unconditional, with the index clamped to nl (the first entry of
+    // the row's zero padding), so that no wait for them lands inside the loop.
+    const int nl = lmax - m + 1;
+    auto tile_a = [&](int i) { return Arow[min(i, nl)]; };
+    sA[lane] = tile_a(lane);
+    // every load issued so far (ring seeds, S/D, tile 0) completes here, so the loop
+    // body waits on nothing but its own LDS reads
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    const int v = lane / LPV;
-    const int h = (lane % LPV) * (32 / LPV);
-    double sum = 0.0;
+    double An = tile_a(LTILE + lane);
+
+    for (int l0 = m; l0 <= lmax; l0 += ACH) {
+      const int t0 = (l0 - m) & (LTILE - 1);
+      if (t0 == 0 && l0 > m) {
+        sA[lane] = An;      // the previous tile's last readers passed the barrier below
+        __syncthreads();
+        An = tile_a(l0 - m + LTILE + lane);
+      }
+      double are[ACH], aim[ACH];
 #pragma unroll
-    for (int k = 0; k < 32 / LPV; ++k) sum += red[v][h + k];
+      for (int j = 0; j < ACH; ++j) are[j] = aim[j] = 0.0;
+      const double* Ac = sA + t0;
 #pragma unroll
-    for (int x = 1; x < LPV; x <<= 1) sum += __shfl_xor(sum, x);
-    if (lane % LPV == 0) {
-      const int l = l0 + (v >> 1);
-      if (l <= lmax) out[2 * (row + (l - m)) + (v & 1)] = sum;
-    }
-    __syncthreads();
-    int anysc = 0;
+      for (int j = 0; j < ACH; j += 2) {
+        const double A0 = Ac[j], A1 = Ac[j + 1];
 #pragma unroll
-    for (int r = 0; r < R; ++r) anysc |= st.sc[r];
-    const int woke = wave_any(anysc) ? rescale_chunk<R>(st) : 0;
-    if (woke) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (woke & (1 << r)) {
-          const int q = blk * (LANES * R) + r * LANES + lane;
-          const double4 sd = *reinterpret_cast<const double4*>(Gm + (size_t)q * pstride);
-          Sre[r] = sd.x;
-          Sim[r] = sd.y;
-          Dre[r] = sd.z;
-          Dim[r] = sd.w;
+        for (int r = 0; r < R; ++r) {
+          // mu2 <- mu_l (l - m even), then mu1 <- mu_{l+1} (odd)
+          st.mu2[r] = fma(A0 * st.z[r], st.mu1[r], -st.mu2[r]);
+          are[j] = fma(st.mu2[r], Sre[r], are[j]);
+          aim[j] = fma(st.mu2[r], Sim[r], aim[j]);
+          st.mu1[r] = fma(A1 * st.z[r], st.mu2[r], -st.mu1[r]);
+          are[j + 1] = fma(st.mu1[r], Dre[r], are[j + 1]);
+          aim[j + 1] = fma(st.mu1[r], Dim[r], aim[j + 1]);
         }
-      // (rare) complete these loads here rather than at their first use, where the
-      // wait would also cover the tile prefetch
-      __builtin_amdgcn_s_waitcnt(0);
+      }
+      // reduce the NV = 2 ACH values (v = 2 j + re/im) over the 64 lanes: first lanes
+      // l and l + 32 in registers, the lower half keeping values 0..NV/2-1 and the
+      // upper half the rest, then the remaining 32 lanes through LDS, LPV lanes per
+      // value each adding 32 / LPV entries, and LPV - 1 shuffles
+      constexpr int NV = 2 * ACH, LPV = LANES / NV;
+#pragma unroll
+      for (int i = 0; i < ACH; ++i) {
+        const int ja = i >> 1, jb = ACH / 2 + (i >> 1);
+        const double va = (i & 1) ? aim[ja] : are[ja];
+        const double vb = (i & 1) ? aim[jb] : are[jb];
+        red[i + (lane >> 5) * ACH][lane & 31] = fold_halves(va, vb);
+      }
+      __syncthreads();
+      const int v = lane / LPV;
+      const int h = (lane % LPV) * (32 / LPV);
+      double sum = 0.0;
+#pragma unroll
+      for (int k = 0; k < 32 / LPV; ++k) sum += red[v][h + k];
+#pragma unroll
+      for (int x = 1; x < LPV; x <<= 1) sum += __shfl_xor(sum, x);
+      if (lane % LPV == 0) {
+        const int l = l0 + (v >> 1);
+        if (l <= lmax) out[2 * (row + (l - m)) + (v & 1)] = sum;
+      }
+      __syncthreads();
+      int anysc = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) anysc |= st.sc[r];
+      const int woke = wave_any(anysc) ? rescale_chunk<R>(st) : 0;
+      if (woke) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (woke & (1 << r)) {
+            const int q = blk * (LANES * R) + r * LANES + lane;
+            const double4 sd = *reinterpret_cast<const double4*>(Gm + (size_t)q * pstride);
+            Sre[r] = sd.x;
+            Sim[r] = sd.y;
+            Dre[r] = sd.z;
+            Dim[r] = sd.w;
+          }
+        // (rare) complete these loads here rather than at their first use, where the
+        // wait would also cover the tile prefetch
+        __builtin_amdgcn_s_waitcnt(0);
+      }
     }
   }
 }
@@ -308,94 +313,101 @@ constexpr int SCH = 8;   // synthesis steps per coefficient chunk
 
 template <int R>
 __global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
-    PlanDev P, const WorkItem* __restrict__ items, SynthArgs a) {
-  const WorkItem it = items[blockIdx.x];
-  const int m = it.m, blk = it.blk, map = blockIdx.y;
-  const int lane = threadIdx.x;
-  const int lmax = P.lmax;
-  const int64_t roff = P.row_off[m];
-  const double* __restrict__ Arow = P.A + roff;
-  const double2* __restrict__ brow = a.bcoef + (size_t)map * P.rows_total + roff;
-
-  const int nact = P.n_active[m];
-  const int nl = lmax - m + 1;
-  // coefficients of LTILE values of l: lane i loads l = base + i one tile ahead,
-  // the tile in use is read from LDS (the same address in every lane). The loads
-  // are unconditional, with the index clamped to nl (the first entry of the row's
-  // zero padding: A is zero there and the coefficient kernel writes zeros past
-  // lmax), so that no wait for them lands inside the loop.
+    PlanDev P, const WorkItem* __restrict__ items, const int32_t* __restrict__ bins, SynthArgs a) {
   __shared__ double sA[LTILE];
   __shared__ double2 sb[LTILE];
-  auto tile_a = [&](int i) { return Arow[min(i, nl)]; };
-  auto tile_b = [&](int i) { return brow[min(i, nl)]; };
-  RingState<R> st;
-  init_rings<R>(P, m, blk, lane, nact, st);
-  sA[lane] = tile_a(lane);
-  sb[lane] = tile_b(lane);
-  // every load issued so far (ring seeds, tile 0) completes here, so the loop body
-  // waits on nothing but its own LDS reads
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-  double An = tile_a(LTILE + lane);
-  double2 bn = tile_b(LTILE + lane);
-  double Ere[R], Eim[R], Ore[R], Oim[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
+  const int map = blockIdx.y;
+  // this wave's bin of work items (packed at plan time)
+  const int k_end = bins[blockIdx.x + 1];
+  for (int k = bins[blockIdx.x]; k < k_end; ++k) {
+    const WorkItem it = items[k];
+    const int m = it.m, blk = it.blk;
+    const int lane = threadIdx.x;
+    const int lmax = P.lmax;
+    const int64_t roff = P.row_off[m];
+    const double* __restrict__ Arow = P.A + roff;
+    const double2* __restrict__ brow = a.bcoef + (size_t)map * P.rows_total + roff;
 
-  for (int l0 = m; l0 <= lmax; l0 += SCH) {
-    const int t0 = (l0 - m) & (LTILE - 1);
-    if (t0 == 0 && l0 > m) {
-      __syncthreads();
-      sA[lane] = An;
-      sb[lane] = bn;
-      __syncthreads();
-      An = tile_a(l0 - m + LTILE + lane);
-      bn = tile_b(l0 - m + LTILE + lane);
-    }
-    double A[SCH];
-    double2 b[SCH];
+    const int nact = P.n_active[m];
+    const int nl = lmax - m + 1;
+    // coefficients of LTILE values of l: lane i loads l = base + i one tile ahead,
+    // the tile in use is read from LDS (the same address in every lane). The loads
+    // are unconditional, with the index clamped to nl (the first entry of the row's
+    // zero padding: A is zero there and the coefficient kernel writes zeros past
+    // lmax), so that no wait for them lands inside the loop.
+    auto tile_a = [&](int i) { return Arow[min(i, nl)]; };
+    auto tile_b = [&](int i) { return brow[min(i, nl)]; };
+    RingState<R> st;
+    init_rings<R>(P, m, blk, lane, nact, st);
+    sA[lane] = tile_a(lane);
+    sb[lane] = tile_b(lane);
+    // every load issued so far (ring seeds, tile 0) completes here, so the loop body
+    // waits on nothing but its own LDS reads
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    double An = tile_a(LTILE + lane);
+    double2 bn = tile_b(LTILE + lane);
+    double Ere[R], Eim[R], Ore[R], Oim[R];
 #pragma unroll
-    for (int j = 0; j < SCH; ++j) {
-      A[j] = sA[t0 + j];
-      b[j] = sb[t0 + j];
-    }
-    int scaled = 0;
+    for (int r = 0; r < R; ++r) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
+
+    for (int l0 = m; l0 <= lmax; l0 += SCH) {
+      const int t0 = (l0 - m) & (LTILE - 1);
+      if (t0 == 0 && l0 > m) {
+        __syncthreads();
+        sA[lane] = An;
+        sb[lane] = bn;
+        __syncthreads();
+        An = tile_a(l0 - m + LTILE + lane);
+        bn = tile_b(l0 - m + LTILE + lane);
+      }
+      double A[SCH];
+      double2 b[SCH];
 #pragma unroll
-    for (int r = 0; r < R; ++r) scaled |= (st.sc[r] != 0) << r;
+      for (int j = 0; j < SCH; ++j) {
+        A[j] = sA[t0 + j];
+        b[j] = sb[t0 + j];
+      }
+      int scaled = 0;
 #pragma unroll
-    for (int j = 0; j < SCH; j += 2) {
+      for (int r = 0; r < R; ++r) scaled |= (st.sc[r] != 0) << r;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        st.mu2[r] = fma(A[j] * st.z[r], st.mu1[r], -st.mu2[r]);          // l - m even
-        Ere[r] = fma(st.mu2[r], b[j].x, Ere[r]);
-        Eim[r] = fma(st.mu2[r], b[j].y, Eim[r]);
-        st.mu1[r] = fma(A[j + 1] * st.z[r], st.mu2[r], -st.mu1[r]);      // odd
-        Ore[r] = fma(st.mu1[r], b[j + 1].x, Ore[r]);
-        Oim[r] = fma(st.mu1[r], b[j + 1].y, Oim[r]);
+      for (int j = 0; j < SCH; j += 2) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          st.mu2[r] = fma(A[j] * st.z[r], st.mu1[r], -st.mu2[r]);          // l - m even
+          Ere[r] = fma(st.mu2[r], b[j].x, Ere[r]);
+          Eim[r] = fma(st.mu2[r], b[j].y, Eim[r]);
+          st.mu1[r] = fma(A[j + 1] * st.z[r], st.mu2[r], -st.mu1[r]);      // odd
+          Ore[r] = fma(st.mu1[r], b[j + 1].x, Ore[r]);
+          Oim[r] = fma(st.mu1[r], b[j + 1].y, Oim[r]);
+        }
+      }
+      // a ring still scaled at the chunk start has contributed nothing so far: clear it
+      if (wave_any(scaled)) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (scaled & (1 << r)) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
+        rescale_chunk<R>(st);
       }
     }
-    // a ring still scaled at the chunk start has contributed nothing so far: clear it
-    if (wave_any(scaled)) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (scaled & (1 << r)) Ere[r] = Eim[r] = Ore[r] = Oim[r] = 0.0;
-      rescale_chunk<R>(st);
-    }
-  }
 
-  const size_t pstride = (size_t)(lmax + 1) * 4;
-  double* Fm = a.F + (size_t)map * P.npairs * pstride + (size_t)m * 4;
+    const size_t pstride = (size_t)(lmax + 1) * 4;
+    double* Fm = a.F + (size_t)map * P.npairs * pstride + (size_t)m * 4;
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const int q = blk * (LANES * R) + r * LANES + lane;
-    if (q < nact)
-      *reinterpret_cast<double4*>(Fm + (size_t)q * pstride) =
-          make_double4(Ere[r], Eim[r], Ore[r], Oim[r]);
+    for (int r = 0; r < R; ++r) {
+      const int q = blk * (LANES * R) + r * LANES + lane;
+      if (q < nact)
+        *reinterpret_cast<double4*>(Fm + (size_t)q * pstride) =
+            make_double4(Ere[r], Eim[r], Ore[r], Oim[r]);
+    }
   }
 }
 
-// Plan time: does lambda_lm(z_q) rise above the negligible threshold for some l <= lmax?
-__global__ void reach_kernel(PlanDev P, uint8_t* __restrict__ reach) {
+// Plan time, per (m, ring pair): the first l - m + 1 at which lambda_lm(z_q) has
+// risen above the scaled range (its scale reached 0; 0 if it starts there), or
+// WAKE_NEVER if that does not happen for l <= lmax (the pair is skipped for m).
+__global__ void reach_kernel(PlanDev P, uint16_t* __restrict__ wake) {
   const int m = blockIdx.y;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.npairs) return;
@@ -403,8 +415,8 @@ __global__ void reach_kernel(PlanDev P, uint8_t* __restrict__ reach) {
   double v;
   int s;
   sectoral_seed(m, rp.sin_t, P.norm_m[m], &v, &s);
-  uint8_t ok = (s == 0);
-  if (!ok) {
+  uint16_t w = s == 0 ? 0 : WAKE_NEVER;
+  if (s != 0) {
     const double* Arow = P.A + P.row_off[m];
     double mu1 = 0.0, mu2 = -v;
     for (int l = m; l <= P.lmax; ++l) {
@@ -415,40 +427,39 @@ __global__ void reach_kernel(PlanDev P, uint8_t* __restrict__ reach) {
         mu1 *= RESCALE;
         mu2 *= RESCALE;
         if (--s == 0) {
-          ok = 1;
+          w = (uint16_t)(l - m + 1);
           break;
         }
       }
     }
   }
-  reach[(size_t)m * P.npairs + q] = ok;
+  wake[(size_t)m * P.npairs + q] = w;
 }
 
 template <int R>
-hipError_t launch_ana_r(const PlanDev& P, const WorkItem* items, int nitems, int nmaps,
+hipError_t launch_ana_r(const PlanDev& P, const WorkItem* items, const int32_t* bins, int nbins, int nmaps,
                         const double* G, double2* partial, hipStream_t s) {
-  hipLaunchKernelGGL(legendre_analysis_f64_kernel<R>, dim3(nitems, nmaps), dim3(64), 0, s, P,
-                     items, G, partial);
+  hipLaunchKernelGGL(legendre_analysis_f64_kernel<R>, dim3(nbins, nmaps), dim3(64), 0, s, P, items, bins, G,
+                     partial);
   return hipGetLastError();
 }
 
 template <int R>
-hipError_t launch_syn_r(const PlanDev& P, const WorkItem* items, int nitems, const SynthArgs& a,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(legendre_synthesis_f64_kernel<R>, dim3(nitems, a.nmaps), dim3(64), 0, s,
-                     P, items, a);
+hipError_t launch_syn_r(const PlanDev& P, const WorkItem* items, const int32_t* bins, int nbins,
+                        const SynthArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(legendre_synthesis_f64_kernel<R>, dim3(nbins, a.nmaps), dim3(64), 0, s, P, items, bins, a);
   return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, int nitems,
-                                        int nmaps, const double* G, double2* partial,
+hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items, const int32_t* bins,
+                                        int nbins, int nmaps, const double* G, double2* partial,
                                         hipStream_t s) {
   switch (P.ring_block_ana / LANES) {
-    case 1: return launch_ana_r<1>(P, items, nitems, nmaps, G, partial, s);
-    case 2: return launch_ana_r<2>(P, items, nitems, nmaps, G, partial, s);
-    case 4: return launch_ana_r<4>(P, items, nitems, nmaps, G, partial, s);
+    case 1: return launch_ana_r<1>(P, items, bins, nbins, nmaps, G, partial, s);
+    case 2: return launch_ana_r<2>(P, items, bins, nbins, nmaps, G, partial, s);
+    case 4: return launch_ana_r<4>(P, items, bins, nbins, nmaps, G, partial, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -458,19 +469,19 @@ hipError_t launch_legendre_coeff(const PlanDev& P, const SynthArgs& a, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, int nitems,
-                                         const SynthArgs& a, hipStream_t s) {
+hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items, const int32_t* bins,
+                                         int nbins, const SynthArgs& a, hipStream_t s) {
   switch (P.ring_block_syn / LANES) {
-    case 1: return launch_syn_r<1>(P, items, nitems, a, s);
-    case 2: return launch_syn_r<2>(P, items, nitems, a, s);
-    case 4: return launch_syn_r<4>(P, items, nitems, a, s);
+    case 1: return launch_syn_r<1>(P, items, bins, nbins, a, s);
+    case 2: return launch_syn_r<2>(P, items, bins, nbins, a, s);
+    case 4: return launch_syn_r<4>(P, items, bins, nbins, a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_reach(const PlanDev& P, uint8_t* reach, hipStream_t s) {
+hipError_t launch_reach(const PlanDev& P, uint16_t* wake, hipStream_t s) {
   dim3 grid((P.npairs + 127) / 128, P.lmax + 1);
-  hipLaunchKernelGGL(reach_kernel, grid, dim3(128), 0, s, P, reach);
+  hipLaunchKernelGGL(reach_kernel, grid, dim3(128), 0, s, P, wake);
   return hipGetLastError();
 }
 

@@ -72,8 +72,12 @@ struct Geometry {
   float2* chirp32 = nullptr;
   float2* blue32 = nullptr;
   // work lists, longest first
-  WorkItem* items_ana = nullptr;       // FP64 analysis (ring_block_ana)
-  WorkItem* items_syn = nullptr;       // FP64 synthesis (ring_block_syn)
+  WorkItem* items_ana = nullptr;       // FP64 analysis (ring_block_ana), packed into bins
+  WorkItem* items_syn = nullptr;       // FP64 synthesis (ring_block_syn), packed into bins
+  int32_t* bins_ana = nullptr;         // [nbins + 1] item range of each wave of an FP64 launch
+  int32_t* bins_syn = nullptr;
+  int nbins_ana = 0, nbins_syn = 0;
+  int n_cu = 0;                        // compute units of the device
   WorkItem* items_a128 = nullptr;      // matrix-core analysis, 128 / 256 ring pairs
   WorkItem* items_a256 = nullptr;
   WorkItem* items_s64 = nullptr;       // matrix-core synthesis, 64 ring pairs
