@@ -203,9 +203,7 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   a.map_in = map_in;
   a.map_out = map_out;
   const Geometry& g = *p->geo;
-  // With few maps one launch over all ring pairs fills the GPU better than two
-  // back-to-back launches split by transform length.
-  // with few maps, one launch per transform kind fills the GPU better than also
+  // With few maps, one launch per transform kind fills the GPU better than also
   // splitting off the short transforms; the two kinds then run side by side (the
   // Bluestein class on the plan's second stream), since neither alone fills it
   const int split = nmaps >= RING_SPLIT_MAPS ? 1 : 0;
@@ -220,10 +218,14 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
     MWF_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
     MWF_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   }
+  // Bluestein rings of the longest transform on the second stream; on this one the
+  // shorter Bluestein rings (their smaller LDS lets them share the chip with the
+  // long ones), then the power-of-two rings
   TIMED(0, {
     MWF_HIP(hipEventRecord(p->ev_fork, s));
     MWF_HIP(hipStreamWaitEvent(p->aux, p->ev_fork, 0));
-    MWF_HIP(launch_phase_b_class(p->dev, a, cls[0], 0, fp32, p->aux));
+    MWF_HIP(launch_phase_b_class(p->dev, a, g.blue_split[0], 0, fp32, p->aux));
+    if (g.blue_split[1].count) MWF_HIP(launch_phase_b_class(p->dev, a, g.blue_split[1], 0, fp32, s));
     MWF_HIP(launch_phase_b_class(p->dev, a, cls[1], 1, fp32, s));
     MWF_HIP(hipEventRecord(p->ev_join, p->aux));
     MWF_HIP(hipStreamWaitEvent(s, p->ev_join, 0));

@@ -209,6 +209,20 @@ int build_geometry(Geometry& g) {
         if ((rc = M.upload(&d, lists[k][c]))) return rc;
         g.ring_cls[k][c] = RingClass{d, (int32_t)lists[k][c].size(), lens[k][c]};
       }
+    // Bluestein rings of the longest transform apart from the shorter ones: at the
+    // longest length alone they can hold all of the chip's LDS
+    std::vector<int32_t> bl[2];
+    int bl_len[2] = {4, 4};
+    for (int q : lists[0][0]) {
+      const int k = pairs[q].bl_M == lens[0][0] ? 0 : 1;
+      bl[k].push_back(q);
+      bl_len[k] = std::max(bl_len[k], pairs[q].bl_M);
+    }
+    for (int k = 0; k < 2; ++k) {
+      int32_t* d = nullptr;
+      if ((rc = M.upload(&d, bl[k]))) return rc;
+      g.blue_split[k] = RingClass{d, (int32_t)bl[k].size(), bl_len[k]};
+    }
   }
 
   // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range

@@ -212,7 +212,7 @@ __device__ __forceinline__ void stockham_pass(typename CT<C>::V* x, int L, int N
 // smaller radices first). Input and output are in the plain layout; between passes
 // the data sit in the padded one, so the buffer holds fft_padded(L) elements. wt:
 // the per-pass twiddle tables in pass order (fft_twiddle_entries(lg) entries, see
-// stage_ring_twiddles). The caller synchronises before the call; the last pass ends
+// twiddle_glob_index). The caller synchronises before the call; the last pass ends
 // with a barrier.
 template <class C, int NT, int MAXB>
 __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
@@ -242,52 +242,57 @@ __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
   }
 }
 
-// The per-pass twiddle tables of a 2^lg-point transform into wt (LDS), from the plan's
-// table glob[t] = exp(-2 pi i t / glob_len), t < glob_len / 2: for each pass with
-// Ns > 1, wt[off + k] = exp(-2 pi i k / (R Ns)) = glob[k glob_len / (R Ns)], k < Ns.
-// Written by all threads; the caller's next barrier orders them before use.
-template <class C, int NT>
-__device__ __forceinline__ void stage_ring_twiddles(typename CT<C>::V* wt, int lg,
-                                                    const typename CT<C>::V* __restrict__ glob, int glob_len) {
+// Plan-table index of entry e of the per-pass twiddle tables of a 2^lg-point
+// transform: for each pass with Ns > 1 (in pass order), entries off + k, k < Ns, hold
+// exp(-2 pi i k / (R Ns)) = glob[k glob_len / (R Ns)] of the plan's table glob[t] =
+// exp(-2 pi i t / glob_len), t < glob_len / 2.
+__device__ __forceinline__ int twiddle_glob_index(int lg, int e, int glob_len) {
   int n2, n4, n8;
   fft_schedule(lg, &n2, &n4, &n8);
-  const int np = n2 + n4 + n8;
   int Ns = 1, off = 0;
-  for (int p = 0; p < np; ++p) {
+  for (int p = 0; p < n2 + n4 + n8; ++p) {
     const int R = p < n2 ? 2 : (p < n2 + n4 ? 4 : 8);
     if (Ns > 1) {
-      const int stride = glob_len / (R * Ns);
-      for (int k = threadIdx.x; k < Ns; k += NT) wt[off + k] = glob[(size_t)k * stride];
+      if (e < off + Ns) return (e - off) * (glob_len / (R * Ns));
       off += Ns;
     }
     Ns *= R;
   }
+  return 0;
 }
 
-// DFT of any length n of x[0..n) in place (dir = -1 forward, +1 inverse) by
-// Bluestein's method, using the LDS buffer x[0..M), the chirp exp(-i pi j^2/n)
-// (length n) and the filter spectrum H (length M).
+// This thread's share of a ring's Bluestein chirp (cj[u] = chirp[tid + u NT], j < n)
+// and filter spectrum (hk[u] = H[tid + u NT], k < M), in registers.
+template <class C, int NT, int MAXB>
+struct BlueRegs {
+  static constexpr int NK = 4 * MAXB;     // M <= 4 MAXB NT
+  static constexpr int NJ = 2 * MAXB;     // n <= M / 2
+  typename CT<C>::V cj[NJ], hk[NK];
+  __device__ __forceinline__ void load(int n, int M, const typename CT<C>::V* __restrict__ chirp,
+                                       const typename CT<C>::V* __restrict__ H) {
+#pragma unroll
+    for (int u = 0; u < NJ; ++u) {
+      const int j = threadIdx.x + u * NT;
+      if (j < n) cj[u] = chirp[j];
+    }
+#pragma unroll
+    for (int u = 0; u < NK; ++u) {
+      const int k = threadIdx.x + u * NT;
+      if (k < M) hk[u] = H[k];
+    }
+  }
+};
+
 template <class C, int NT, int MAXB>
 __device__ void dft_bluestein(typename CT<C>::V* x, int n, int M, int lgM, int dir,
-                              const typename CT<C>::V* __restrict__ chirp,
-                              const typename CT<C>::V* __restrict__ H,
+                              const BlueRegs<C, NT, MAXB>& br,
                               const typename CT<C>::V* __restrict__ wt) {
   using V = typename CT<C>::V;
-  constexpr int NK = 4 * MAXB;     // M <= 4 MAXB NT
-  constexpr int NJ = 2 * MAXB;     // n <= M / 2
+  constexpr int NK = BlueRegs<C, NT, MAXB>::NK;
+  constexpr int NJ = BlueRegs<C, NT, MAXB>::NJ;
   const int tid = threadIdx.x;
-  // chirp and filter spectrum into registers before any of them is needed
-  V cj[NJ], hk[NK];
-#pragma unroll
-  for (int u = 0; u < NJ; ++u) {
-    const int j = tid + u * NT;
-    if (j < n) cj[u] = chirp[j];
-  }
-#pragma unroll
-  for (int u = 0; u < NK; ++u) {
-    const int k = tid + u * NT;
-    if (k < M) hk[u] = H[k];
-  }
+  const V(&cj)[NJ] = br.cj;
+  const V(&hk)[NK] = br.hk;
 #pragma unroll
   for (int u = 0; u < NK; ++u) {
     const int j = tid + u * NT;
@@ -341,17 +346,19 @@ struct Tabs<float> {
   __device__ static const float2* blue(const PlanDev& P) { return P.bluestein32; }
 };
 
-// The ring's transform, with the twiddles of its length L (n, or the Bluestein M)
-// staged in LDS: twl[t] = exp(-2 pi i t / L), t < L / 4. KIND 0: the launch holds
-// only power-of-two rings, 1: only Bluestein rings, 2: both.
+// The ring's transform (n points, or Bluestein over M), with the per-pass twiddles
+// of its length staged in LDS (twl). KIND 0: the launch holds only power-of-two
+// rings, 1: only Bluestein rings, 2: both. The Bluestein chirp and filter spectrum
+// are loaded per transform (held across the workgroup they cost occupancy).
 template <class C, int NT, int MAXB, int KIND>
 __device__ __forceinline__ void ring_dft(typename CT<C>::V* buf, const typename CT<C>::V* twl,
                                          const RingPair& rp, int dir, const PlanDev& P) {
   if (KIND == 0 || (KIND == 2 && rp.log2n >= 0)) {
     fft_pow2<C, NT, MAXB>(buf, rp.log2n, dir, twl);
   } else {
-    dft_bluestein<C, NT, MAXB>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, Tabs<C>::chirp(P) + rp.chirp_off,
-                               Tabs<C>::blue(P) + rp.bl_off, twl);
+    BlueRegs<C, NT, MAXB> br;
+    br.load(rp.nphi, rp.bl_M, Tabs<C>::chirp(P) + rp.chirp_off, Tabs<C>::blue(P) + rp.bl_off);
+    dft_bluestein<C, NT, MAXB>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, br, twl);
   }
 }
 
@@ -389,14 +396,28 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
   const T* __restrict__ q_tab = static_cast<const T*>(P.q) + (a.slots ? map * a.q_stride : 0);
 
-  // per-pass twiddles of this ring's transform length into LDS (after the padded
-  // data buffer), written at the end of the loading step (after any partial sums
-  // there are consumed) and ordered before their first use by the barrier that
+  // per-pass twiddles of this ring's transform length: loaded now, written to LDS
+  // (after the padded data buffer) at the end of the loading step (after any partial
+  // sums there are consumed) and ordered before their first use by the barrier that
   // closes that step
+  // (thread tid holds entries tid + u NT, u < TWP; any beyond TWP NT, none for the
+  // lengths a launch admits, are read at the store)
+  // (three scalars rather than an array, which the compiler kept in scratch memory)
   V* twl = buf + fft_padded(buf_elems);
+  constexpr int TWP = (2 * MAXB + 2) / 3;
+  static_assert(TWP <= 3, "twiddle prefetch holds at most three entries per thread");
+  const int tw_lg = rp.log2n >= 0 ? rp.log2n : __ffs(rp.bl_M) - 1;
+  const int tw_n = fft_twiddle_entries(tw_lg);
+  const V* __restrict__ twg = Tabs<C>::tw(P);
+  auto tw_load = [&](int e) { return e < tw_n ? twg[twiddle_glob_index(tw_lg, e, P.tw_len)] : CT<C>::make(0, 0); };
+  const V tw0 = tw_load(tid);
+  const V tw1 = TWP > 1 ? tw_load(tid + NT) : CT<C>::make(0, 0);
+  const V tw2 = TWP > 2 ? tw_load(tid + 2 * NT) : CT<C>::make(0, 0);
   auto stage_twiddles = [&]() {
-    const int lg = rp.log2n >= 0 ? rp.log2n : __ffs(rp.bl_M) - 1;
-    stage_ring_twiddles<C, NT>(twl, lg, Tabs<C>::tw(P), P.tw_len);
+    if (tid < tw_n) twl[tid] = tw0;
+    if (TWP > 1 && tid + NT < tw_n) twl[tid + NT] = tw1;
+    if (TWP > 2 && tid + 2 * NT < tw_n) twl[tid + 2 * NT] = tw2;
+    for (int e = tid + TWP * NT; e < tw_n; e += NT) twl[e] = twg[twiddle_glob_index(tw_lg, e, P.tw_len)];
   };
 
   // ---- ring values into buf (x = north + i south)

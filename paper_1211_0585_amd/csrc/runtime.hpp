@@ -85,6 +85,9 @@ struct Geometry {
   // ring launch classes: [0] one or few maps (Bluestein, power of two), [1] from
   // RING_SPLIT_MAPS maps on (long Bluestein, long power of two, short)
   RingClass ring_cls[2][NRING_CLASSES]{};
+  // few-maps plan launches: the Bluestein rings split by transform length, [0] those
+  // of the longest M, [1] the rest (each launch's LDS sized to its own length)
+  RingClass blue_split[2]{};
   DevMem mem;
 };
 
