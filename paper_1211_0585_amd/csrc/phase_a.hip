@@ -129,22 +129,39 @@ __device__ __forceinline__ int rescale_chunk(RingState<R>& st) {
 }
 
 constexpr int LTILE = 64;  // values of l per prefetched coefficient tile (one per lane)
+
+// FP64 Legendre launches: workgroups of FP64_WG_WAVES waves, one bin each, so that
+// every SIMD of a CU gets the same number of waves (with single-wave workgroups
+// the spread over a CU's SIMDs depends on what ran before: after a ring phase of
+// three concurrent launches, some SIMDs got four waves and some two, and the
+// launch took a third longer).
+constexpr int FP64_WG_WAVES = 4;
+
+// Orders a wave's LDS accesses around it (one wave's LDS operations execute in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
 constexpr int ACH = 16;    // analysis: values of l per cross-lane reduction (and scale check)
 static_assert(LTILE % ACH == 0 && (2 * ACH) <= LANES, "analysis chunking");
 
 template <int R>
-__global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
-    PlanDev P, const WorkItem* __restrict__ items, const int32_t* __restrict__ bins,
+__global__ void __launch_bounds__(FP64_WG_WAVES * LANES) legendre_analysis_f64_kernel(
+    PlanDev P, const WorkItem* __restrict__ items, const int32_t* __restrict__ bins, int nbins,
     const double* __restrict__ G, double2* __restrict__ partial) {
-  __shared__ double red[2 * ACH][LANES / 2 + 1];
-  __shared__ double sA[LTILE];
+  // per-wave LDS: the waves of a workgroup run unrelated bins and never synchronise
+  __shared__ double red_w[FP64_WG_WAVES][2 * ACH][LANES / 2 + 1];
+  __shared__ double sA_w[FP64_WG_WAVES][LTILE];
+  const int wave = threadIdx.x / LANES;
+  const int bin = blockIdx.x * FP64_WG_WAVES + wave;
+  if (bin >= nbins) return;
+  double(*red)[LANES / 2 + 1] = red_w[wave];
+  double* sA = sA_w[wave];
   const int map = blockIdx.y;
   // this wave's bin of work items (packed at plan time)
-  const int k_end = bins[blockIdx.x + 1];
-  for (int k = bins[blockIdx.x]; k < k_end; ++k) {
+  const int k_end = bins[bin + 1];
+  for (int k = bins[bin]; k < k_end; ++k) {
     const WorkItem it = items[k];
     const int m = it.m, blk = it.blk;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % LANES;
     const int lmax = P.lmax;
     const int nact = P.n_active[m];
     const double* __restrict__ Arow = P.A + P.row_off[m];
@@ -182,14 +199,14 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
     // every load issued so far (ring seeds, S/D, tile 0) completes here, so the loop
     // body waits on nothing but its own LDS reads
     __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    wave_sync();
     double An = tile_a(LTILE + lane);
 
     for (int l0 = m; l0 <= lmax; l0 += ACH) {
       const int t0 = (l0 - m) & (LTILE - 1);
       if (t0 == 0 && l0 > m) {
         sA[lane] = An;      // the previous tile's last readers passed the barrier below
-        __syncthreads();
+        wave_sync();
         An = tile_a(l0 - m + LTILE + lane);
       }
       double are[ACH], aim[ACH];
@@ -222,7 +239,7 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
         const double vb = (i & 1) ? aim[jb] : are[jb];
         red[i + (lane >> 5) * ACH][lane & 31] = fold_halves(va, vb);
       }
-      __syncthreads();
+      wave_sync();
       const int v = lane / LPV;
       const int h = (lane % LPV) * (32 / LPV);
       double sum = 0.0;
@@ -234,7 +251,7 @@ __global__ void __launch_bounds__(64) legendre_analysis_f64_kernel(
         const int l = l0 + (v >> 1);
         if (l <= lmax) out[2 * (row + (l - m)) + (v & 1)] = sum;
       }
-      __syncthreads();
+      wave_sync();
       int anysc = 0;
 #pragma unroll
       for (int r = 0; r < R; ++r) anysc |= st.sc[r];
@@ -312,17 +329,23 @@ __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
 constexpr int SCH = 8;   // synthesis steps per coefficient chunk
 
 template <int R>
-__global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
-    PlanDev P, const WorkItem* __restrict__ items, const int32_t* __restrict__ bins, SynthArgs a) {
-  __shared__ double sA[LTILE];
-  __shared__ double2 sb[LTILE];
+__global__ void __launch_bounds__(FP64_WG_WAVES * LANES) legendre_synthesis_f64_kernel(
+    PlanDev P, const WorkItem* __restrict__ items, const int32_t* __restrict__ bins, int nbins, SynthArgs a) {
+  // per-wave LDS: the waves of a workgroup run unrelated bins and never synchronise
+  __shared__ double sA_w[FP64_WG_WAVES][LTILE];
+  __shared__ double2 sb_w[FP64_WG_WAVES][LTILE];
+  const int wave = threadIdx.x / LANES;
+  const int bin = blockIdx.x * FP64_WG_WAVES + wave;
+  if (bin >= nbins) return;
+  double* sA = sA_w[wave];
+  double2* sb = sb_w[wave];
   const int map = blockIdx.y;
   // this wave's bin of work items (packed at plan time)
-  const int k_end = bins[blockIdx.x + 1];
-  for (int k = bins[blockIdx.x]; k < k_end; ++k) {
+  const int k_end = bins[bin + 1];
+  for (int k = bins[bin]; k < k_end; ++k) {
     const WorkItem it = items[k];
     const int m = it.m, blk = it.blk;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % LANES;
     const int lmax = P.lmax;
     const int64_t roff = P.row_off[m];
     const double* __restrict__ Arow = P.A + roff;
@@ -344,7 +367,7 @@ __global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
     // every load issued so far (ring seeds, tile 0) completes here, so the loop body
     // waits on nothing but its own LDS reads
     __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    wave_sync();
     double An = tile_a(LTILE + lane);
     double2 bn = tile_b(LTILE + lane);
     double Ere[R], Eim[R], Ore[R], Oim[R];
@@ -354,10 +377,10 @@ __global__ void __launch_bounds__(64) legendre_synthesis_f64_kernel(
     for (int l0 = m; l0 <= lmax; l0 += SCH) {
       const int t0 = (l0 - m) & (LTILE - 1);
       if (t0 == 0 && l0 > m) {
-        __syncthreads();
+        wave_sync();
         sA[lane] = An;
         sb[lane] = bn;
-        __syncthreads();
+        wave_sync();
         An = tile_a(l0 - m + LTILE + lane);
         bn = tile_b(l0 - m + LTILE + lane);
       }
@@ -439,15 +462,16 @@ __global__ void reach_kernel(PlanDev P, uint16_t* __restrict__ wake) {
 template <int R>
 hipError_t launch_ana_r(const PlanDev& P, const WorkItem* items, const int32_t* bins, int nbins, int nmaps,
                         const double* G, double2* partial, hipStream_t s) {
-  hipLaunchKernelGGL(legendre_analysis_f64_kernel<R>, dim3(nbins, nmaps), dim3(64), 0, s, P, items, bins, G,
-                     partial);
+  hipLaunchKernelGGL(legendre_analysis_f64_kernel<R>, dim3((nbins + FP64_WG_WAVES - 1) / FP64_WG_WAVES, nmaps),
+                     dim3(FP64_WG_WAVES * LANES), 0, s, P, items, bins, nbins, G, partial);
   return hipGetLastError();
 }
 
 template <int R>
 hipError_t launch_syn_r(const PlanDev& P, const WorkItem* items, const int32_t* bins, int nbins,
                         const SynthArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(legendre_synthesis_f64_kernel<R>, dim3(nbins, a.nmaps), dim3(64), 0, s, P, items, bins, a);
+  hipLaunchKernelGGL(legendre_synthesis_f64_kernel<R>, dim3((nbins + FP64_WG_WAVES - 1) / FP64_WG_WAVES, a.nmaps),
+                     dim3(FP64_WG_WAVES * LANES), 0, s, P, items, bins, nbins, a);
   return hipGetLastError();
 }
 
