@@ -130,7 +130,8 @@ int wf_solve(wf_plan_t plan, const void* d, void* s_wf, void* s_alm,
              wf_stats* stats);
 
 /*
- * wf_chi2 -- the chi^2 history of the last solve on a plan created with WF_FLAG_CHI2:
+ * wf_chi2 -- the chi^2 history of the last solve on this plan, if it recorded one (a
+ * plan created with WF_FLAG_CHI2, or wf_solve_adaptive):
  *   nmaps, nsweeps  those of that solve (checked)
  *   out             host, nmaps * nsweeps doubles: out[map * nsweeps + k] = chi2_k
  * Waits for the solve. Errors: WF_EINVAL (no such solve, other sizes), WF_EDEVICE.
@@ -145,6 +146,85 @@ int wf_chi2(wf_plan_t plan, int32_t nmaps, int32_t nsweeps, double* out);
 int wf_solve_batch(wf_plan_t plan, int32_t nmaps, const void* d, void* s_wf,
                    void* s_alm, const double* lambda, int32_t nsweeps,
                    void* hip_stream, wf_stats* stats);
+
+/*
+ * wf_solve_banded -- wf_solve of one map with a band limit per sweep (Sect. 3: the
+ * transforms of a sweep need only reach l_max^SHT while lambda smooths the small
+ * scales away). Sweep k runs the transforms and the filter for l, m <= lmax_sht[k]:
+ * s_lm of that sweep is zero above it, and the pixel map it synthesises has no
+ * such modes.
+ *   lmax_sht  host, nsweeps entries, non-decreasing, each in [0, lmax]
+ *   other arguments as for wf_solve; s_alm (full lmax layout) is zero above the
+ *   last sweep's band limit.
+ * The sweeps below lmax run on plans of the same problem at those band limits,
+ * made on first use and kept with this plan (their tables and work buffers count
+ * against device memory). WF_FLAG_CHI2 and WF_FLAG_TIMING work as for wf_solve.
+ * Errors: WF_EINVAL (bad schedule or band limits, NULL d or s_wf), WF_ENOMEM,
+ * WF_EDEVICE.
+ */
+int wf_solve_banded(wf_plan_t plan, const void* d, void* s_wf, void* s_alm,
+                    const double* lambda, const int32_t* lmax_sht, int32_t nsweeps,
+                    void* hip_stream, wf_stats* stats);
+
+/*
+ * Adaptive cooling (Sect. 3). Level j works at l_j = l_iter0 * 2^j with
+ *   lambda_j = C_{l_j} / (tau Omega)      (the lambda at which f_{l_j} = 1/2)
+ *   band limit L_j = min(lmax, l_j + l_pad)   (lmax when full_band = 1)
+ * until lambda_j <= 1 (or l_j > lmax): that level is the last, lambda = 1, L = lmax.
+ * The monitor is the chi^2 of the iterate at lambda = 1 (see WF_FLAG_CHI2), with
+ * sigma = sqrt(2 n_obs), n_obs the observed pixels. The chi^2 of iterate k is known
+ * once the ring pass of sweep k + 1 has synthesised its map; the decision it allows
+ * applies from sweep k + 2 on (the ring work of sweep k + 1 is already running).
+ * With iterates k - 1 and k both of the current level and D = chi2_{k-1} - chi2_k:
+ *   last level:   D < stop_tol * sigma stops; the result is iterate k + 1;
+ *   other levels: |D| < plateau_tol * sigma moves to the next level.
+ * A level other than the last also ends once max_level_sweeps sweeps have been
+ * started at it (0: no limit). The solve ends after max_sweeps sweeps in any case.
+ */
+typedef struct {
+  int32_t l_iter0;          /* first l_iter, >= 1 (the paper starts at 20)             */
+  int32_t l_pad;            /* band-limit margin above l_iter, >= 0 (the paper: ~100)   */
+  int32_t full_band;        /* 1: every sweep at lmax (cooling without truncation)     */
+  int32_t max_level_sweeps; /* >= 0                                                     */
+  double plateau_tol;       /* >= 0, in units of sigma                                  */
+  double stop_tol;          /* >= 0, in units of sigma (the paper: 1e-4)                */
+} wf_adaptive_opts;
+
+/* wf_adaptive_defaults -- l_iter0 20, l_pad 100, full_band 0, max_level_sweeps 50,
+ * plateau_tol 1, stop_tol 1e-4. Host-only. */
+void wf_adaptive_defaults(wf_adaptive_opts* opts);
+
+/*
+ * wf_adaptive_levels -- the level table above, host-only:
+ *   lmax, cl    band limit and C_l (host, lmax + 1 entries); tau, omega as in the plan
+ *   max_levels  capacity of lambda_out and lmax_out
+ *   nlevels     receives the number of levels (the last has lambda 1 and band lmax)
+ * Errors: WF_EINVAL (bad options, tau or omega not > 0, more than max_levels levels).
+ */
+int wf_adaptive_levels(int32_t lmax, const double* cl, double tau, double omega,
+                       const wf_adaptive_opts* opts, int32_t max_levels,
+                       double* lambda_out, int32_t* lmax_out, int32_t* nlevels);
+
+/*
+ * wf_solve_adaptive -- the messenger iteration of one map from s = t = 0 under the
+ * adaptive schedule above, with the band limit of each level (wf_solve_banded).
+ * Waits for its own work: the host reads the chi^2 of every iterate (a 16-byte
+ * copy on a second stream while the sweep's Legendre work runs).
+ *   d, s_wf, s_alm  as for wf_solve (s_alm may be NULL)
+ *   opts            NULL for wf_adaptive_defaults
+ *   max_sweeps      >= 1
+ *   lambda_out, lmax_out, chi2_out  host, max_sweeps entries each: lambda and band
+ *                   limit of every sweep run, and the chi^2 of its iterate
+ *   nsweeps_out     receives the number of sweeps run
+ *   converged       NULL, or receives 1 if the stop rule ended the solve, else 0
+ * The plan's chi^2 history (wf_chi2 with nmaps 1, nsweeps = *nsweeps_out) is set too.
+ * Errors: WF_EINVAL, WF_ENOMEM, WF_EDEVICE.
+ */
+int wf_solve_adaptive(wf_plan_t plan, const void* d, void* s_wf, void* s_alm,
+                      const wf_adaptive_opts* opts, int32_t max_sweeps,
+                      double* lambda_out, int32_t* lmax_out, double* chi2_out,
+                      int32_t* nsweeps_out, int32_t* converged, void* hip_stream,
+                      wf_stats* stats);
 
 /*
  * sht_map2alm -- forward transform of nmaps maps: a_lm = Omega sum_p conj(Y_lm(p)) f_p

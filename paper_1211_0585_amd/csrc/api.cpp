@@ -492,6 +492,8 @@ int wf_plan(wf_plan_t* out, int32_t nside, int32_t lmax, const double* cl, const
     p->q = dq;
   }
   if ((rc = p->mem.upload(&p->cl, std::vector<double>(cl, cl + lmax + 1)))) return bail(rc);
+  p->cl_host.assign(cl, cl + lmax + 1);
+  for (int64_t i = 0; i < npix; ++i) p->n_obs += q[i] > 0.0;
 
   if ((rc = plan_alloc(p))) return bail(rc);
   apply_cached_tuning(p, p->max_batch);
@@ -532,6 +534,7 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
   TimerScope scope(&timer);
   // chi^2 history (WF_FLAG_CHI2): [map][2 k] prior term, [map][2 k + 1] data term of iterate k
   const bool chi = (p->flags & WF_FLAG_CHI2) != 0;
+  p->chi2_nsweeps = 0;
   if (chi) {
     if (nsweeps > p->chi2_cap) {
       if ((rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * 2 * nsweeps))) return rc;
@@ -569,8 +572,8 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
 
 int wf_chi2(wf_plan_t p, int32_t nmaps, int32_t nsweeps, double* out) {
   if (!p || !out) return fail(WF_EINVAL, "plan and out must not be NULL");
-  if (!(p->flags & WF_FLAG_CHI2) || p->chi2_nsweeps == 0)
-    return fail(WF_EINVAL, "no solve with WF_FLAG_CHI2 has run on this plan");
+  if (p->chi2_nsweeps == 0)
+    return fail(WF_EINVAL, "the last solve on this plan recorded no chi^2 (WF_FLAG_CHI2 or wf_solve_adaptive)");
   if (nmaps != p->chi2_nmaps || nsweeps != p->chi2_nsweeps)
     return fail(WF_EINVAL, "nmaps and nsweeps must be those of the last solve (" + std::to_string(p->chi2_nmaps) +
                                ", " + std::to_string(p->chi2_nsweeps) + ")");
@@ -609,6 +612,357 @@ int sht_alm2map(wf_plan_t p, int32_t nmaps, const void* alm, void* map, void* hi
   p->last_stream = s;
   if ((rc = run_synthesis(p, s, SY_FROM_ALM, nmaps, 1.0, alm, nullptr))) return rc;
   return run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr, map);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- truncated solves
+namespace {
+
+// The plan of this problem at band limit L <= lmax: the plan itself, or one made
+// on first use that shares its q and C_l (a prefix of the same table).
+int band_plan(wf_plan_s* p, int L, wf_plan_s** out) {
+  if (L == p->geo->lmax) {
+    *out = p;
+    return WF_OK;
+  }
+  auto it = p->band.find(L);
+  if (it != p->band.end()) {
+    *out = it->second;
+    return WF_OK;
+  }
+  std::shared_ptr<Geometry> geo;
+  if (int rc = get_geometry(p->geo->nside, L, &geo)) return rc;
+  auto* b = new wf_plan_s();
+  b->geo = geo;
+  b->dtype = p->dtype;
+  b->max_batch = 1;
+  b->tau = p->tau;
+  b->stream = p->stream;
+  b->last_stream = p->stream;
+  b->tune_cache = p->tune_cache;
+  b->q = p->q;
+  b->cl = p->cl;
+  b->n_obs = p->n_obs;
+  if (int rc = plan_alloc(b)) {
+    delete b;
+    return rc;
+  }
+  apply_cached_tuning(b, 1);
+  p->band[L] = b;
+  *out = b;
+  return WF_OK;
+}
+
+// The ring Fourier coefficients of the current iterate ([pair][m][4], m <= lmax of
+// `from`) into the buffer of a plan of higher band limit; m above `from`'s limit is
+// zero there, as the iterate has no such modes.
+int carry_F(const wf_plan_s* from, wf_plan_s* to, hipStream_t s) {
+  const size_t sp = (size_t)(from->geo->lmax + 1) * 4 * from->elem;
+  const size_t dp = (size_t)(to->geo->lmax + 1) * 4 * to->elem;
+  const size_t rows = (size_t)from->geo->npairs;
+  MWF_HIP(hipMemcpy2DAsync(to->F, dp, from->F, sp, sp, rows, hipMemcpyDeviceToDevice, s));
+  if (dp > sp) MWF_HIP(hipMemset2DAsync(static_cast<uint8_t*>(to->F) + sp, dp, 0, dp - sp, rows, s));
+  return WF_OK;
+}
+
+// Sweeps of one map on plans of non-decreasing band limit (Sect. 2 sweep, Sect. 3
+// truncation). chi, when set, receives per iterate k the prior term at 2k (from the
+// filter of sweep k) and the data term / tau at 2k + 1 (from the ring pass that
+// synthesises iterate k: that of sweep k + 1, or finish()).
+struct BandRun {
+  wf_plan_s* root = nullptr;
+  hipStream_t s = nullptr;
+  const void* d = nullptr;
+  double* chi = nullptr;
+  wf_plan_s* cur = nullptr;
+  int k = 0;
+
+  // after_ring runs once the ring pass of this sweep is enqueued.
+  template <class Hook>
+  int sweep(double lam, int L, bool write_alm, Hook after_ring) {
+    wf_plan_s* b = nullptr;
+    int rc = band_plan(root, L, &b);
+    if (rc) return rc;
+    if (k > 0 && b != cur && (rc = carry_F(cur, b, s))) return rc;
+    b->last_stream = s;
+    const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
+    if ((rc = run_phase_b(b, s, mode, 1, lam, d, nullptr, nullptr, (k > 0 && chi) ? chi + 2 * (k - 1) + 1 : nullptr)))
+      return rc;
+    if ((rc = after_ring())) return rc;
+    if ((rc = run_analysis(b, s, 1))) return rc;
+    if ((rc = run_synthesis(b, s, SY_FROM_PARTIAL, 1, lam, nullptr, write_alm ? root->alm_scratch : nullptr,
+                            chi ? chi + 2 * k : nullptr)))
+      return rc;
+    cur = b;
+    ++k;
+    return WF_OK;
+  }
+
+  // The map of the last iterate (and its data term), its alm in the full layout.
+  int finish(void* s_wf, void* s_alm) {
+    int rc = run_phase_b(cur, s, PB_SYNTH | PB_WRITE_MAP | (chi ? PB_CHI2 : 0), 1, 1.0, chi ? d : nullptr, nullptr,
+                         s_wf, chi ? chi + 2 * (k - 1) + 1 : nullptr);
+    if (rc) return rc;
+    if (s_alm)
+      MWF_HIP(launch_alm_repack(root->alm_scratch, cur->geo->lmax, s_alm, root->geo->lmax, root->dtype == WF_F64, s));
+    return WF_OK;
+  }
+};
+
+int ensure_alm_scratch(wf_plan_s* p) {
+  if (p->alm_scratch) return WF_OK;
+  uint8_t* a = nullptr;
+  if (int rc = p->mem.alloc(&a, (size_t)p->geo->nalm * 2 * p->elem)) return rc;
+  p->alm_scratch = a;
+  return WF_OK;
+}
+
+// chi^2 history buffer of at least n iterates, cleared on s.
+int ensure_chi2(wf_plan_s* p, int n, hipStream_t s) {
+  if (n > p->chi2_cap) {
+    if (int rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * 2 * n)) return rc;
+    p->chi2_cap = n;
+  }
+  MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * 2 * p->chi2_cap * sizeof(double), s));
+  return WF_OK;
+}
+
+int check_adaptive_opts(const wf_adaptive_opts& o) {
+  if (o.l_iter0 < 1) return fail(WF_EINVAL, "l_iter0 must be >= 1");
+  if (o.l_pad < 0) return fail(WF_EINVAL, "l_pad must be >= 0");
+  if (o.full_band != 0 && o.full_band != 1) return fail(WF_EINVAL, "full_band must be 0 or 1");
+  if (o.max_level_sweeps < 0) return fail(WF_EINVAL, "max_level_sweeps must be >= 0");
+  if (!(o.plateau_tol >= 0) || !std::isfinite(o.plateau_tol)) return fail(WF_EINVAL, "plateau_tol must be finite and >= 0");
+  if (!(o.stop_tol >= 0) || !std::isfinite(o.stop_tol)) return fail(WF_EINVAL, "stop_tol must be finite and >= 0");
+  return WF_OK;
+}
+
+struct Level {
+  double lam;
+  int L;
+};
+
+// Levels of the adaptive schedule (declared with wf_adaptive_levels); the last one
+// has lambda 1 and band limit lmax.
+int adaptive_levels(int lmax, const double* cl, double tau, double omega, const wf_adaptive_opts& o,
+                    std::vector<Level>* out) {
+  out->clear();
+  for (int64_t l = o.l_iter0;; l *= 2) {
+    const double ratio = l <= lmax ? cl[l] / (tau * omega) : 0.0;
+    if (!(ratio > 1.0)) {
+      out->push_back({1.0, lmax});
+      return WF_OK;
+    }
+    const int L = o.full_band ? lmax : (int)std::min<int64_t>(lmax, l + o.l_pad);
+    out->push_back({ratio, L});
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void wf_adaptive_defaults(wf_adaptive_opts* o) {
+  if (!o) return;
+  o->l_iter0 = 20;
+  o->l_pad = 100;
+  o->full_band = 0;
+  o->max_level_sweeps = 50;
+  o->plateau_tol = 1.0;
+  o->stop_tol = 1e-4;
+}
+
+int wf_adaptive_levels(int32_t lmax, const double* cl, double tau, double omega, const wf_adaptive_opts* opts,
+                       int32_t max_levels, double* lambda_out, int32_t* lmax_out, int32_t* nlevels) {
+  if (lmax < 0 || !cl || !opts || !lambda_out || !lmax_out || !nlevels)
+    return fail(WF_EINVAL, "lmax must be >= 0 and the pointers non-NULL");
+  if (!(tau > 0) || !(omega > 0) || !std::isfinite(tau) || !std::isfinite(omega))
+    return fail(WF_EINVAL, "tau and omega must be finite and > 0");
+  if (int rc = check_adaptive_opts(*opts)) return rc;
+  for (int l = 0; l <= lmax; ++l)
+    if (!std::isfinite(cl[l]) || cl[l] < 0) return fail(WF_EINVAL, "cl must be finite and >= 0");
+  std::vector<Level> lv;
+  adaptive_levels(lmax, cl, tau, omega, *opts, &lv);
+  if ((int)lv.size() > max_levels) return fail(WF_EINVAL, "more levels than max_levels");
+  for (size_t j = 0; j < lv.size(); ++j) {
+    lambda_out[j] = lv[j].lam;
+    lmax_out[j] = lv[j].L;
+  }
+  *nlevels = (int32_t)lv.size();
+  return WF_OK;
+}
+
+int wf_solve_banded(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const double* lambda,
+                    const int32_t* lmax_sht, int32_t nsweeps, void* hip_stream, wf_stats* stats) {
+  int rc = check_batch(p, 1);
+  if (rc) return rc;
+  if (!d || !s_wf) return fail(WF_EINVAL, "d and s_wf must not be NULL");
+  if ((rc = check_schedule(lambda, nsweeps))) return rc;
+  if (!lmax_sht) return fail(WF_EINVAL, "lmax_sht must not be NULL");
+  for (int k = 0; k < nsweeps; ++k) {
+    if (lmax_sht[k] < 0 || lmax_sht[k] > p->geo->lmax) return fail(WF_EINVAL, "every lmax_sht must be in [0, lmax]");
+    if (k > 0 && lmax_sht[k] < lmax_sht[k - 1]) return fail(WF_EINVAL, "lmax_sht must be non-decreasing");
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  p->last_stream = s;
+  // every plan the schedule needs exists before the first launch
+  for (int k = 0; k < nsweeps; ++k) {
+    wf_plan_s* b = nullptr;
+    if ((rc = band_plan(p, lmax_sht[k], &b))) return rc;
+  }
+  if (s_alm && (rc = ensure_alm_scratch(p))) return rc;
+  Timer timer;
+  timer.on = (p->flags & WF_FLAG_TIMING) != 0;
+  timer.s = s;
+  TimerScope scope(&timer);
+  const bool chi = (p->flags & WF_FLAG_CHI2) != 0;
+  p->chi2_nsweeps = 0;
+  if (chi) {
+    if ((rc = ensure_chi2(p, nsweeps, s))) return rc;
+    p->chi2_nsweeps = nsweeps;
+    p->chi2_nmaps = 1;
+  }
+  BandRun run;
+  run.root = p;
+  run.s = s;
+  run.d = d;
+  run.chi = chi ? p->chi2_buf : nullptr;
+  auto none = [] { return WF_OK; };
+  for (int k = 0; k < nsweeps; ++k)
+    if ((rc = run.sweep(lambda[k], lmax_sht[k], s_alm && k == nsweeps - 1, none))) return rc;
+  if ((rc = run.finish(s_wf, s_alm))) return rc;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->sweeps_done = nsweeps;
+    if ((rc = timer.collect(stats))) return rc;
+    if (chi) {
+      double last[2];
+      MWF_HIP(hipMemcpyAsync(last, p->chi2_buf + 2 * (nsweeps - 1), sizeof(last), hipMemcpyDeviceToHost, s));
+      MWF_HIP(hipStreamSynchronize(s));
+      stats->chi2_last = last[0] + last[1] / p->tau;
+    }
+  }
+  return WF_OK;
+}
+
+int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const wf_adaptive_opts* opts,
+                      int32_t max_sweeps, double* lambda_out, int32_t* lmax_out, double* chi2_out,
+                      int32_t* nsweeps_out, int32_t* converged, void* hip_stream, wf_stats* stats) {
+  int rc = check_batch(p, 1);
+  if (rc) return rc;
+  if (!d || !s_wf) return fail(WF_EINVAL, "d and s_wf must not be NULL");
+  if (max_sweeps < 1) return fail(WF_EINVAL, "max_sweeps must be >= 1");
+  if (!lambda_out || !lmax_out || !chi2_out || !nsweeps_out)
+    return fail(WF_EINVAL, "lambda_out, lmax_out, chi2_out and nsweeps_out must not be NULL");
+  wf_adaptive_opts o;
+  wf_adaptive_defaults(&o);
+  if (opts) o = *opts;
+  if ((rc = check_adaptive_opts(o))) return rc;
+  std::vector<Level> lv;
+  adaptive_levels(p->geo->lmax, p->cl_host.data(), p->tau, p->geo->omega, o, &lv);
+  const double sigma = std::sqrt(2.0 * (double)p->n_obs);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  p->last_stream = s;
+  for (const Level& l : lv) {
+    wf_plan_s* b = nullptr;
+    if ((rc = band_plan(p, l.L, &b))) return rc;
+  }
+  if ((rc = ensure_alm_scratch(p))) return rc;
+  if (!p->copy) {
+    MWF_HIP(hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking));
+    MWF_HIP(hipEventCreateWithFlags(&p->ev_ring, hipEventDisableTiming));
+    MWF_HIP(hipEventCreateWithFlags(&p->ev_copied, hipEventDisableTiming));
+  }
+  if (p->chi_host_cap < max_sweeps) {
+    if (p->chi_host) MWF_HIP(hipHostFree(p->chi_host));
+    p->chi_host = nullptr;
+    p->chi_host_cap = 0;
+    MWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->chi_host), (size_t)2 * max_sweeps * sizeof(double)));
+    p->chi_host_cap = max_sweeps;
+  }
+  if ((rc = ensure_chi2(p, max_sweeps, s))) return rc;
+  Timer timer;
+  timer.on = (p->flags & WF_FLAG_TIMING) != 0;
+  timer.s = s;
+  TimerScope scope(&timer);
+
+  BandRun run;
+  run.root = p;
+  run.s = s;
+  run.d = d;
+  run.chi = p->chi2_buf;
+  // once the ring pass of sweep k + 1 is enqueued, the two terms of iterate k are
+  // copied out on the copy stream, behind that pass only
+  auto copy_terms = [&]() -> int {
+    const int it = run.k - 1;
+    if (it < 0) return WF_OK;
+    MWF_HIP(hipEventRecord(p->ev_ring, s));
+    MWF_HIP(hipStreamWaitEvent(p->copy, p->ev_ring, 0));
+    MWF_HIP(hipMemcpyAsync(p->chi_host + 2 * it, p->chi2_buf + 2 * it, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           p->copy));
+    MWF_HIP(hipEventRecord(p->ev_copied, p->copy));
+    return WF_OK;
+  };
+  std::vector<int> lev;
+  std::vector<double> chi;
+  auto start = [&](int j) -> int {
+    lambda_out[run.k] = lv[j].lam;
+    lmax_out[run.k] = lv[j].L;
+    lev.push_back(j);
+    return run.sweep(lv[j].lam, lv[j].L, true, copy_terms);
+  };
+  int cur = 0, at_cur = 0;
+  bool conv = false;
+  if ((rc = start(0))) return rc;
+  ++at_cur;
+  if (max_sweeps > 1) {
+    if ((rc = start(0))) return rc;
+    ++at_cur;
+  }
+  for (int k = 0; k + 1 < run.k; ++k) {
+    // iterate k: its terms were copied behind the ring pass of sweep k + 1, the
+    // latest one started
+    MWF_HIP(hipEventSynchronize(p->ev_copied));
+    chi.push_back(p->chi_host[2 * k] + p->chi_host[2 * k + 1] / p->tau);
+    const bool last = cur + 1 == (int)lv.size();
+    int next = cur;
+    if (k >= 1 && lev[k] == cur && lev[k - 1] == cur) {
+      const double dchi = chi[k - 1] - chi[k];
+      if (last) {
+        if (dchi < o.stop_tol * sigma) conv = true;
+      } else if (std::fabs(dchi) < o.plateau_tol * sigma) {
+        next = cur + 1;
+      }
+    }
+    if (!last && o.max_level_sweeps > 0 && at_cur >= o.max_level_sweeps) next = cur + 1;
+    if (conv || run.k >= max_sweeps) break;
+    if (next != cur) {
+      cur = next;
+      at_cur = 0;
+    }
+    if ((rc = start(cur))) return rc;
+    ++at_cur;
+  }
+  if ((rc = run.finish(s_wf, s_alm))) return rc;
+  const int n = run.k;
+  MWF_HIP(hipMemcpyAsync(p->chi_host + 2 * (n - 1), p->chi2_buf + 2 * (n - 1), 2 * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  MWF_HIP(hipStreamSynchronize(s));
+  chi.resize(n - 1);
+  chi.push_back(p->chi_host[2 * (n - 1)] + p->chi_host[2 * (n - 1) + 1] / p->tau);
+  for (int k = 0; k < n; ++k) chi2_out[k] = chi[k];
+  *nsweeps_out = n;
+  if (converged) *converged = conv ? 1 : 0;
+  p->chi2_nsweeps = n;
+  p->chi2_nmaps = 1;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->sweeps_done = n;
+    if ((rc = timer.collect(stats))) return rc;
+    stats->chi2_last = chi[n - 1];
+  }
+  return WF_OK;
 }
 
 }  // extern "C"

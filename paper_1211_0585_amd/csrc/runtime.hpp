@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -132,6 +133,8 @@ int run_group_step(const TaskDev* tasks, const int64_t* offs, const int64_t* nbl
                    int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s);
 size_t plan_buffer_bytes(int nside, int lmax, int dtype, int nmaps);
 size_t geometry_bytes(int nside, int lmax);
+// Packed alm of band limit ls into the packed layout of band limit ld >= ls (zero above ls).
+hipError_t launch_alm_repack(const void* src, int ls, void* dst, int ld, bool fp64, hipStream_t s);
 
 }  // namespace mwf
 
@@ -161,6 +164,18 @@ struct wf_plan_s {
   // with the fork / join events; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // host copies kept for the truncated solves
+  std::vector<double> cl_host;         // C_l, l = 0..lmax
+  int64_t n_obs = 0;                   // observed pixels (ninv > 0, not masked)
+  // truncated solves: plans of this problem at lower band limits, by lmax. They
+  // share q and cl with this plan (which owns both) and hold their own work buffers.
+  std::map<int, wf_plan_s*> band;
+  void* alm_scratch = nullptr;         // packed alm of the latest sweep (any band limit)
+  // adaptive solve: chi^2 terms copied to pinned host memory on a copy stream
+  double* chi_host = nullptr;
+  int chi_host_cap = 0;
+  hipStream_t copy = nullptr;
+  hipEvent_t ev_ring = nullptr, ev_copied = nullptr;
   ~wf_plan_s() {
     if (aux) {
       hipStreamSynchronize(aux);
@@ -168,6 +183,17 @@ struct wf_plan_s {
     }
     if (ev_fork) hipEventDestroy(ev_fork);
     if (ev_join) hipEventDestroy(ev_join);
+    if (copy) {
+      hipStreamSynchronize(copy);
+      hipStreamDestroy(copy);
+    }
+    if (ev_ring) hipEventDestroy(ev_ring);
+    if (ev_copied) hipEventDestroy(ev_copied);
+    if (chi_host) hipHostFree(chi_host);
+    for (auto& kv : band) {
+      hipStreamSynchronize(kv.second->last_stream);
+      delete kv.second;
+    }
   }
 };
 

@@ -45,6 +45,14 @@ _SIGS = [
     ("wf_server_query", _c.c_int, [_c.c_void_p, _c.c_void_p]),
     ("wf_server_destroy", None, [_c.c_void_p]),
     ("wf_chi2", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p]),
+    ("wf_solve_banded", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                   _c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("wf_adaptive_defaults", None, [_c.c_void_p]),
+    ("wf_adaptive_levels", _c.c_int, [_c.c_int32, _c.c_void_p, _c.c_double, _c.c_double, _c.c_void_p, _c.c_int32,
+                                      _c.c_void_p, _c.c_void_p, _c.POINTER(_c.c_int32)]),
+    ("wf_solve_adaptive", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
+                                     _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.POINTER(_c.c_int32),
+                                     _c.POINTER(_c.c_int32), _c.c_void_p, _c.c_void_p]),
     ("wf_sync", _c.c_int, [_c.c_void_p]),
     ("wf_destroy", None, [_c.c_void_p]),
     ("wf_strerror", _c.c_char_p, [_c.c_int]),
@@ -92,6 +100,38 @@ class wf_stats(ctypes.Structure):
                 ("ms_synthesis", ctypes.c_double), ("n_ring", ctypes.c_int32),
                 ("n_analysis", ctypes.c_int32), ("n_synthesis", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("chi2_last", ctypes.c_double)]
+
+
+class wf_adaptive_opts(ctypes.Structure):
+    _fields_ = [("l_iter0", ctypes.c_int32), ("l_pad", ctypes.c_int32), ("full_band", ctypes.c_int32),
+                ("max_level_sweeps", ctypes.c_int32), ("plateau_tol", ctypes.c_double),
+                ("stop_tol", ctypes.c_double)]
+
+
+def adaptive_opts(**kw):
+    """wf_adaptive_defaults with the given fields replaced."""
+    o = wf_adaptive_opts()
+    lib().wf_adaptive_defaults(ctypes.byref(o))
+    for k, v in kw.items():
+        if k not in dict(wf_adaptive_opts._fields_):
+            raise TypeError(f"unknown adaptive option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def adaptive_levels(lmax, cl, tau, omega, **kw):
+    """Level table of the adaptive schedule (host only): list of (lambda, band limit)."""
+    cl = np.ascontiguousarray(cl, dtype=np.float64)
+    if cl.size != lmax + 1:
+        raise ValueError("cl must have lmax+1 entries")
+    cap = 64
+    lam = np.empty(cap)
+    lm = np.empty(cap, dtype=np.int32)
+    n = ctypes.c_int32()
+    o = adaptive_opts(**kw)
+    _check(lib().wf_adaptive_levels(lmax, cl.ctypes.data, tau, omega, ctypes.byref(o), cap, lam.ctypes.data,
+                                    lm.ctypes.data, ctypes.byref(n)))
+    return [(float(lam[j]), int(lm[j])) for j in range(n.value)]
 
 
 def footprint(nside, lmax, dtype=WF_F64, nmaps=1):
@@ -198,6 +238,53 @@ class Plan:
                                     lam.ctypes.data, lam.size, _stream_handle(stream), ctypes.byref(st)))
         self.last_stats = st
         return s_wf, s_alm
+
+    def solve_banded(self, d, lambdas, lmax_sht, s_wf=None, s_alm=None, stream=None, want_alm=True):
+        """One map, sweep k at band limit lmax_sht[k] (non-decreasing). Returns (s_wf, s_alm)."""
+        import torch
+        rt, ct = self._types()
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        lm = np.ascontiguousarray(lmax_sht, dtype=np.int32)
+        if lm.size != lam.size:
+            raise ValueError("need one band limit per lambda")
+        if s_wf is None:
+            s_wf = torch.empty_like(d)
+        if s_alm is None and want_alm:
+            s_alm = torch.empty((self.nalm,), dtype=ct, device=d.device)
+        aptr = _dev_ptr(s_alm, ct, self.nalm, "s_alm") if s_alm is not None else None
+        st = wf_stats()
+        _check(lib().wf_solve_banded(self.handle, _dev_ptr(d, rt, self.npix, "d"), _dev_ptr(s_wf, rt, self.npix, "s_wf"),
+                                     aptr, lam.ctypes.data, lm.ctypes.data, lam.size, _stream_handle(stream),
+                                     ctypes.byref(st)))
+        self.last_stats = st
+        return s_wf, s_alm
+
+    def solve_adaptive(self, d, max_sweeps, s_wf=None, s_alm=None, stream=None, want_alm=True, **opts):
+        """One map under the adaptive schedule (keyword options of wf_adaptive_opts).
+
+        Returns (s_wf, s_alm, info) with info = dict(lambdas, lmax_sht, chi2, converged)."""
+        import torch
+        rt, ct = self._types()
+        if s_wf is None:
+            s_wf = torch.empty_like(d)
+        if s_alm is None and want_alm:
+            s_alm = torch.empty((self.nalm,), dtype=ct, device=d.device)
+        aptr = _dev_ptr(s_alm, ct, self.nalm, "s_alm") if s_alm is not None else None
+        o = adaptive_opts(**opts)
+        lam = np.empty(max_sweeps)
+        lm = np.empty(max_sweeps, dtype=np.int32)
+        chi = np.empty(max_sweeps)
+        n, conv = ctypes.c_int32(), ctypes.c_int32()
+        st = wf_stats()
+        _check(lib().wf_solve_adaptive(self.handle, _dev_ptr(d, rt, self.npix, "d"),
+                                       _dev_ptr(s_wf, rt, self.npix, "s_wf"), aptr, ctypes.byref(o), max_sweeps,
+                                       lam.ctypes.data, lm.ctypes.data, chi.ctypes.data, ctypes.byref(n),
+                                       ctypes.byref(conv), _stream_handle(stream), ctypes.byref(st)))
+        self.last_stats = st
+        k = n.value
+        info = {"lambdas": lam[:k].copy(), "lmax_sht": lm[:k].copy(), "chi2": chi[:k].copy(),
+                "converged": bool(conv.value)}
+        return s_wf, s_alm, info
 
     def chi2(self, nmaps, nsweeps):
         """chi^2 after every sweep of the last solve (plan flag WF_FLAG_CHI2): [nmaps, nsweeps]."""
