@@ -176,6 +176,27 @@ struct Timer {
 
 thread_local Timer* g_timer = nullptr;
 
+// chi^2 of one iterate from its record: the prior term's slots plus the data term's
+// (tau N^-1 weighted, hence the division), each added in slot order.
+double chi_of_record(const double* rec, double tau) {
+  double prior = 0.0, data = 0.0;
+  for (int i = 0; i < CHI_SLOTS; ++i) {
+    prior += rec[i * CHI_SLOT_STRIDE];
+    data += rec[CHI_TERM + i * CHI_SLOT_STRIDE];
+  }
+  return prior + data / tau;
+}
+
+// The record of iterate k of map 0, copied to the host (waits for the stream).
+int read_chi_record(const wf_plan_s* p, int k, hipStream_t s, double* out) {
+  std::vector<double> rec(CHI_REC);
+  MWF_HIP(hipMemcpyAsync(rec.data(), p->chi2_buf + (size_t)CHI_REC * k, CHI_REC * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  MWF_HIP(hipStreamSynchronize(s));
+  *out = chi_of_record(rec.data(), p->tau);
+  return WF_OK;
+}
+
 struct TimerScope {
   explicit TimerScope(Timer* t) { g_timer = t->on ? t : nullptr; }
   ~TimerScope() { g_timer = nullptr; }
@@ -193,7 +214,7 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
                 const void* map_in, void* map_out, double* chi2 = nullptr) {
   PhaseBArgs a{};
   a.chi2 = chi2;
-  a.chi2_stride = 2 * (int64_t)p->chi2_cap;
+  a.chi2_stride = (int64_t)CHI_REC * p->chi2_cap;
   a.mode = mode;
   a.nmaps = nmaps;
   a.lambda = lam;
@@ -274,7 +295,7 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, 
   if (p->dtype != WF_F64) {
     MfmaArgs ma = mfma_args(p, mode, nmaps, lam, alm_in, alm_out);
     ma.chi2 = chi2;
-    ma.chi2_stride = 2 * (int64_t)p->chi2_cap;
+    ma.chi2_stride = (int64_t)CHI_REC * p->chi2_cap;
     TIMED(2, {
       MWF_HIP(launch_mfma_coeff(p->dev, ma, s));
       if (mode != SY_ALM_ONLY)
@@ -292,7 +313,7 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, 
   a.F = static_cast<double*>(p->F);
   a.bcoef = p->bcoef;
   a.chi2 = chi2;
-  a.chi2_stride = 2 * (int64_t)p->chi2_cap;
+  a.chi2_stride = (int64_t)CHI_REC * p->chi2_cap;
   TIMED(2, {
     MWF_HIP(launch_legendre_coeff(p->dev, a, s));
     if (mode != SY_ALM_ONLY) MWF_HIP(launch_legendre_synthesis_f64(p->dev, g.items_syn, g.bins_syn, g.nbins_syn, a, s));
@@ -537,14 +558,14 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
   p->chi2_nsweeps = 0;
   if (chi) {
     if (nsweeps > p->chi2_cap) {
-      if ((rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * 2 * nsweeps))) return rc;
+      if ((rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * CHI_REC * nsweeps))) return rc;
       p->chi2_cap = nsweeps;
     }
-    MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * 2 * p->chi2_cap * sizeof(double), s));
+    MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * CHI_REC * p->chi2_cap * sizeof(double), s));
     p->chi2_nsweeps = nsweeps;
     p->chi2_nmaps = nmaps;
   }
-  auto slot = [&](int k, int term) { return chi ? p->chi2_buf + 2 * k + term : nullptr; };
+  auto slot = [&](int k, int term) { return chi ? p->chi2_buf + (size_t)CHI_REC * k + term * CHI_TERM : nullptr; };
   for (int k = 0; k < nsweeps; ++k) {
     const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
     if ((rc = run_phase_b(p, s, mode, nmaps, lambda[k], d, nullptr, nullptr, k > 0 ? slot(k - 1, 1) : nullptr)))
@@ -560,12 +581,7 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
     std::memset(stats, 0, sizeof(*stats));
     stats->sweeps_done = nsweeps;
     if ((rc = timer.collect(stats))) return rc;
-    if (chi) {
-      double last[2];
-      MWF_HIP(hipMemcpyAsync(last, p->chi2_buf + 2 * (nsweeps - 1), sizeof(last), hipMemcpyDeviceToHost, s));
-      MWF_HIP(hipStreamSynchronize(s));
-      stats->chi2_last = last[0] + last[1] / p->tau;
-    }
+    if (chi && (rc = read_chi_record(p, nsweeps - 1, s, &stats->chi2_last))) return rc;
   }
   return WF_OK;
 }
@@ -577,13 +593,13 @@ int wf_chi2(wf_plan_t p, int32_t nmaps, int32_t nsweeps, double* out) {
   if (nmaps != p->chi2_nmaps || nsweeps != p->chi2_nsweeps)
     return fail(WF_EINVAL, "nmaps and nsweeps must be those of the last solve (" + std::to_string(p->chi2_nmaps) +
                                ", " + std::to_string(p->chi2_nsweeps) + ")");
-  std::vector<double> raw((size_t)nmaps * 2 * p->chi2_cap);
+  std::vector<double> raw((size_t)nmaps * CHI_REC * p->chi2_cap);
   MWF_HIP(hipStreamSynchronize(p->last_stream));
   MWF_HIP(hipMemcpy(raw.data(), p->chi2_buf, raw.size() * sizeof(double), hipMemcpyDeviceToHost));
   for (int i = 0; i < nmaps; ++i)
     for (int k = 0; k < nsweeps; ++k) {
-      const double* r = raw.data() + (size_t)i * 2 * p->chi2_cap + 2 * k;
-      out[(size_t)i * nsweeps + k] = r[0] + r[1] / p->tau;
+      const double* r = raw.data() + ((size_t)i * p->chi2_cap + k) * CHI_REC;
+      out[(size_t)i * nsweeps + k] = chi_of_record(r, p->tau);
     }
   return WF_OK;
 }
@@ -687,12 +703,12 @@ struct BandRun {
     if (k > 0 && b != cur && (rc = carry_F(cur, b, s))) return rc;
     b->last_stream = s;
     const int mode = (k == 0 ? 0 : PB_SYNTH) | PB_UPDATE | PB_ANALYSIS;
-    if ((rc = run_phase_b(b, s, mode, 1, lam, d, nullptr, nullptr, (k > 0 && chi) ? chi + 2 * (k - 1) + 1 : nullptr)))
+    if ((rc = run_phase_b(b, s, mode, 1, lam, d, nullptr, nullptr, (k > 0 && chi) ? chi + (size_t)CHI_REC * (k - 1) + CHI_TERM : nullptr)))
       return rc;
     if ((rc = after_ring())) return rc;
     if ((rc = run_analysis(b, s, 1))) return rc;
     if ((rc = run_synthesis(b, s, SY_FROM_PARTIAL, 1, lam, nullptr, write_alm ? root->alm_scratch : nullptr,
-                            chi ? chi + 2 * k : nullptr)))
+                            chi ? chi + (size_t)CHI_REC * k : nullptr)))
       return rc;
     cur = b;
     ++k;
@@ -702,7 +718,7 @@ struct BandRun {
   // The map of the last iterate (and its data term), its alm in the full layout.
   int finish(void* s_wf, void* s_alm) {
     int rc = run_phase_b(cur, s, PB_SYNTH | PB_WRITE_MAP | (chi ? PB_CHI2 : 0), 1, 1.0, chi ? d : nullptr, nullptr,
-                         s_wf, chi ? chi + 2 * (k - 1) + 1 : nullptr);
+                         s_wf, chi ? chi + (size_t)CHI_REC * (k - 1) + CHI_TERM : nullptr);
     if (rc) return rc;
     if (s_alm)
       MWF_HIP(launch_alm_repack(root->alm_scratch, cur->geo->lmax, s_alm, root->geo->lmax, root->dtype == WF_F64, s));
@@ -721,10 +737,10 @@ int ensure_alm_scratch(wf_plan_s* p) {
 // chi^2 history buffer of at least n iterates, cleared on s.
 int ensure_chi2(wf_plan_s* p, int n, hipStream_t s) {
   if (n > p->chi2_cap) {
-    if (int rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * 2 * n)) return rc;
+    if (int rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * CHI_REC * n)) return rc;
     p->chi2_cap = n;
   }
-  MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * 2 * p->chi2_cap * sizeof(double), s));
+  MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * CHI_REC * p->chi2_cap * sizeof(double), s));
   return WF_OK;
 }
 
@@ -836,12 +852,7 @@ int wf_solve_banded(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const d
     std::memset(stats, 0, sizeof(*stats));
     stats->sweeps_done = nsweeps;
     if ((rc = timer.collect(stats))) return rc;
-    if (chi) {
-      double last[2];
-      MWF_HIP(hipMemcpyAsync(last, p->chi2_buf + 2 * (nsweeps - 1), sizeof(last), hipMemcpyDeviceToHost, s));
-      MWF_HIP(hipStreamSynchronize(s));
-      stats->chi2_last = last[0] + last[1] / p->tau;
-    }
+    if (chi && (rc = read_chi_record(p, nsweeps - 1, s, &stats->chi2_last))) return rc;
   }
   return WF_OK;
 }
@@ -878,7 +889,7 @@ int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const
     if (p->chi_host) MWF_HIP(hipHostFree(p->chi_host));
     p->chi_host = nullptr;
     p->chi_host_cap = 0;
-    MWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->chi_host), (size_t)2 * max_sweeps * sizeof(double)));
+    MWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->chi_host), (size_t)CHI_REC * max_sweeps * sizeof(double)));
     p->chi_host_cap = max_sweeps;
   }
   if ((rc = ensure_chi2(p, max_sweeps, s))) return rc;
@@ -899,8 +910,8 @@ int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const
     if (it < 0) return WF_OK;
     MWF_HIP(hipEventRecord(p->ev_ring, s));
     MWF_HIP(hipStreamWaitEvent(p->copy, p->ev_ring, 0));
-    MWF_HIP(hipMemcpyAsync(p->chi_host + 2 * it, p->chi2_buf + 2 * it, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                           p->copy));
+    MWF_HIP(hipMemcpyAsync(p->chi_host + (size_t)CHI_REC * it, p->chi2_buf + (size_t)CHI_REC * it,
+                           CHI_REC * sizeof(double), hipMemcpyDeviceToHost, p->copy));
     MWF_HIP(hipEventRecord(p->ev_copied, p->copy));
     return WF_OK;
   };
@@ -924,7 +935,7 @@ int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const
     // iterate k: its terms were copied behind the ring pass of sweep k + 1, the
     // latest one started
     MWF_HIP(hipEventSynchronize(p->ev_copied));
-    chi.push_back(p->chi_host[2 * k] + p->chi_host[2 * k + 1] / p->tau);
+    chi.push_back(chi_of_record(p->chi_host + (size_t)CHI_REC * k, p->tau));
     const bool last = cur + 1 == (int)lv.size();
     int next = cur;
     if (k >= 1 && lev[k] == cur && lev[k - 1] == cur) {
@@ -946,11 +957,10 @@ int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const
   }
   if ((rc = run.finish(s_wf, s_alm))) return rc;
   const int n = run.k;
-  MWF_HIP(hipMemcpyAsync(p->chi_host + 2 * (n - 1), p->chi2_buf + 2 * (n - 1), 2 * sizeof(double),
-                         hipMemcpyDeviceToHost, s));
-  MWF_HIP(hipStreamSynchronize(s));
+  double chi_last = 0.0;
+  if ((rc = read_chi_record(p, n - 1, s, &chi_last))) return rc;
   chi.resize(n - 1);
-  chi.push_back(p->chi_host[2 * (n - 1)] + p->chi_host[2 * (n - 1) + 1] / p->tau);
+  chi.push_back(chi_last);
   for (int k = 0; k < n; ++k) chi2_out[k] = chi[k];
   *nsweeps_out = n;
   if (converged) *converged = conv ? 1 : 0;

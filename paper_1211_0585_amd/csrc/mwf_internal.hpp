@@ -142,10 +142,29 @@ struct PhaseBArgs {
 // Sum of v over each wave, added to *dst by one FP64 atomic per wave (no LDS: the
 // ring phase of the longest FP64 transforms uses all of it). Every lane of the wave
 // must call it.
+// A chi^2 term is accumulated in CHI_SLOTS partial sums, each on its own 128-byte
+// line, so that the atomics of many workgroups do not all queue on one address;
+// readers add the slots in order. A record holds the prior term's slots, then the
+// data term's.
+constexpr int CHI_SLOTS = 16;
+constexpr int CHI_SLOT_STRIDE = 16;                   // doubles between slots
+constexpr int CHI_TERM = CHI_SLOTS * CHI_SLOT_STRIDE;  // doubles per term
+constexpr int CHI_REC = 2 * CHI_TERM;                  // doubles per iterate
+
+// Sum of v over the workgroup (blockDim.x a multiple of 64, at most 1024, every
+// thread present, at most one call per kernel), added to slot blockIdx.x % CHI_SLOTS
+// of the term at dst by one atomic.
 __device__ __forceinline__ void block_sum_add(double v, double* dst) {
+  __shared__ double wsum[16];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  if ((threadIdx.x & 63) == 0 && v != 0.0) atomicAdd(dst, v);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += wsum[w];
+    if (t != 0.0) atomicAdd(dst + (blockIdx.x % CHI_SLOTS) * CHI_SLOT_STRIDE, t);
+  }
 }
 
 // Ring pairs launched together: a device list of pair indices and the largest

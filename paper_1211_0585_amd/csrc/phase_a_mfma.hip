@@ -480,20 +480,23 @@ __global__ void __launch_bounds__(64) mfma_synthesis_kernel(PlanDev P, const Wor
   synthesis_body<NP, NCT>(P, a, items[blockIdx.x], blockIdx.y);
 }
 
-// chi^2 prior term of the elements of one workgroup, added per map: through an LDS
-// slot per map when the maps fit in one workgroup, else one global atomic per element.
+// chi^2 prior term of the elements of one workgroup, added per map into the
+// workgroup's slot of the term: through an LDS entry per map when the maps fit in
+// one workgroup, else one global atomic per element.
 __device__ __forceinline__ void coeff_chi2(const MfmaArgs& a, int64_t e, bool valid, double v) {
   __shared__ double macc[COEFF_THREADS];
   const int nm = a.nmaps;
   const int map = (int)(e % nm);
+  const int slot = (blockIdx.x % CHI_SLOTS) * CHI_SLOT_STRIDE;
   if (nm <= COEFF_THREADS) {
     if (threadIdx.x < nm) macc[threadIdx.x] = 0.0;
     __syncthreads();
     if (valid && v != 0.0) atomicAdd(&macc[map], v);
     __syncthreads();
-    if ((int)threadIdx.x < nm && macc[threadIdx.x] != 0.0) atomicAdd(a.chi2 + threadIdx.x * a.chi2_stride, macc[threadIdx.x]);
+    if ((int)threadIdx.x < nm && macc[threadIdx.x] != 0.0)
+      atomicAdd(a.chi2 + threadIdx.x * a.chi2_stride + slot, macc[threadIdx.x]);
   } else if (valid && v != 0.0) {
-    atomicAdd(a.chi2 + map * a.chi2_stride, v);
+    atomicAdd(a.chi2 + map * a.chi2_stride + slot, v);
   }
 }
 
