@@ -13,7 +13,9 @@ power spectrum, anisotropic white pixel noise, and a galactic-plane cut plus
 point-source holes.
 
 Random streams: numpy PCG64 seeded by SeedSequence([seed, stream]) with
-stream 0 = signal, 1 = noise, 2 = noise model / mask (model_seed).
+stream 0 = signal, 1 = noise, 2 = noise model / mask (model_seed), 3 and 4 = the
+unit draws of constrained realisations (SeedSequence([seed, map, 3]) per map for
+the alm draws, [seed, 4] for the pixel draws).
 """
 import numpy as np
 
@@ -53,7 +55,8 @@ def cl_satellite(lmax, amp=1e3, fwhm_arcmin=13.0, peaks=(220.0, 540.0, 800.0),
 def random_alm(cl, lmax, seed):
     """Gaussian alm of a real field with spectrum cl, packed m-major
     (index m*(2*lmax+1-m)/2 + l): a_l0 = sqrt(C_l) g, a_lm = sqrt(C_l/2)(g1 + i g2)."""
-    g = rng(seed, 0)
+    g = rng(seed, 0) if np.isscalar(seed) else np.random.Generator(
+        np.random.PCG64(np.random.SeedSequence([int(x) for x in seed])))
     cl = np.asarray(cl, dtype=np.float64)
     out = []
     for m in range(lmax + 1):
@@ -70,6 +73,17 @@ def random_alm(cl, lmax, seed):
 def noise_draw(sigma2, seed):
     """n_p = sigma_p g_p (drawn everywhere, also where the pixel is masked)."""
     return np.sqrt(sigma2) * rng(seed, 1).standard_normal(np.size(sigma2))
+
+
+def fluctuation_draws(npix, lmax, seed, nmaps=1):
+    """Unit draws of a constrained realisation, one set per map: xi, packed alm with
+    E|xi_lm|^2 = 1 (real N(0,1) at m = 0, (g1 + i g2)/sqrt 2 above), from stream 3;
+    eta, N(0,1) per pixel, from stream 4. Shapes [nmaps, N_lm] and [nmaps, npix]."""
+    ones = np.ones(lmax + 1)
+    xi = np.stack([random_alm(ones, lmax, (seed, i, 3)) for i in range(nmaps)])
+    g = rng(seed, 4)
+    eta = g.standard_normal((nmaps, npix))
+    return xi, eta
 
 
 def unit_vectors(theta, phi):
