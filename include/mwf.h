@@ -227,6 +227,29 @@ int wf_solve_adaptive(wf_plan_t plan, const void* d, void* s_wf, void* s_alm,
                       wf_stats* stats);
 
 /*
+ * wf_constrained_batch -- constrained realisations (Sect. 3: the Wiener-filter map plus
+ * a fluctuation map has the fiducial power spectrum). For each map i, with a signal
+ * draw s_rand from S and a noise draw n_rand from N built from the caller's unit
+ * normal draws,
+ *   s_rand   = sum_lm sqrt(C_l) xi_lm Y_lm         (xi_l0 real: its imaginary part is ignored)
+ *   n_rand_p = eta_p / sqrt(ninv_p)                (0 where unobserved)
+ *   s_CR     = s_rand + WF(d - s_rand - n_rand)
+ * where WF is the messenger solve of wf_solve_batch with the same lambda schedule.
+ *   d      device, nmaps * npix (plan dtype): the data maps
+ *   xi     device, nmaps * 2 N_lm (plan dtype): packed alm of unit draws,
+ *          E|xi_lm|^2 = 1 (real N(0,1) at m = 0, (g1 + i g2)/sqrt 2 above)
+ *   eta    device, nmaps * npix (plan dtype): N(0,1) per pixel
+ *   s_cr   device, nmaps * npix: receives s_CR
+ *   s_alm  device, nmaps * 2 N_lm, or NULL: receives the alm of s_CR
+ * The plan keeps three work buffers for this call (two maps and one alm set per
+ * map of max_batch), made on first use. Errors: as wf_solve_batch, and WF_EINVAL for
+ * NULL xi or eta.
+ */
+int wf_constrained_batch(wf_plan_t plan, int32_t nmaps, const void* d, const void* xi,
+                         const void* eta, void* s_cr, void* s_alm, const double* lambda,
+                         int32_t nsweeps, void* hip_stream, wf_stats* stats);
+
+/*
  * sht_map2alm -- forward transform of nmaps maps: a_lm = Omega sum_p conj(Y_lm(p)) f_p
  * (the basis change of Sect. 2 from pixels to harmonics).
  *   map  device, nmaps * npix elements; alm device, nmaps * 2 N_lm elements.

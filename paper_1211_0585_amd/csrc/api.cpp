@@ -609,6 +609,38 @@ int wf_solve(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const double* 
   return wf_solve_batch(p, 1, d, s_wf, s_alm, lambda, nsweeps, hip_stream, stats);
 }
 
+int wf_constrained_batch(wf_plan_t p, int32_t nmaps, const void* d, const void* xi, const void* eta, void* s_cr,
+                         void* s_alm, const double* lambda, int32_t nsweeps, void* hip_stream, wf_stats* stats) {
+  int rc = check_batch(p, nmaps);
+  if (rc) return rc;
+  if (!d || !xi || !eta || !s_cr) return fail(WF_EINVAL, "d, xi, eta and s_cr must not be NULL");
+  if ((rc = check_schedule(lambda, nsweeps))) return rc;
+  const Geometry& g = *p->geo;
+  if (!p->cr_map) {
+    uint8_t *a = nullptr, *b = nullptr, *c = nullptr;
+    const size_t maps = (size_t)p->max_batch * g.npix * p->elem;
+    if ((rc = p->mem.alloc(&a, maps)) || (rc = p->mem.alloc(&b, maps)) ||
+        (rc = p->mem.alloc(&c, (size_t)p->max_batch * g.nalm * 2 * p->elem)))
+      return rc;
+    p->cr_map = a;
+    p->cr_d = b;
+    p->cr_alm = c;
+  }
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  p->last_stream = s;
+  const bool fp64 = p->dtype == WF_F64;
+  // the signal draw: alm sqrt(C_l) xi, synthesised to s_rand
+  MWF_HIP(launch_cr_alm(p->cl, g.lmax, g.nalm, nmaps, xi, p->cr_alm, false, fp64, s));
+  if ((rc = run_synthesis(p, s, SY_FROM_ALM, nmaps, 1.0, p->cr_alm, nullptr))) return rc;
+  if ((rc = run_phase_b(p, s, PB_SYNTH | PB_WRITE_MAP, nmaps, 1.0, nullptr, nullptr, p->cr_map))) return rc;
+  // the Wiener filter of d - s_rand - n_rand, then s_rand added back
+  MWF_HIP(launch_cr_data(d, p->cr_map, eta, p->q, p->tau, p->cr_d, g.npix, nmaps, fp64, s));
+  if ((rc = wf_solve_batch(p, nmaps, p->cr_d, s_cr, s_alm, lambda, nsweeps, hip_stream, stats))) return rc;
+  MWF_HIP(launch_cr_add(s_cr, p->cr_map, (int64_t)nmaps * g.npix, fp64, s));
+  if (s_alm) MWF_HIP(launch_cr_alm(p->cl, g.lmax, g.nalm, nmaps, xi, s_alm, true, fp64, s));
+  return WF_OK;
+}
+
 int sht_map2alm(wf_plan_t p, int32_t nmaps, const void* map, void* alm, void* hip_stream) {
   int rc = check_batch(p, nmaps);
   if (rc) return rc;

@@ -133,6 +133,13 @@ int run_group_step(const TaskDev* tasks, const int64_t* offs, const int64_t* nbl
                    int ntasks, int dtype, const Tuning& tune, bool synth_only, hipStream_t s);
 size_t plan_buffer_bytes(int nside, int lmax, int dtype, int nmaps);
 size_t geometry_bytes(int nside, int lmax);
+// Constrained realisations: out (+)= sqrt(C_l) xi over nmaps packed alm sets; the data
+// map d - s_rand - eta sqrt(tau / q); out += s_rand.
+hipError_t launch_cr_alm(const double* cl, int lmax, int64_t nalm, int nmaps, const void* xi, void* out,
+                         bool accumulate, bool fp64, hipStream_t s);
+hipError_t launch_cr_data(const void* d, const void* srand, const void* eta, const void* q, double tau, void* out,
+                          int64_t npix, int nmaps, bool fp64, hipStream_t s);
+hipError_t launch_cr_add(void* out, const void* srand, int64_t total, bool fp64, hipStream_t s);
 // Packed alm of band limit ls into the packed layout of band limit ld >= ls (zero above ls).
 hipError_t launch_alm_repack(const void* src, int ls, void* dst, int ld, bool fp64, hipStream_t s);
 
@@ -171,6 +178,10 @@ struct wf_plan_s {
   // share q and cl with this plan (which owns both) and hold their own work buffers.
   std::map<int, wf_plan_s*> band;
   void* alm_scratch = nullptr;         // packed alm of the latest sweep (any band limit)
+  // constrained realisations: signal draw (map, alm) and the modified data, max_batch maps
+  void* cr_map = nullptr;
+  void* cr_alm = nullptr;
+  void* cr_d = nullptr;
   // adaptive solve: chi^2 terms copied to pinned host memory on a copy stream
   double* chi_host = nullptr;
   int chi_host_cap = 0;

@@ -45,6 +45,8 @@ _SIGS = [
     ("wf_server_query", _c.c_int, [_c.c_void_p, _c.c_void_p]),
     ("wf_server_destroy", None, [_c.c_void_p]),
     ("wf_chi2", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_int32, _c.c_void_p]),
+    ("wf_constrained_batch", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                        _c.c_void_p, _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p]),
     ("wf_solve_banded", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                    _c.c_int32, _c.c_void_p, _c.c_void_p]),
     ("wf_adaptive_defaults", None, [_c.c_void_p]),
@@ -238,6 +240,28 @@ class Plan:
                                     lam.ctypes.data, lam.size, _stream_handle(stream), ctypes.byref(st)))
         self.last_stats = st
         return s_wf, s_alm
+
+    def constrained(self, d, xi, eta, lambdas, s_cr=None, s_alm=None, stream=None, want_alm=True):
+        """Constrained realisations s_rand + WF(d - s_rand - n_rand) from unit draws xi
+        (packed alm, complex) and eta (per pixel); d, eta: [npix] or [nmaps, npix]."""
+        import torch
+        rt, ct = self._types()
+        nmaps = 1 if d.dim() == 1 else d.shape[0]
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        if s_cr is None:
+            s_cr = torch.empty_like(d)
+        if s_alm is None and want_alm:
+            shape = (self.nalm,) if d.dim() == 1 else (nmaps, self.nalm)
+            s_alm = torch.empty(shape, dtype=ct, device=d.device)
+        aptr = _dev_ptr(s_alm, ct, nmaps * self.nalm, "s_alm") if s_alm is not None else None
+        st = wf_stats()
+        _check(lib().wf_constrained_batch(self.handle, nmaps, _dev_ptr(d, rt, nmaps * self.npix, "d"),
+                                          _dev_ptr(xi, ct, nmaps * self.nalm, "xi"),
+                                          _dev_ptr(eta, rt, nmaps * self.npix, "eta"),
+                                          _dev_ptr(s_cr, rt, nmaps * self.npix, "s_cr"), aptr, lam.ctypes.data,
+                                          lam.size, _stream_handle(stream), ctypes.byref(st)))
+        self.last_stats = st
+        return s_cr, s_alm
 
     def solve_banded(self, d, lambdas, lmax_sht, s_wf=None, s_alm=None, stream=None, want_alm=True):
         """One map, sweep k at band limit lmax_sht[k] (non-decreasing). Returns (s_wf, s_alm)."""
