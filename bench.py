@@ -49,6 +49,13 @@ def parse():
                     help="length of the Poisson request stream (0 skips serving)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
     ap.add_argument("--serve-nsides", default="64,128,256,512,1024")
+    ap.add_argument("--adaptive-repeats", type=int, default=3,
+                    help="timed runs of the adaptive solve (Sect. 3 cooling with band-limited "
+                         "transforms) on the plain workload; 0 skips it")
+    ap.add_argument("--adaptive-max-sweeps", type=int, default=1000)
+    ap.add_argument("--constrained-repeats", type=int, default=3,
+                    help="timed constrained realisations (Wiener filter plus fluctuation map) on the "
+                         "plain workload with the fixed schedule; 0 skips them")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run N plain 512 MiB device copies (reference for HBM byte counters)")
     return ap.parse_args()
@@ -165,6 +172,14 @@ def main():
         batched = run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside, lmax, K, W,
                               value)
 
+    adapt = {}
+    if args.adaptive_repeats > 0:
+        adapt = run_adaptive(args, np, torch, mwf, plan, d, case, sched, lat)
+
+    cres = {}
+    if args.constrained_repeats > 0:
+        cres = run_constrained(args, np, torch, mwf, synth, plan, d, sched, lat, dev)
+
     mixed = {}
     if args.mixed:
         mixed = run_mixed(args, np, torch, mwf, synth, dev, K, W)
@@ -211,6 +226,8 @@ def main():
                               "sweeps": int(len(sched)), "repeats": int(len(lat))} if len(lat) else None),
         "kernels": kern,
         "batched": batched,
+        "adaptive": adapt,
+        "constrained": cres,
         "mixed_batch": mixed,
         "serving": serving,
         "roofline": roof,
@@ -272,6 +289,79 @@ def run_batched(args, np, torch, mwf, synth, theta, phi, case, lams, dev, nside,
         out["vs_plain_f64"][name] = mit / plain_value
         log(f"[bench] batched {name}: {mit:.0f} map-it/s ({1e3 * el / K:.2f} ms per sweep of {B} maps)")
     return out
+
+
+def run_adaptive(args, np, torch, mwf, plan, d, case, sched, lat):
+    """The paper's adaptive schedule (Sect. 3) on the plain FP64 workload: lambda from
+    l_iter = 20, doubled on a chi^2 plateau, stop at lambda = 1 once chi^2 gains less
+    than 1e-4 sigma; transforms cut at l_iter + 100. Timed against the same decision
+    rules at the full band limit and against the fixed 80-sweep schedule."""
+    mx = args.adaptive_max_sweeps
+    n_obs = int(np.count_nonzero(case["ninv"] > 0))
+
+    def timed(**opts):
+        plan.solve_adaptive(d, mx, want_alm=False, **opts)          # warm-up: band-limited plans
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(args.adaptive_repeats):
+            a = time.perf_counter()
+            _, _, info = plan.solve_adaptive(d, mx, want_alm=False, **opts)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - a))
+        return float(np.median(ms)), info
+
+    log("[bench] adaptive schedule with band-limited transforms")
+    ms_t, it = timed()
+    log(f"[bench] adaptive: {len(it['chi2'])} sweeps in {ms_t:.1f} ms, bands {sorted(set(it['lmax_sht'].tolist()))}")
+    ms_f, itf = timed(full_band=1)
+    log(f"[bench] adaptive at full band: {len(itf['chi2'])} sweeps in {ms_f:.1f} ms")
+    levels = []
+    for lam, band in zip(it["lambdas"].tolist(), it["lmax_sht"].tolist()):
+        if levels and levels[-1]["lambda"] == lam:
+            levels[-1]["sweeps"] += 1
+        else:
+            levels.append({"lambda": lam, "lmax_sht": band, "sweeps": 1})
+    cplan = mwf.Plan(plan.nside, plan.lmax, case["cl"], case["ninv"], mask=~case["mask"], flags=mwf.WF_FLAG_CHI2)
+    cplan.solve(d, sched, want_alm=False)
+    chi_fixed = cplan.last_stats.chi2_last
+    cplan.close()
+    ms_fixed = float(np.percentile(lat, 50)) if len(lat) else None
+    return {
+        "options": {"l_iter0": 20, "l_pad": 100, "plateau_tol": 1.0, "stop_tol": 1e-4, "max_level_sweeps": 50,
+                    "max_sweeps": mx},
+        "sweeps": int(len(it["chi2"])), "converged": bool(it["converged"]), "levels": levels,
+        "ms": ms_t, "ms_per_sweep": ms_t / len(it["chi2"]),
+        "chi2_final": float(it["chi2"][-1]), "chi2_per_obs": float(it["chi2"][-1]) / n_obs, "n_obs": n_obs,
+        "full_band": {"sweeps": int(len(itf["chi2"])), "ms": ms_f, "chi2_final": float(itf["chi2"][-1]),
+                      "converged": bool(itf["converged"])},
+        "fixed_schedule": {"sweeps": int(len(sched)), "ms": ms_fixed, "chi2_final": float(chi_fixed)},
+        "speedup_vs_full_band": ms_f / ms_t,
+        "speedup_vs_fixed": (ms_fixed / ms_t) if ms_fixed else None,
+        "repeats": args.adaptive_repeats,
+    }
+
+
+def run_constrained(args, np, torch, mwf, synth, plan, d, sched, lat, dev):
+    """One constrained realisation (Sect. 3 figure) of the plain FP64 workload with the
+    fixed schedule: signal and noise draws, the solve of the modified data, the sum.
+    The unit draws are made on the host and resident in HBM before timing."""
+    xi, eta = synth.fluctuation_draws(plan.npix, plan.lmax, 1)
+    X = torch.from_numpy(xi[0]).to(dev)
+    E = torch.from_numpy(eta[0]).to(dev)
+    plan.constrained(d, X, E, sched, want_alm=False)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(args.constrained_repeats):
+        a = time.perf_counter()
+        plan.constrained(d, X, E, sched, want_alm=False)
+        torch.cuda.synchronize()
+        ms.append(1e3 * (time.perf_counter() - a))
+    med = float(np.median(ms))
+    solve_ms = float(np.percentile(lat, 50)) if len(lat) else None
+    log(f"[bench] constrained realisation: {med:.2f} ms ({len(sched)} sweeps)")
+    return {"sweeps": int(len(sched)), "ms": med, "solve_ms": solve_ms,
+            "overhead_vs_solve": (med / solve_ms - 1.0) if solve_ms else None,
+            "repeats": args.constrained_repeats}
 
 
 def run_mixed(args, np, torch, mwf, synth, dev, K, W):
