@@ -210,6 +210,16 @@ struct TimerScope {
   } while (0)
 
 // ---------------------------------------------------------------- plan-level launches
+// The plan's second stream and its fork / join events (default priority), made on
+// first use; band-limited plans borrow their parent's.
+int ensure_aux(wf_plan_s* p) {
+  if (p->aux) return WF_OK;
+  MWF_HIP(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+  MWF_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  MWF_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  return WF_OK;
+}
+
 int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, const void* d,
                 const void* map_in, void* map_out, double* chi2 = nullptr) {
   PhaseBArgs a{};
@@ -234,11 +244,7 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
     TIMED(0, MWF_HIP(launch_phase_b(p->dev, a, cls, fp32, s)));
     return WF_OK;
   }
-  if (!p->aux) {
-    MWF_HIP(hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
-    MWF_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
-    MWF_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
-  }
+  if (int rc = ensure_aux(p)) return rc;
   // Bluestein rings of the longest transform on the second stream; on this one the
   // shorter Bluestein rings (their smaller LDS lets them share the chip with the
   // long ones), then the power-of-two rings
@@ -692,6 +698,16 @@ int band_plan(wf_plan_s* p, int L, wf_plan_s** out) {
   b->q = p->q;
   b->cl = p->cl;
   b->n_obs = p->n_obs;
+  // one second stream for the whole family of plans: each stream a process holds
+  // takes a share of the few hardware queues, also from unrelated work
+  if (int rc = ensure_aux(p)) {
+    delete b;
+    return rc;
+  }
+  b->aux = p->aux;
+  b->ev_fork = p->ev_fork;
+  b->ev_join = p->ev_join;
+  b->owns_aux = false;
   if (int rc = plan_alloc(b)) {
     delete b;
     return rc;
@@ -912,8 +928,8 @@ int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const
     if ((rc = band_plan(p, l.L, &b))) return rc;
   }
   if ((rc = ensure_alm_scratch(p))) return rc;
-  if (!p->copy) {
-    MWF_HIP(hipStreamCreateWithFlags(&p->copy, hipStreamNonBlocking));
+  if ((rc = ensure_aux(p))) return rc;
+  if (!p->ev_ring) {
     MWF_HIP(hipEventCreateWithFlags(&p->ev_ring, hipEventDisableTiming));
     MWF_HIP(hipEventCreateWithFlags(&p->ev_copied, hipEventDisableTiming));
   }
@@ -936,15 +952,15 @@ int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const
   run.d = d;
   run.chi = p->chi2_buf;
   // once the ring pass of sweep k + 1 is enqueued, the two terms of iterate k are
-  // copied out on the copy stream, behind that pass only
+  // copied out on the plan's second stream, behind that pass only
   auto copy_terms = [&]() -> int {
     const int it = run.k - 1;
     if (it < 0) return WF_OK;
     MWF_HIP(hipEventRecord(p->ev_ring, s));
-    MWF_HIP(hipStreamWaitEvent(p->copy, p->ev_ring, 0));
+    MWF_HIP(hipStreamWaitEvent(p->aux, p->ev_ring, 0));
     MWF_HIP(hipMemcpyAsync(p->chi_host + (size_t)CHI_REC * it, p->chi2_buf + (size_t)CHI_REC * it,
-                           CHI_REC * sizeof(double), hipMemcpyDeviceToHost, p->copy));
-    MWF_HIP(hipEventRecord(p->ev_copied, p->copy));
+                           CHI_REC * sizeof(double), hipMemcpyDeviceToHost, p->aux));
+    MWF_HIP(hipEventRecord(p->ev_copied, p->aux));
     return WF_OK;
   };
   std::vector<int> lev;

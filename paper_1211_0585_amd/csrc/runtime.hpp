@@ -171,6 +171,7 @@ struct wf_plan_s {
   // with the fork / join events; created on first use
   hipStream_t aux = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  bool owns_aux = true;                // false for band-limited plans (the parent's)
   // host copies kept for the truncated solves
   std::vector<double> cl_host;         // C_l, l = 0..lmax
   int64_t n_obs = 0;                   // observed pixels (ninv > 0, not masked)
@@ -182,29 +183,24 @@ struct wf_plan_s {
   void* cr_map = nullptr;
   void* cr_alm = nullptr;
   void* cr_d = nullptr;
-  // adaptive solve: chi^2 terms copied to pinned host memory on a copy stream
+  // adaptive solve: chi^2 terms copied to pinned host memory on the second stream
   double* chi_host = nullptr;
   int chi_host_cap = 0;
-  hipStream_t copy = nullptr;
   hipEvent_t ev_ring = nullptr, ev_copied = nullptr;
   ~wf_plan_s() {
-    if (aux) {
-      hipStreamSynchronize(aux);
-      hipStreamDestroy(aux);
-    }
-    if (ev_fork) hipEventDestroy(ev_fork);
-    if (ev_join) hipEventDestroy(ev_join);
-    if (copy) {
-      hipStreamSynchronize(copy);
-      hipStreamDestroy(copy);
-    }
-    if (ev_ring) hipEventDestroy(ev_ring);
-    if (ev_copied) hipEventDestroy(ev_copied);
-    if (chi_host) hipHostFree(chi_host);
     for (auto& kv : band) {
       hipStreamSynchronize(kv.second->last_stream);
       delete kv.second;
     }
+    if (aux && owns_aux) {
+      hipStreamSynchronize(aux);
+      hipStreamDestroy(aux);
+      if (ev_fork) hipEventDestroy(ev_fork);
+      if (ev_join) hipEventDestroy(ev_join);
+    }
+    if (ev_ring) hipEventDestroy(ev_ring);
+    if (ev_copied) hipEventDestroy(ev_copied);
+    if (chi_host) hipHostFree(chi_host);
   }
 };
 
