@@ -75,7 +75,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"libmwf.so not built ({LIB_PATH}); run __graft_entry__.build()")
+            raise RuntimeError(f"libmwf.so not built ({LIB_PATH}); run python -m paper_1211_0585_amd.build")
         L = ctypes.CDLL(LIB_PATH)
         for name, res, args in _SIGS:
             f = getattr(L, name)
