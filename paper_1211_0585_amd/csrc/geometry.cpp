@@ -232,6 +232,7 @@ int build_geometry(Geometry& g) {
   D.npairs = g.npairs;
   D.pairs = g.pairs;
   D.A = g.A;
+  D.C = g.C;
   D.row_off = g.row_off;
   D.norm_m = g.norm;
   std::vector<uint16_t> wake((size_t)(lmax + 1) * g.npairs);
