@@ -225,6 +225,9 @@ def main():
         "solve_latency_ms": ({"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                               "sweeps": int(len(sched)), "repeats": int(len(lat))} if len(lat) else None),
         "kernels": kern,
+        "polar_skip": {"units_all": int(plan.units_all), "units_active": int(plan.units_active),
+                       "skipped_frac": 1.0 - plan.units_active / plan.units_all,
+                       "threshold": "lambda_lm below 2^-448 for every l <= lmax"},
         "batched": batched,
         "adaptive": adapt,
         "constrained": cres,
