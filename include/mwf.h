@@ -208,8 +208,8 @@ int wf_adaptive_levels(int32_t lmax, const double* cl, double tau, double omega,
 /*
  * wf_solve_adaptive -- the messenger iteration of one map from s = t = 0 under the
  * adaptive schedule above, with the band limit of each level (wf_solve_banded).
- * Waits for its own work: the host reads the chi^2 of every iterate (a 16-byte
- * copy on a second stream while the sweep's Legendre work runs).
+ * Waits for its own work: the host reads the chi^2 of every iterate (a 4 KB copy
+ * on the plan's second stream while the sweep's Legendre work runs).
  *   d, s_wf, s_alm  as for wf_solve (s_alm may be NULL)
  *   opts            NULL for wf_adaptive_defaults
  *   max_sweeps      >= 1
