@@ -187,6 +187,19 @@ double chi_of_record(const double* rec, double tau) {
   return prior + data / tau;
 }
 
+// chi^2 history buffer ([map][CHI_REC chi2_cap]) for at least `maps` maps and n
+// iterates, cleared on s. Kernels find map i at chi2 + i CHI_REC chi2_cap.
+int ensure_chi2(wf_plan_s* p, int maps, int n, hipStream_t s) {
+  if (n > p->chi2_cap || maps > p->chi2_maps) {
+    const int cap = std::max(n, p->chi2_cap), nm = std::max(maps, p->chi2_maps);
+    if (int rc = p->mem.alloc(&p->chi2_buf, (size_t)nm * CHI_REC * cap)) return rc;
+    p->chi2_cap = cap;
+    p->chi2_maps = nm;
+  }
+  MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->chi2_maps * CHI_REC * p->chi2_cap * sizeof(double), s));
+  return WF_OK;
+}
+
 // The record of iterate k of map 0, copied to the host (waits for the stream).
 int read_chi_record(const wf_plan_s* p, int k, hipStream_t s, double* out) {
   std::vector<double> rec(CHI_REC);
@@ -563,11 +576,7 @@ int wf_solve_batch(wf_plan_t p, int32_t nmaps, const void* d, void* s_wf, void* 
   const bool chi = (p->flags & WF_FLAG_CHI2) != 0;
   p->chi2_nsweeps = 0;
   if (chi) {
-    if (nsweeps > p->chi2_cap) {
-      if ((rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * CHI_REC * nsweeps))) return rc;
-      p->chi2_cap = nsweeps;
-    }
-    MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * CHI_REC * p->chi2_cap * sizeof(double), s));
+    if ((rc = ensure_chi2(p, nmaps, nsweeps, s))) return rc;
     p->chi2_nsweeps = nsweeps;
     p->chi2_nmaps = nmaps;
   }
@@ -782,15 +791,6 @@ int ensure_alm_scratch(wf_plan_s* p) {
   return WF_OK;
 }
 
-// chi^2 history buffer of at least n iterates, cleared on s.
-int ensure_chi2(wf_plan_s* p, int n, hipStream_t s) {
-  if (n > p->chi2_cap) {
-    if (int rc = p->mem.alloc(&p->chi2_buf, (size_t)p->max_batch * CHI_REC * n)) return rc;
-    p->chi2_cap = n;
-  }
-  MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->max_batch * CHI_REC * p->chi2_cap * sizeof(double), s));
-  return WF_OK;
-}
 
 int check_adaptive_opts(const wf_adaptive_opts& o) {
   if (o.l_iter0 < 1) return fail(WF_EINVAL, "l_iter0 must be >= 1");
@@ -883,7 +883,7 @@ int wf_solve_banded(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const d
   const bool chi = (p->flags & WF_FLAG_CHI2) != 0;
   p->chi2_nsweeps = 0;
   if (chi) {
-    if ((rc = ensure_chi2(p, nsweeps, s))) return rc;
+    if ((rc = ensure_chi2(p, 1, nsweeps, s))) return rc;
     p->chi2_nsweeps = nsweeps;
     p->chi2_nmaps = 1;
   }
@@ -940,7 +940,7 @@ int wf_solve_adaptive(wf_plan_t p, const void* d, void* s_wf, void* s_alm, const
     MWF_HIP(hipHostMalloc(reinterpret_cast<void**>(&p->chi_host), (size_t)CHI_REC * max_sweeps * sizeof(double)));
     p->chi_host_cap = max_sweeps;
   }
-  if ((rc = ensure_chi2(p, max_sweeps, s))) return rc;
+  if ((rc = ensure_chi2(p, 1, max_sweeps, s))) return rc;
   Timer timer;
   timer.on = (p->flags & WF_FLAG_TIMING) != 0;
   timer.s = s;

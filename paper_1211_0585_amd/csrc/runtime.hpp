@@ -163,8 +163,8 @@ struct wf_plan_s {
   double2* bcoef = nullptr;            // FP64: [batch][rows_total]
   float* partial32 = nullptr;          // matrix cores: [blk128][nalm][batch][2]
   float* bcoef32 = nullptr;            // matrix cores: [rows_total][batch][2]
-  double* chi2_buf = nullptr;          // WF_FLAG_CHI2: [batch][2 chi2_cap] (prior, data / tau) per iterate
-  int chi2_cap = 0, chi2_nsweeps = 0, chi2_nmaps = 0;
+  double* chi2_buf = nullptr;          // chi^2 history: [chi2_maps][CHI_REC chi2_cap], one record per iterate
+  int chi2_cap = 0, chi2_maps = 0, chi2_nsweeps = 0, chi2_nmaps = 0;
   mwf::PlanDev dev{};
   mwf::DevMem mem;
   // second stream for ring classes that run side by side (default priority),
