@@ -114,10 +114,16 @@ def iteration_matrix(ninv, cl, lam, nside, lmax):
     return fd[:, None] * (omega * (Y.T @ ((1.0 - w)[:, None] * Y)))
 
 
+def gram_matrix(nside, lmax):
+    """(Omega Y^T Y, modes): the Gram matrix of the real basis functions l <= lmax under
+    the pixel-area sum (the identity for an exact quadrature)."""
+    modes = real_modes(lmax)
+    Y = synthesis_matrix(nside, lmax, modes)
+    return healpix.pixel_area(nside) * (Y.T @ Y), modes
+
+
 def gram_defect(nside, lmax):
     """|| I - Omega Y^T Y ||_2 over all modes l <= lmax: how far the pixel-area
     analysis is from inverting the synthesis (zero for an exact quadrature)."""
-    modes = real_modes(lmax)
-    Y = synthesis_matrix(nside, lmax, modes)
-    G = healpix.pixel_area(nside) * (Y.T @ Y)
+    G, modes = gram_matrix(nside, lmax)
     return float(np.linalg.norm(np.eye(len(modes)) - G, 2))

@@ -201,3 +201,105 @@ def _finish(cl, sigma2, mask, lmax, seed, schedule):
         "schedule": schedule,
         "lmax": lmax,
     }
+
+
+# ------------------------------------------------------------------ polarisation (T, Q, U)
+def cl_pol(cl_tt, e_frac=0.05, b_frac=0.01, te_corr=0.5, te_period=150.0):
+    """Four spectra [TT, EE, BB, TE] from a temperature spectrum: EE = e_frac TT,
+    BB = b_frac EE, TE = rho_l sqrt(TT EE) with rho_l = te_corr cos(pi l / te_period)
+    (|rho| < 1 keeps every 2x2 TE block positive definite). E and B start at l = 2."""
+    tt = np.asarray(cl_tt, dtype=np.float64)
+    l = np.arange(tt.size, dtype=np.float64)
+    ee = e_frac * tt
+    bb = b_frac * ee
+    te = te_corr * np.cos(np.pi * l / te_period) * np.sqrt(tt * ee)
+    ee[:2] = bb[:2] = te[:2] = 0.0
+    return np.stack([tt, ee, bb, te])
+
+
+def random_alm_pol(cl4, lmax, seed):
+    """Gaussian [T, E, B] alm with the 3x3 spectrum of cl4 (signal stream of `seed`):
+    T = sqrt(TT) g1, E = TE/sqrt(TT) g1 + sqrt(EE - TE^2/TT) g2, B = sqrt(BB) g3, each g
+    real at m = 0 and (g' + i g'')/sqrt 2 above, drawn m by m in packed order."""
+    tt, ee, bb, te = (np.asarray(c, dtype=np.float64) for c in cl4)
+    g = rng(seed, 0)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        c_te = np.where(tt > 0, te / np.sqrt(np.where(tt > 0, tt, 1.0)), 0.0)
+        c_ee = np.sqrt(np.maximum(ee - np.where(tt > 0, te * te / np.where(tt > 0, tt, 1.0), 0.0), 0.0))
+    out = [[], [], []]
+    for m in range(lmax + 1):
+        n = lmax + 1 - m
+        if m == 0:
+            g1, g2, g3 = (g.standard_normal(n) + 0j for _ in range(3))
+        else:
+            g1, g2, g3 = ((g.standard_normal(n) + 1j * g.standard_normal(n)) * np.sqrt(0.5) for _ in range(3))
+        sl = slice(m, lmax + 1)
+        out[0].append(np.sqrt(tt[sl]) * g1)
+        out[1].append(c_te[sl] * g1 + c_ee[sl] * g2)
+        out[2].append(np.sqrt(bb[sl]) * g3)
+    return np.stack([np.concatenate(o) for o in out])
+
+
+def pol_noise_model(sigma2_t, p_factor=2.0, qu_corr_max=0.3, model_seed=0):
+    """Per-pixel 3x3 noise covariance: T variance sigma2_t, Q and U variance
+    p_factor sigma2_t with a Q-U correlation coefficient drawn uniformly in
+    [-qu_corr_max, qu_corr_max] per pixel (stream 5 of model_seed); T uncorrelated with
+    Q and U. Returns (cov6, ninv6), each [6, npix] in the order TT, QQ, UU, TQ, TU, QU;
+    ninv6 is the inverse of the covariance (the QU block inverted in closed form)."""
+    s2 = np.asarray(sigma2_t, dtype=np.float64)
+    rho = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(model_seed), 5]))).uniform(
+        -qu_corr_max, qu_corr_max, s2.size)
+    sp = p_factor * s2
+    z = np.zeros_like(s2)
+    cov6 = np.stack([s2, sp, sp, z, z, rho * sp])
+    det = sp * sp * (1.0 - rho * rho)
+    ninv6 = np.stack([1.0 / s2, sp / det, sp / det, z, z, -rho * sp / det])
+    return cov6, ninv6
+
+
+def pol_noise_draw(cov6, seed):
+    """Noise maps [3, npix] with the per-pixel covariance cov6 (Cholesky of each 3x3
+    block), from the noise stream of `seed`; drawn everywhere, also where masked."""
+    tt, qq, uu, tq, tu, qu = np.asarray(cov6, dtype=np.float64)
+    g = rng(seed, 1).standard_normal((3, tt.size))
+    l00 = np.sqrt(tt)
+    l10 = tq / l00
+    l20 = tu / l00
+    l11 = np.sqrt(qq - l10 * l10)
+    l21 = (qu - l20 * l10) / l11
+    l22 = np.sqrt(uu - l20 * l20 - l21 * l21)
+    return np.stack([l00 * g[0], l10 * g[0] + l11 * g[1], l20 * g[0] + l21 * g[1] + l22 * g[2]])
+
+
+def pol_mask_bits(mask_t, mask_p):
+    """Mask bytes: bit 0 set where T is observed, bit 1 where Q/U are (True = masked in)."""
+    return ((~np.asarray(mask_t)).astype(np.uint8) | ((~np.asarray(mask_p)).astype(np.uint8) << 1))
+
+
+def pol_small_case(theta, lmax, seed=0, model_seed=0):
+    """Small polarised case (Nside 4..64 tests): TT = 1e3/(l(l+1)), cl_pol defaults;
+    T noise (30 muK)^2 / h_p as in the small band case, P noise twice that with Q-U
+    correlations; T mask |theta - pi/2| < 0.35 rad, P mask |theta - pi/2| < 0.5 rad."""
+    lmax = int(lmax)
+    cl4 = cl_pol(cl_power_law(lmax))
+    h = np.exp(0.5 * rng(model_seed, 2).standard_normal(theta.size))
+    cov6, ninv6 = pol_noise_model((30.0 * MUK) ** 2 / h, model_seed=model_seed)
+    mask_t = np.abs(theta - 0.5 * np.pi) < 0.35
+    mask_p = np.abs(theta - 0.5 * np.pi) < 0.5
+    return {"cl4": cl4, "cov6": cov6, "ninv6": ninv6, "mask": pol_mask_bits(mask_t, mask_p),
+            "mask_t": mask_t, "mask_p": mask_p, "lmax": lmax,
+            "signal_alm": random_alm_pol(cl4, lmax, seed), "noise": pol_noise_draw(cov6, seed),
+            "schedule": geometric_schedule(1e4, 40, 100)}
+
+
+def pol_satellite_case(theta, phi, lmax, seed=0, model_seed=0, nobs_scale=1.0, pcut_deg=20.0, **kw):
+    """Satellite-style polarised case: the temperature recipe of `satellite_model` (its
+    spectrum, N_obs noise and |b| < 15 deg + discs mask) for T; cl_pol spectra; P noise
+    twice the T variance with Q-U correlations; P mask |b| < pcut_deg plus the same discs."""
+    t = satellite_model(theta, phi, lmax, model_seed=model_seed, nobs_scale=nobs_scale, **kw)
+    cl4 = cl_pol(t["cl"])
+    cov6, ninv6 = pol_noise_model(t["sigma2"], model_seed=model_seed)
+    mask_p = t["mask"] | galactic_cut(theta, pcut_deg)
+    return {"cl4": cl4, "cov6": cov6, "ninv6": ninv6, "mask": pol_mask_bits(t["mask"], mask_p),
+            "mask_t": t["mask"], "mask_p": mask_p, "lmax": int(lmax), "schedule": t["schedule"],
+            "signal_alm": random_alm_pol(cl4, lmax, seed), "noise": pol_noise_draw(cov6, seed)}

@@ -169,6 +169,33 @@ def test_quadrature_gap_shrinks_with_nside():
     assert gaps[2] < 1e-2
 
 
+def test_gram_defect_nside1_by_hand():
+    """Nside 1 (rings z = 2/3, 0, -2/3, four pixels each, Omega = pi/3), worked by hand:
+    at lmax 0 the monopole is exact (Omega * 12 / (4 pi) = 1); at lmax 1 the Gram matrix
+    of (Y_00, Y_10, Y_11^c, Y_11^s) is diag(1, 8/9, 19/18, 19/18): sum z^2 = 32/9 times
+    3/(4 pi) Omega gives 8/9; sum sin^2(theta) cos^2(phi) = 2 (5/9) 2 + 2 = 38/9 gives 19/18;
+    every cross term sums to zero over a ring. So ||I - G||_2 = 1/9."""
+    assert dense.gram_defect(1, 0) < 1e-15
+    G, modes = dense.gram_matrix(1, 1)
+    assert modes == [(0, 0, 0), (1, 0, 0), (1, 1, 1), (1, 1, 2)]
+    assert np.allclose(G, np.diag([1.0, 8.0 / 9.0, 19.0 / 18.0, 19.0 / 18.0]), rtol=0, atol=1e-15)
+    assert abs(dense.gram_defect(1, 1) - 1.0 / 9.0) < 1e-15
+
+
+@pytest.mark.parametrize("nside,lmax", [(1, 3), (2, 6), (4, 8), (8, 12)])
+def test_gram_trace_is_addition_theorem(nside, lmax):
+    """trace of the l-block of Omega Y^T Y = Omega npix (2l+1)/(4 pi) = 2l + 1 exactly
+    (addition theorem at every pixel), so I - G has eigenvalues of both signs."""
+    G, modes = dense.gram_matrix(nside, lmax)
+    ell = np.array([l for (l, _, _) in modes])
+    for l in range(lmax + 1):
+        assert abs(np.trace(G[np.ix_(ell == l, ell == l)]) - (2 * l + 1)) < 1e-12 * (2 * l + 1)
+    ev = np.linalg.eigvalsh(np.eye(len(modes)) - G)
+    assert abs(max(abs(ev.min()), abs(ev.max())) - dense.gram_defect(nside, lmax)) < 1e-14
+    if nside * 2 <= lmax:
+        assert ev.min() < 0 < ev.max()
+
+
 def test_chi2_monotone_at_fixed_lambda():
     """I10: chi^2_lambda(s) is non-increasing per sweep at fixed lambda up to the
     quadrature defect || I - Omega Y^T Y ||."""
