@@ -250,6 +250,30 @@ int wf_constrained_batch(wf_plan_t plan, int32_t nmaps, const void* d, const voi
                          int32_t nsweeps, void* hip_stream, wf_stats* stats);
 
 /*
+ * wf_solve_batch_static -- wf_solve_batch with every work buffer (ring coefficients,
+ * Legendre partial sums, filtered coefficients) in one static workspace per device
+ * instead of the plan's own buffers. For callers that cannot allocate (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid allocation): the
+ * call allocates no device memory and creates no stream or event. The plan (made
+ * beforehand) is only read; its device must be current.
+ *   arguments as for wf_solve_batch. The result equals wf_solve_batch's on the same
+ *   plan (same kernels; the ring launches run one after another on hip_stream).
+ *   The workspace holds 128 MiB per device, taken when the library's device code is
+ *   loaded on that device and held until the process ends: enough for one FP64 map
+ *   at nside 512 / lmax 1024 (105 MiB) or one FP32 map there (69 MiB).
+ *   Every call on a device shares the workspace and leaves its contents behind
+ *   (the call clears what must start at zero): calls that overlap on one device,
+ *   on any streams, race and give wrong results. No chi^2 history or kernel
+ *   timings are recorded (WF_FLAG_CHI2 / WF_FLAG_TIMING are ignored;
+ *   wf_chi2 afterwards reports no history).
+ * Errors: as wf_solve_batch; WF_EINVAL when the solve needs more workspace than
+ * 128 MiB (the message gives the need) or the plan's device is not current.
+ */
+int wf_solve_batch_static(wf_plan_t plan, int32_t nmaps, const void* d, void* s_wf,
+                          void* s_alm, const double* lambda, int32_t nsweeps,
+                          void* hip_stream, wf_stats* stats);
+
+/*
  * sht_map2alm -- forward transform of nmaps maps: a_lm = Omega sum_p conj(Y_lm(p)) f_p
  * (the basis change of Sect. 2 from pixels to harmonics).
  *   map  device, nmaps * npix elements; alm device, nmaps * 2 N_lm elements.

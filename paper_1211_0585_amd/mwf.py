@@ -24,6 +24,8 @@ _SIGS = [
                             _c.c_void_p, _c.c_void_p]),
     ("wf_solve_batch", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p,
                                   _c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("wf_solve_batch_static", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                         _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p]),
     ("sht_map2alm", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     ("sht_alm2map", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
     ("wf_footprint", _c.c_int, [_c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32, _c.POINTER(_c.c_size_t)]),
@@ -222,8 +224,10 @@ class Plan:
             return torch.float64, torch.complex128
         return torch.float32, torch.complex64
 
-    def solve(self, d, lambdas, s_wf=None, s_alm=None, stream=None, want_alm=True):
-        """Run the messenger iteration; d is [npix] or [nmaps, npix]. Returns (s_wf, s_alm)."""
+    def solve(self, d, lambdas, s_wf=None, s_alm=None, stream=None, want_alm=True, static=False):
+        """Run the messenger iteration; d is [npix] or [nmaps, npix]. Returns (s_wf, s_alm).
+        static=True runs wf_solve_batch_static (work buffers in the per-device static
+        workspace; pass preallocated s_wf / s_alm to allocate nothing at all)."""
         import torch
         rt, ct = self._types()
         nmaps = 1 if d.dim() == 1 else d.shape[0]
@@ -235,7 +239,8 @@ class Plan:
             s_alm = torch.empty(shape, dtype=ct, device=d.device)
         aptr = _dev_ptr(s_alm, ct, nmaps * self.nalm, "s_alm") if s_alm is not None else None
         st = wf_stats()
-        _check(lib().wf_solve_batch(self.handle, nmaps, _dev_ptr(d, rt, nmaps * self.npix, "d"),
+        fn = lib().wf_solve_batch_static if static else lib().wf_solve_batch
+        _check(fn(self.handle, nmaps, _dev_ptr(d, rt, nmaps * self.npix, "d"),
                                     _dev_ptr(s_wf, rt, nmaps * self.npix, "s_wf"), aptr,
                                     lam.ctypes.data, lam.size, _stream_handle(stream), ctypes.byref(st)))
         self.last_stats = st
