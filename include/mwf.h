@@ -433,6 +433,75 @@ int wf_server_query(wf_server_t server, wf_server_stats* out);
  */
 void wf_server_destroy(wf_server_t server);
 
+/*
+ * Polarisation (Sect. 3: temperature and polarisation maps filtered together, with
+ * separate temperature and polarisation masks). Each map is three fields T, Q, U;
+ * each alm set three fields T, E, B. Per pixel the noise is a 3x3 covariance N_p, per
+ * mode the signal covariance the 3x3 C_l of the TT, EE, BB and TE spectra (TB = EB = 0).
+ *   - Spin-weighted harmonics sY_lm (Goldberg et al. 1967), Q +/- iU = sum_lm
+ *     a_{+/-2,lm} (+/-2)Y_lm with a_{+/-2} = -(a_E +/- i a_B); the forward transform is the
+ *     pixel-area-weighted adjoint, a_{+/-2,lm} = Omega sum_p (Q +/- iU)_p conj((+/-2)Y_lm(p)).
+ *     E and B have no modes below l = 2 (those entries are 0 on output, ignored on input).
+ *   - tau = 1 / max over pixels of the largest eigenvalue of N^-1_p (the largest T = tau 1
+ *     with N - T positive semi-definite); Eq. (3) per pixel: t = s + W (d - s),
+ *     W = lambda tau N^-1 (1 + (lambda - 1) tau N^-1)^-1; Eq. (4) per mode:
+ *     s_lm = C_l (C_l + lambda tau Omega 1)^-1 a_lm.
+ *   - Layouts: maps [map][field][npix] (T, Q, U; RING order), alm [map][field][N_lm]
+ *     (T, E, B; packed as above), doubles (WF_F64 only); nside <= 512.
+ */
+typedef struct wf_pol_plan_s* wf_pol_plan_t;
+
+/*
+ * wf_pol_plan -- tables and work buffers of one polarised problem.
+ *   nside    power of two in [1, 512]; lmax in [0, 4 nside - 1]
+ *   cl       host, 4 (lmax+1) doubles: TT, EE, BB, TE spectra, one after another; every
+ *            block [[TT, TE], [TE, EE]] positive semi-definite, BB >= 0, and EE = BB =
+ *            TE = 0 at l < 2
+ *   ninv     host, 6 npix doubles: the TT, QQ, UU, TQ, TU, QU entries of N^-1_p, one
+ *            array of npix after another; every N^-1_p positive semi-definite
+ *   mask     host, npix bytes: bit 0 set where T is observed, bit 1 where Q and U are
+ *            (an unobserved field has its rows and columns of N^-1 set to 0); NULL =
+ *            all observed
+ *   opts     NULL, or dtype WF_F64, max_batch, flags 0 or WF_FLAG_TIMING
+ * Errors: WF_EINVAL (shape, non-finite or indefinite input, no observed pixel),
+ * WF_EUNSUPPORTED (another dtype), WF_ENOMEM, WF_EDEVICE. The plan copies its inputs.
+ */
+int wf_pol_plan(wf_pol_plan_t* out, int32_t nside, int32_t lmax, const double* cl,
+                const double* ninv, const uint8_t* mask, const wf_plan_opts* opts,
+                void* hip_stream);
+
+/*
+ * wf_pol_solve_batch -- the messenger iteration of nmaps polarised maps sharing the
+ * plan's spectra, noise and masks, from s = t = 0, one sweep per lambda.
+ *   d, s_wf  device, nmaps * 3 * npix doubles; s_alm device, nmaps * 3 * 2 N_lm doubles
+ *            or NULL; lambda host, nsweeps entries, finite and > 0
+ * WF_FLAG_TIMING fills stats->ms_ring (ring phase), ms_analysis (spin-0 T and spin-2
+ * E/B analysis) and ms_synthesis (filter and both syntheses), and waits.
+ * Errors: WF_EINVAL (NULL buffers, bad schedule, nmaps outside [1, max_batch]), WF_EDEVICE.
+ */
+int wf_pol_solve_batch(wf_pol_plan_t plan, int32_t nmaps, const void* d, void* s_wf,
+                       void* s_alm, const double* lambda, int32_t nsweeps,
+                       void* hip_stream, wf_stats* stats);
+
+/* sht_pol_map2alm -- [T, Q, U] maps -> [T, E, B] alm of nmaps maps (device buffers as above). */
+int sht_pol_map2alm(wf_pol_plan_t plan, int32_t nmaps, const void* map, void* alm,
+                    void* hip_stream);
+
+/* sht_pol_alm2map -- [T, E, B] alm -> [T, Q, U] maps (imaginary parts at m = 0 ignored). */
+int sht_pol_alm2map(wf_pol_plan_t plan, int32_t nmaps, const void* alm, void* map,
+                    void* hip_stream);
+
+/* wf_pol_plan_info -- npix, N_lm, tau and the active (l, m, ring pair) triples of one
+ * transform of one field (any pointer may be NULL). */
+int wf_pol_plan_info(wf_pol_plan_t plan, int64_t* npix, int64_t* nalm, double* tau,
+                     int64_t* units_active);
+
+/* wf_pol_sync -- wait for the plan's stream work; reports asynchronous device errors. */
+int wf_pol_sync(wf_pol_plan_t plan);
+
+/* wf_pol_destroy -- free a polarised plan (NULL is accepted). */
+void wf_pol_destroy(wf_pol_plan_t plan);
+
 /* wf_sync -- wait for the plan's stream work; reports asynchronous device errors. */
 int wf_sync(wf_plan_t plan);
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmwf.so")
 
-SOURCES = ["api.cpp", "geometry.cpp", "server.cpp", "phase_a.hip", "phase_a_mfma.hip", "phase_b.hip", "band.hip", "cr.hip", "static_solve.hip"]
+SOURCES = ["api.cpp", "geometry.cpp", "server.cpp", "phase_a.hip", "phase_a_mfma.hip", "phase_b.hip", "band.hip", "cr.hip", "static_solve.hip", "pol.hip", "pol_api.cpp"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

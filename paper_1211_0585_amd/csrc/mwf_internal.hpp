@@ -63,6 +63,35 @@ constexpr int FP64_SCALED_COST_SYN = 6;
 constexpr int FP64_ITEM_COST_L = 32;
 constexpr uint16_t WAKE_NEVER = 0xffff;
 
+// lambda_mm(z) = norm_m sin^m(theta) as v * 2^(-512 s) with |v| >= 2^-449 when s = 0.
+__device__ __forceinline__ void sectoral_seed(int m, double sin_t, double norm, double* v, int* s) {
+  int eb;
+  double b = frexp(sin_t, &eb);
+  double r = 1.0;
+  int er = 0;
+  int k = m;
+  while (k) {
+    if (k & 1) {
+      int t;
+      r = frexp(r * b, &t);
+      er += eb + t;
+    }
+    k >>= 1;
+    if (k) {
+      int t;
+      b = frexp(b * b, &t);
+      eb = 2 * eb + t;
+    }
+  }
+  int t;
+  double x = frexp(norm * r, &t);
+  const int e = er + t;                 // value = x * 2^e, 0.5 <= |x| < 1
+  int sc = 0;
+  if (e < 64 - SCALE_BITS) sc = (64 - SCALE_BITS - e + SCALE_BITS - 1) / SCALE_BITS;
+  *v = ldexp(x, e + SCALE_BITS * sc);
+  *s = sc;
+}
+
 // Work item of the m-parallel phase: one m and one block of ring pairs.
 struct WorkItem {
   int32_t m;
@@ -376,6 +405,66 @@ hipError_t launch_group_synthesis(const GroupLaunch& g, int mode, int nct, int a
 // Ring phase over (task, ring pair, map) blocks, float storage and arithmetic.
 // Ring launch of class cls over TaskDev::ring_q[cls]; fft_len: the longest transform of the class.
 hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, int fft_len, hipStream_t s);
+
+// ---------------------------------------------------------------- polarisation (T, Q, U)
+// A polarised problem runs three fields per map. Ring coefficients are stored field
+// by field, [field][map][pair][m][4] with field_maps maps per field block (the plan's
+// max_batch), so the T block is an ordinary spin-0 buffer; maps and d are
+// [map][field][npix]; tau N^-1 is [6][npix] (TT, QQ, UU, TQ, TU, QU).
+struct PolRingArgs {
+  int32_t mode;          // PhaseBMode bits (PB_SYNTH, PB_UPDATE, PB_ANALYSIS, PB_WRITE_MAP, PB_READ_MAP)
+  int32_t nmaps;
+  int32_t field_maps;    // maps per field block of F and G
+  int32_t pad_;
+  double lambda;
+  const double* F;
+  double* G;
+  const double* d;
+  const double* map_in;
+  double* map_out;
+  const double* q6;
+};
+// The ring launch classes 0 and 1 of a polarised plan (512 threads).
+hipError_t launch_pol_ring(const PlanDev& P, const PolRingArgs& a, const RingClass* cls, hipStream_t s);
+
+// Spin-2 Legendre tables and work of a polarised plan (FP64). The functions
+// u = s_lambda / K obey u_l = (A_l z + B_l s/2) u_{l-1} - u_{l-2} for s = +2 and -2
+// (rows per m in the padded layout of the spin-0 tables; A = B = 0 at l <= l0 =
+// max(m, 2), K = 0 below l0).
+struct Spin2Dev {
+  const double* A;       // [rows_total]
+  const double* B;
+  const double* K;
+  const double* norm;    // [lmax+1] sqrt(m (m-1) / ((m+1)(m+2))) for m >= 2; m = 0, 1: sqrt(15/(32 pi)), sqrt(5/pi)
+  const WorkItem* items; // (m, block of 64 ring pairs), longest first
+  int32_t nitems;
+  int32_t field_maps;    // maps per field block of F and G
+};
+
+// Polarised coefficient step: sums the T partials (spin-0 layout) and the E/B partials
+// ([map][blk][nalm][4]: E re, E im, B re, B im), applies the TE-coupled 3x3 filter of
+// Eq. (4) (SY_FROM_PARTIAL), or passes the transform (SY_ALM_ONLY) or the caller's alm
+// (SY_FROM_ALM) through; writes alm_out [map][3][nalm] and the synthesis coefficients.
+struct PolCoeffArgs {
+  int32_t mode;
+  int32_t nmaps;
+  double lambda;
+  const double2* partial_t;   // [map][nblk_max][nalm]
+  const double* partial_eb;   // [map][nblk2][nalm][4]
+  int32_t nblk2;              // blocks of 64 ring pairs (partials per (l, m) of E/B)
+  int32_t pad_;
+  const int32_t* nblk2_m;     // [lmax+1] E/B blocks written for m
+  const double2* alm_in;      // [map][3][nalm]
+  double2* alm_out;           // [map][3][nalm] or null
+  double2* bcoef_t;           // [map][rows_total]: C_l s_T (spin-0 synthesis input)
+  double2* bcoef_eb;          // [map][rows_total][2]: -K s_E / 2, -K s_B / 2
+  const double* cl4;          // [4][lmax+1] TT, EE, BB, TE
+};
+hipError_t launch_pol_coeff(const PlanDev& P, const Spin2Dev& S2, const PolCoeffArgs& a, hipStream_t s);
+hipError_t launch_spin2_analysis(const PlanDev& P, const Spin2Dev& S2, int nmaps, const double* G, double* partial_eb,
+                                 int nblk2, hipStream_t s);
+hipError_t launch_spin2_synthesis(const PlanDev& P, const Spin2Dev& S2, int nmaps, const double2* bcoef_eb, double* F,
+                                  hipStream_t s);
 
 // Plan-time, per (m, ring pair): where lambda_lm leaves the scaled range, or WAKE_NEVER
 // (polar skip and the cost of the FP64 work items).

@@ -40,35 +40,6 @@ namespace {
 constexpr double BIG_THRESH = 0x1p64;
 constexpr double RESCALE = 0x1p-512;
 
-// lambda_mm(z) = norm_m sin^m(theta) as v * 2^(-512 s) with |v| >= 2^-449 when s = 0.
-__device__ __forceinline__ void sectoral_seed(int m, double sin_t, double norm, double* v, int* s) {
-  int eb;
-  double b = frexp(sin_t, &eb);
-  double r = 1.0;
-  int er = 0;
-  int k = m;
-  while (k) {
-    if (k & 1) {
-      int t;
-      r = frexp(r * b, &t);
-      er += eb + t;
-    }
-    k >>= 1;
-    if (k) {
-      int t;
-      b = frexp(b * b, &t);
-      eb = 2 * eb + t;
-    }
-  }
-  int t;
-  double x = frexp(norm * r, &t);
-  const int e = er + t;                 // value = x * 2^e, 0.5 <= |x| < 1
-  int sc = 0;
-  if (e < 64 - SCALE_BITS) sc = (64 - SCALE_BITS - e + SCALE_BITS - 1) / SCALE_BITS;
-  *v = ldexp(x, e + SCALE_BITS * sc);
-  *s = sc;
-}
-
 __device__ __forceinline__ int wave_any(int pred) { return __any(pred); }
 
 // a + b over lanes l and l + 32 with the halves exchanged (v_permlane32_swap): lanes

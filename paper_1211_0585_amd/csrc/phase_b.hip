@@ -376,10 +376,173 @@ struct Vec4<float> {
   using type = float4;
 };
 
+// Synthesis loading step of one ring pair: the bins B[k] = sum over m = k (mod n) of
+// F(m) exp(i m phi0) (F(-m) = conj F(m)) of the north and south rings, from the E/O
+// coefficients Fp[m][4] of this map and pair, into buf as B_N + i B_S (k < n). Short
+// rings use lds_raw for partial sums (consumed before the function returns). Every
+// thread of the workgroup calls it.
+template <class T, class C, int NT>
+__device__ __forceinline__ void fold_synthesis(const PlanDev& P, const T* __restrict__ Fp, const RingPair& rp,
+                                               typename CT<C>::V* buf, unsigned char* lds_raw) {
+  using V4 = typename Vec4<T>::type;
+  using V = typename CT<C>::V;
+  const int n = rp.nphi;
+  const int lmax = P.lmax;
+  const int tid = threadIdx.x;
+  const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
+  // exp(i k phi0) for k = tid + s * NT, advanced by one complex multiply
+  double2 ph = expipi<double>((int64_t)tid * rp.ph_num, n);
+  const double2 step = expipi<double>((int64_t)NT * rp.ph_num, n);
+  if (n > FOLD_PARTS) {
+    // the first positive and negative alias of the next bin are loaded while the
+    // current bin is folded (one bin ahead)
+    V4 pos_nx{}, neg_nx{};
+    {
+      const int k = tid, mn = (k == 0) ? n : n - k;
+      if (k < n && k <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k * 4);
+      if (k < n && mn <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn * 4);
+    }
+    for (int k = tid; k < n; k += NT) {
+      const V4 pos0 = pos_nx, neg0 = neg_nx;
+      {
+        const int k1 = k + NT, mn1 = n - k1;
+        if (k1 < n && k1 <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k1 * 4);
+        if (k1 < n && mn1 <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn1 * 4);
+      }
+      double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+      double s = 1.0;                               // sig^t for m = k + t n
+      for (int m = k; m <= lmax; m += n) {          // m >= 0 with m = k (mod n)
+        const V4 eo = (m == k) ? pos0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+        double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
+        double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
+        if (m == 0) {
+          fn.y = 0.0;
+          fs.y = 0.0;
+        } else {
+          const double2 phm = make_double2(s * ph.x, s * ph.y);
+          fn = cmul(fn, phm);
+          fs = cmul(fs, phm);
+        }
+        bn = cadd(bn, fn);
+        bs = cadd(bs, fs);
+        s *= sig;
+      }
+      // m < 0 terms: |m| = t n - k (t >= 1), exp(i |m| phi0) = sig^t conj(exp(i k phi0))
+      s = sig;
+      const int mn = (k == 0) ? n : n - k;
+      for (int m = mn; m <= lmax; m += n) {
+        const V4 eo = (m == mn) ? neg0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+        const double2 phm = make_double2(s * ph.x, -s * ph.y);
+        const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
+        const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
+        bn = cadd(bn, cconj(fn));
+        bs = cadd(bs, cconj(fs));
+        s *= sig;
+      }
+      buf[k] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
+      ph = cmul(ph, step);
+    }
+  } else {
+    // short rings carry many aliases per bin: G partial sums per bin, each over
+    // every G-th alias, spread over the whole workgroup, then added in a fixed order
+    const int G = FOLD_PARTS / n, np = G * n;
+    const double sigG = (G & 1) ? sig : 1.0;
+    double2* part = reinterpret_cast<double2*>(lds_raw);    // [np][N, S]
+    for (int p = tid; p < np; p += NT) {
+      const int k = p % n, g = p / n;
+      const double2 phk = expipi<double>((int64_t)k * rp.ph_num, n);   // exp(i k phi0)
+      double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+      double s = (g & 1) ? sig : 1.0;               // sig^t, t = g + u G
+      for (int m = k + g * n; m <= lmax; m += G * n) {
+        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+        double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
+        double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
+        if (m == 0) {
+          fn.y = 0.0;
+          fs.y = 0.0;
+        } else {
+          const double2 phm = make_double2(s * phk.x, s * phk.y);
+          fn = cmul(fn, phm);
+          fs = cmul(fs, phm);
+        }
+        bn = cadd(bn, fn);
+        bs = cadd(bs, fs);
+        s *= sigG;
+      }
+      s = ((g + 1) & 1) ? sig : 1.0;               // negative aliases |m| = t n - k, t = 1 + g + u G
+      for (int m = (g + 1) * n - k; m <= lmax; m += G * n) {
+        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
+        const double2 phm = make_double2(s * phk.x, -s * phk.y);
+        const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
+        const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
+        bn = cadd(bn, cconj(fn));
+        bs = cadd(bs, cconj(fs));
+        s *= sigG;
+      }
+      part[2 * p] = bn;
+      part[2 * p + 1] = bs;
+    }
+    __syncthreads();
+    constexpr int KB = (FOLD_PARTS + NT - 1) / NT;   // bins per thread
+    V bk[KB];
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const int k = tid + b * NT;
+      if (k < n) {
+        double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+        for (int g = 0; g < G; ++g) {
+          bn = cadd(bn, part[2 * (g * n + k)]);
+          bs = cadd(bs, part[2 * (g * n + k) + 1]);
+        }
+        bk[b] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const int k = tid + b * NT;
+      if (k < n) buf[k] = bk[b];
+    }
+  }
+}
+
+// Analysis unfolding step of one ring pair, after the forward DFT of x_N + i x_S in
+// buf: G(m) = Omega exp(-i m phi0) X[m mod n] of each ring (Hermitian unfold), written
+// as S = G_N + G_S and D = G_N - G_S to Gp[m][4], m = 0..lmax.
+template <class T, class C, int NT>
+__device__ __forceinline__ void unfold_analysis(const PlanDev& P, T* __restrict__ Gp, const RingPair& rp,
+                                                const typename CT<C>::V* buf) {
+  using V4 = typename Vec4<T>::type;
+  using V = typename CT<C>::V;
+  const int n = rp.nphi;
+  const int lmax = P.lmax;
+  const int tid = threadIdx.x;
+  const double half_omega = 0.5 * P.omega;
+  double2 ph = expipi<double>(-(int64_t)tid * rp.ph_num, n);          // exp(-i m phi0)
+  const double2 step = expipi<double>(-(int64_t)NT * rp.ph_num, n);
+  for (int m = tid; m <= lmax; m += NT) {
+    const int k = m % n;
+    const int nk = (k == 0) ? 0 : n - k;
+    const V zkv = buf[k], znkv = buf[nk];
+    const double2 zk = make_double2((double)zkv.x, (double)zkv.y);
+    const double2 znk = make_double2((double)znkv.x, (double)znkv.y);
+    // X_N = (Z_k + conj Z_nk) / 2, X_S = (Z_k - conj Z_nk) / (2 i); Omega folded in
+    const double2 xn = make_double2((zk.x + znk.x) * half_omega, (zk.y - znk.y) * half_omega);
+    const double2 xs = make_double2((zk.y + znk.y) * half_omega, -(zk.x - znk.x) * half_omega);
+    const double2 gn = cmul(xn, ph), gs = cmul(xs, ph);
+    V4 o;
+    o.x = (T)(gn.x + gs.x);
+    o.y = (T)(gn.y + gs.y);
+    o.z = (T)(gn.x - gs.x);
+    o.w = (T)(gn.y - gs.y);
+    *reinterpret_cast<V4*>(Gp + (size_t)m * 4) = o;
+    ph = cmul(ph, step);
+  }
+}
+
 template <class T, class C, int NT, int MAXB, int KIND>
 __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs& a, const int q,
                                              const int map, const int buf_elems) {
-  using V4 = typename Vec4<T>::type;
   using V = typename CT<C>::V;
   extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
   V* buf = reinterpret_cast<V*>(lds_raw);
@@ -393,7 +556,6 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   const int64_t mbase = (int64_t)map * P.npix;
   const int mode = a.slots ? a.slots[map].pb_mode : a.mode;
   if (mode == 0) return;                          // idle slot (uniform over the block)
-  const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
   const T* __restrict__ q_tab = static_cast<const T*>(P.q) + (a.slots ? map * a.q_stride : 0);
 
   // per-pass twiddles of this ring's transform length: loaded now, written to LDS
@@ -422,121 +584,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
 
   // ---- ring values into buf (x = north + i south)
   if (mode & PB_SYNTH) {
-    const T* __restrict__ Fp = static_cast<const T*>(a.F) + pbase;
-    // exp(i k phi0) for k = tid + s * NT, advanced by one complex multiply
-    double2 ph = expipi<double>((int64_t)tid * rp.ph_num, n);
-    const double2 step = expipi<double>((int64_t)NT * rp.ph_num, n);
-    if (n > FOLD_PARTS) {
-      // the first positive and negative alias of the next bin are loaded while the
-      // current bin is folded (one bin ahead)
-      V4 pos_nx{}, neg_nx{};
-      {
-        const int k = tid, mn = (k == 0) ? n : n - k;
-        if (k < n && k <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k * 4);
-        if (k < n && mn <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn * 4);
-      }
-      for (int k = tid; k < n; k += NT) {
-        const V4 pos0 = pos_nx, neg0 = neg_nx;
-        {
-          const int k1 = k + NT, mn1 = n - k1;
-          if (k1 < n && k1 <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k1 * 4);
-          if (k1 < n && mn1 <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn1 * 4);
-        }
-        double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
-        double s = 1.0;                               // sig^t for m = k + t n
-        for (int m = k; m <= lmax; m += n) {          // m >= 0 with m = k (mod n)
-          const V4 eo = (m == k) ? pos0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-          double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
-          double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
-          if (m == 0) {
-            fn.y = 0.0;
-            fs.y = 0.0;
-          } else {
-            const double2 phm = make_double2(s * ph.x, s * ph.y);
-            fn = cmul(fn, phm);
-            fs = cmul(fs, phm);
-          }
-          bn = cadd(bn, fn);
-          bs = cadd(bs, fs);
-          s *= sig;
-        }
-        // m < 0 terms: |m| = t n - k (t >= 1), exp(i |m| phi0) = sig^t conj(exp(i k phi0))
-        s = sig;
-        const int mn = (k == 0) ? n : n - k;
-        for (int m = mn; m <= lmax; m += n) {
-          const V4 eo = (m == mn) ? neg0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-          const double2 phm = make_double2(s * ph.x, -s * ph.y);
-          const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
-          const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
-          bn = cadd(bn, cconj(fn));
-          bs = cadd(bs, cconj(fs));
-          s *= sig;
-        }
-        buf[k] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
-        ph = cmul(ph, step);
-      }
-    } else {
-      // short rings carry many aliases per bin: G partial sums per bin, each over
-      // every G-th alias, spread over the whole workgroup, then added in a fixed order
-      const int G = FOLD_PARTS / n, np = G * n;
-      const double sigG = (G & 1) ? sig : 1.0;
-      double2* part = reinterpret_cast<double2*>(lds_raw);    // [np][N, S]
-      for (int p = tid; p < np; p += NT) {
-        const int k = p % n, g = p / n;
-        const double2 phk = expipi<double>((int64_t)k * rp.ph_num, n);   // exp(i k phi0)
-        double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
-        double s = (g & 1) ? sig : 1.0;               // sig^t, t = g + u G
-        for (int m = k + g * n; m <= lmax; m += G * n) {
-          const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-          double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
-          double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
-          if (m == 0) {
-            fn.y = 0.0;
-            fs.y = 0.0;
-          } else {
-            const double2 phm = make_double2(s * phk.x, s * phk.y);
-            fn = cmul(fn, phm);
-            fs = cmul(fs, phm);
-          }
-          bn = cadd(bn, fn);
-          bs = cadd(bs, fs);
-          s *= sigG;
-        }
-        s = ((g + 1) & 1) ? sig : 1.0;               // negative aliases |m| = t n - k, t = 1 + g + u G
-        for (int m = (g + 1) * n - k; m <= lmax; m += G * n) {
-          const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-          const double2 phm = make_double2(s * phk.x, -s * phk.y);
-          const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
-          const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
-          bn = cadd(bn, cconj(fn));
-          bs = cadd(bs, cconj(fs));
-          s *= sigG;
-        }
-        part[2 * p] = bn;
-        part[2 * p + 1] = bs;
-      }
-      __syncthreads();
-      constexpr int KB = (FOLD_PARTS + NT - 1) / NT;   // bins per thread
-      V bk[KB];
-#pragma unroll
-      for (int b = 0; b < KB; ++b) {
-        const int k = tid + b * NT;
-        if (k < n) {
-          double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
-          for (int g = 0; g < G; ++g) {
-            bn = cadd(bn, part[2 * (g * n + k)]);
-            bs = cadd(bs, part[2 * (g * n + k) + 1]);
-          }
-          bk[b] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < KB; ++b) {
-        const int k = tid + b * NT;
-        if (k < n) buf[k] = bk[b];
-      }
-    }
+    fold_synthesis<T, C, NT>(P, static_cast<const T*>(a.F) + pbase, rp, buf, lds_raw);
     stage_twiddles();
     __syncthreads();
     ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, +1, P);
@@ -614,29 +662,149 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   // ---- analysis: forward DFT and unfold into S/D per m
   if (mode & PB_ANALYSIS) {
     ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, -1, P);
-    T* Gp = static_cast<T*>(a.G) + pbase;
-    const double half_omega = 0.5 * P.omega;
-    double2 ph = expipi<double>(-(int64_t)tid * rp.ph_num, n);          // exp(-i m phi0)
-    const double2 step = expipi<double>(-(int64_t)NT * rp.ph_num, n);
-    for (int m = tid; m <= lmax; m += NT) {
-      const int k = m % n;
-      const int nk = (k == 0) ? 0 : n - k;
-      const V zkv = buf[k], znkv = buf[nk];
-      const double2 zk = make_double2((double)zkv.x, (double)zkv.y);
-      const double2 znk = make_double2((double)znkv.x, (double)znkv.y);
-      // X_N = (Z_k + conj Z_nk) / 2, X_S = (Z_k - conj Z_nk) / (2 i); Omega folded in
-      const double2 xn = make_double2((zk.x + znk.x) * half_omega, (zk.y - znk.y) * half_omega);
-      const double2 xs = make_double2((zk.y + znk.y) * half_omega, -(zk.x - znk.x) * half_omega);
-      const double2 gn = cmul(xn, ph), gs = cmul(xs, ph);
-      V4 o;
-      o.x = (T)(gn.x + gs.x);
-      o.y = (T)(gn.y + gs.y);
-      o.z = (T)(gn.x - gs.x);
-      o.w = (T)(gn.y - gs.y);
-      *reinterpret_cast<V4*>(Gp + (size_t)m * 4) = o;
-      ph = cmul(ph, step);
+    unfold_analysis<T, C, NT>(P, static_cast<T*>(a.G) + pbase, rp, buf);
+  }
+}
+
+// Eq. (3) for the polarised fields at one pixel: t = s + lambda (1 + (lambda - 1) M)^-1 M (d - s)
+// with M = tau N^-1 (q: TT, QQ, UU, TQ, TU, QU). 1 + (lambda - 1) M is symmetric with
+// eigenvalues 1 + (lambda - 1) mu, mu in [0, 1] (tau bounds every eigenvalue of N^-1),
+// so it is inverted through its adjugate; at lambda = 1 it is the identity.
+__device__ __forceinline__ void pol_update(double& s0, double& s1, double& s2, double d0, double d1, double d2,
+                                           const double* q, double lam) {
+  const double r0 = d0 - s0, r1 = d1 - s1, r2 = d2 - s2;
+  const double v0 = q[0] * r0 + q[3] * r1 + q[4] * r2;
+  const double v1 = q[3] * r0 + q[1] * r1 + q[5] * r2;
+  const double v2 = q[4] * r0 + q[5] * r1 + q[2] * r2;
+  const double c = lam - 1.0;
+  const double a00 = 1.0 + c * q[0], a11 = 1.0 + c * q[1], a22 = 1.0 + c * q[2];
+  const double a01 = c * q[3], a02 = c * q[4], a12 = c * q[5];
+  const double i00 = a11 * a22 - a12 * a12, i01 = a02 * a12 - a01 * a22, i02 = a01 * a12 - a02 * a11;
+  const double i11 = a00 * a22 - a02 * a02, i12 = a01 * a02 - a00 * a12, i22 = a00 * a11 - a01 * a01;
+  const double f = lam / (a00 * i00 + a01 * i01 + a02 * i02);
+  s0 += f * (i00 * v0 + i01 * v1 + i02 * v2);
+  s1 += f * (i01 * v0 + i11 * v1 + i12 * v2);
+  s2 += f * (i02 * v0 + i12 * v1 + i22 * v2);
+}
+
+// Polarised ring phase of one (ring pair, map): the three fields T, Q, U of the map,
+// each a real field packed north + i south as in phase_b_body. The fields pass one
+// after another through the one LDS buffer: the synthesised values of the pixels a
+// thread updates are kept in its registers (at most PPT per field: n <= PPT NT), the
+// 3x3 update couples them, and the forward transforms follow field by field.
+template <class C, int NT, int MAXB, int KIND>
+__device__ __forceinline__ void phase_b_pol_body(const PlanDev& P, const PolRingArgs& a, const int q, const int map,
+                                                 const int buf_elems) {
+  using V = typename CT<C>::V;
+  constexpr int PPT = (KIND == 0 ? 4 : 2) * MAXB;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  V* buf = reinterpret_cast<V*>(lds_raw);
+  const RingPair rp = P.pairs[q];
+  const int n = rp.nphi;
+  const int lmax = P.lmax;
+  const bool equator = rp.start_s < 0;
+  const int tid = threadIdx.x;
+  const int mode = a.mode;
+  const size_t pstride = (size_t)(lmax + 1) * 4;
+  auto pbase = [&](int f) { return (((size_t)f * a.field_maps + map) * P.npairs + q) * pstride; };
+  const int64_t mbase = (int64_t)map * 3 * P.npix;
+
+  V* twl = buf + fft_padded(buf_elems);
+  const int tw_lg = rp.log2n >= 0 ? rp.log2n : __ffs(rp.bl_M) - 1;
+  const int tw_n = fft_twiddle_entries(tw_lg);
+  const V* __restrict__ twg = Tabs<C>::tw(P);
+  auto stage_twiddles = [&]() {
+    for (int e = tid; e < tw_n; e += NT) twl[e] = twg[twiddle_glob_index(tw_lg, e, P.tw_len)];
+  };
+
+  V sx[3][PPT];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    if (mode & PB_SYNTH) {
+      fold_synthesis<double, C, NT>(P, a.F + pbase(f), rp, buf, lds_raw);
+      stage_twiddles();
+      __syncthreads();
+      ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, +1, P);
+    } else if (mode & PB_READ_MAP) {
+      const double* src = a.map_in + mbase + (int64_t)f * P.npix;
+      for (int j = tid; j < n; j += NT)
+        buf[j] = CT<C>::make((C)src[rp.start_n + j], equator ? (C)0 : (C)src[rp.start_s + j]);
+      if (f == 0) stage_twiddles();
+      __syncthreads();
+    } else {
+      for (int j = tid; j < n; j += NT) buf[j] = CT<C>::make(0, 0);
+      if (f == 0) stage_twiddles();
+      __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int j = tid + u * NT;
+      sx[f][u] = j < n ? buf[j] : CT<C>::make(0, 0);
+    }
+    __syncthreads();
+  }
+
+  if (mode & (PB_WRITE_MAP | PB_UPDATE)) {
+    const double lam = a.lambda;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+      const int j = tid + u * NT;
+      if (j >= n) continue;
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        if (side == 1 && equator) continue;
+        const int64_t pix = (side == 0 ? rp.start_n : rp.start_s) + j;
+        double s0 = side == 0 ? (double)sx[0][u].x : (double)sx[0][u].y;
+        double s1 = side == 0 ? (double)sx[1][u].x : (double)sx[1][u].y;
+        double s2 = side == 0 ? (double)sx[2][u].x : (double)sx[2][u].y;
+        if (mode & PB_WRITE_MAP) {
+          a.map_out[mbase + pix] = s0;
+          a.map_out[mbase + P.npix + pix] = s1;
+          a.map_out[mbase + 2 * P.npix + pix] = s2;
+        }
+        if (mode & PB_UPDATE) {
+          double qv[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) qv[c] = a.q6[(int64_t)c * P.npix + pix];
+          const double* dd = a.d + mbase;
+          pol_update(s0, s1, s2, dd[pix], dd[P.npix + pix], dd[2 * P.npix + pix], qv, lam);
+          if (side == 0) {
+            sx[0][u].x = (C)s0;
+            sx[1][u].x = (C)s1;
+            sx[2][u].x = (C)s2;
+          } else {
+            sx[0][u].y = (C)s0;
+            sx[1][u].y = (C)s1;
+            sx[2][u].y = (C)s2;
+          }
+        }
+      }
+      if (equator) {
+        sx[0][u].y = sx[1][u].y = sx[2][u].y = (C)0;
+      }
     }
   }
+
+  if (mode & PB_ANALYSIS) {
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+#pragma unroll
+      for (int u = 0; u < PPT; ++u) {
+        const int j = tid + u * NT;
+        if (j < n) buf[j] = sx[f][u];
+      }
+      __syncthreads();
+      ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, -1, P);
+      unfold_analysis<double, C, NT>(P, a.G + pbase(f), rp, buf);
+      __syncthreads();
+    }
+  }
+}
+
+template <int NT, int MAXB, int CLS>
+__global__ void __launch_bounds__(NT) phase_b_pol_kernel(PlanDev P, PolRingArgs a, const int32_t* __restrict__ qlist,
+                                                          int buf_elems) {
+  phase_b_pol_body<double, NT, MAXB, class_kind(CLS)>(P, a, qlist[blockIdx.x], blockIdx.y, buf_elems);
 }
 
 template <class T, class C, int NT, int MAXB, int CLS>
@@ -735,6 +903,27 @@ hipError_t group_class(const GroupLaunch& g, int fft_len, hipStream_t s) {
   }
 }
 
+template <int NT, int MAXB, int CLS>
+hipError_t launch_pol_class_b(const PlanDev& P, const PolRingArgs& a, const RingClass& rc, hipStream_t s) {
+  static size_t attr = 0;
+  const size_t lds = ring_lds_bytes(rc.fft_len, sizeof(double2));
+  if (hipError_t e = set_lds(phase_b_pol_kernel<NT, MAXB, CLS>, lds, &attr)) return e;
+  hipLaunchKernelGGL((phase_b_pol_kernel<NT, MAXB, CLS>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q,
+                     rc.fft_len);
+  return hipGetLastError();
+}
+
+template <int CLS>
+hipError_t launch_pol_class(const PlanDev& P, const PolRingArgs& a, const RingClass& rc, hipStream_t s) {
+  if (rc.count == 0) return hipSuccess;
+  switch (maxb_for(rc.fft_len, 512)) {
+    case 1: return launch_pol_class_b<512, 1, CLS>(P, a, rc, s);
+    case 2: return launch_pol_class_b<512, 2, CLS>(P, a, rc, s);
+    case 4: return launch_pol_class_b<512, 4, CLS>(P, a, rc, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, int fft_len, hipStream_t s) {
@@ -757,6 +946,12 @@ hipError_t launch_phase_b_class(const PlanDev& P, const PhaseBArgs& a, const Rin
     case 1: return fp32 ? launch_class<float, float, 1>(P, a, rc, s) : launch_class<double, double, 1>(P, a, rc, s);
     default: return fp32 ? launch_class<float, float, 2>(P, a, rc, s) : launch_class<double, double, 2>(P, a, rc, s);
   }
+}
+
+hipError_t launch_pol_ring(const PlanDev& P, const PolRingArgs& a, const RingClass* cls, hipStream_t s) {
+  hipError_t e = launch_pol_class<0>(P, a, cls[0], s);
+  if (e == hipSuccess) e = launch_pol_class<1>(P, a, cls[1], s);
+  return e;
 }
 
 }  // namespace mwf

@@ -57,6 +57,16 @@ _SIGS = [
     ("wf_solve_adaptive", _c.c_int, [_c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.c_int32,
                                      _c.c_void_p, _c.c_void_p, _c.c_void_p, _c.POINTER(_c.c_int32),
                                      _c.POINTER(_c.c_int32), _c.c_void_p, _c.c_void_p]),
+    ("wf_pol_plan", _c.c_int, [_c.POINTER(_c.c_void_p), _c.c_int32, _c.c_int32, _c.c_void_p, _c.c_void_p,
+                               _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    ("wf_pol_solve_batch", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p,
+                                      _c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p]),
+    ("sht_pol_map2alm", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    ("sht_pol_alm2map", _c.c_int, [_c.c_void_p, _c.c_int32, _c.c_void_p, _c.c_void_p, _c.c_void_p]),
+    ("wf_pol_plan_info", _c.c_int, [_c.c_void_p, _c.POINTER(_c.c_int64), _c.POINTER(_c.c_int64),
+                                    _c.POINTER(_c.c_double), _c.POINTER(_c.c_int64)]),
+    ("wf_pol_sync", _c.c_int, [_c.c_void_p]),
+    ("wf_pol_destroy", None, [_c.c_void_p]),
     ("wf_sync", _c.c_int, [_c.c_void_p]),
     ("wf_destroy", None, [_c.c_void_p]),
     ("wf_strerror", _c.c_char_p, [_c.c_int]),
@@ -356,6 +366,104 @@ class Plan:
     def close(self):
         if self._h is not None:
             lib().wf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class PolPlan:
+    """A polarised (T, Q, U) problem: spectra cl4 [4, lmax+1] (TT, EE, BB, TE), noise
+    precision ninv6 [6, npix] (TT, QQ, UU, TQ, TU, QU), mask bytes (bit 0 T observed,
+    bit 1 Q/U observed). Maps are [nmaps, 3, npix], alm [nmaps, 3, N_lm] (FP64)."""
+
+    def __init__(self, nside, lmax, cl4, ninv6, mask=None, max_batch=1, stream=None, flags=0):
+        L = lib()
+        cl4 = np.ascontiguousarray(cl4, dtype=np.float64)
+        ninv6 = np.ascontiguousarray(ninv6, dtype=np.float64)
+        npix = 12 * nside * nside
+        if cl4.shape != (4, lmax + 1):
+            raise ValueError("cl4 must have shape (4, lmax+1)")
+        if ninv6.shape != (6, npix):
+            raise ValueError("ninv6 must have shape (6, npix)")
+        mptr = None
+        if mask is not None:
+            mask = np.ascontiguousarray(np.asarray(mask).astype(np.uint8))
+            if mask.size != npix:
+                raise ValueError("mask must have npix entries")
+            mptr = mask.ctypes.data
+        opts = wf_plan_opts(WF_F64, max_batch, flags, None)
+        h = ctypes.c_void_p()
+        _check(L.wf_pol_plan(ctypes.byref(h), nside, lmax, cl4.ctypes.data, ninv6.ctypes.data, mptr,
+                             ctypes.byref(opts), _stream_handle(stream)))
+        self._h = h
+        self.nside, self.lmax, self.max_batch = nside, lmax, max_batch
+        a, b, t, u = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_int64()
+        _check(L.wf_pol_plan_info(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(t), ctypes.byref(u)))
+        self.npix, self.nalm, self.tau, self.units_active = a.value, b.value, t.value, u.value
+        self.last_stats = None
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan has been closed")
+        return self._h
+
+    def solve(self, d, lambdas, s_wf=None, s_alm=None, stream=None, want_alm=True):
+        """d: [3, npix] or [nmaps, 3, npix] float64 on the device. Returns (s_wf, s_alm)."""
+        import torch
+        nmaps = 1 if d.dim() == 2 else d.shape[0]
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        if s_wf is None:
+            s_wf = torch.empty_like(d)
+        if s_alm is None and want_alm:
+            shape = (3, self.nalm) if d.dim() == 2 else (nmaps, 3, self.nalm)
+            s_alm = torch.empty(shape, dtype=torch.complex128, device=d.device)
+        aptr = _dev_ptr(s_alm, torch.complex128, nmaps * 3 * self.nalm, "s_alm") if s_alm is not None else None
+        st = wf_stats()
+        _check(lib().wf_pol_solve_batch(self.handle, nmaps, _dev_ptr(d, torch.float64, nmaps * 3 * self.npix, "d"),
+                                        _dev_ptr(s_wf, torch.float64, nmaps * 3 * self.npix, "s_wf"), aptr,
+                                        lam.ctypes.data, lam.size, _stream_handle(stream), ctypes.byref(st)))
+        self.last_stats = st
+        return s_wf, s_alm
+
+    def map2alm(self, maps, alm=None, stream=None):
+        import torch
+        nmaps = 1 if maps.dim() == 2 else maps.shape[0]
+        if alm is None:
+            shape = (3, self.nalm) if maps.dim() == 2 else (nmaps, 3, self.nalm)
+            alm = torch.empty(shape, dtype=torch.complex128, device=maps.device)
+        _check(lib().sht_pol_map2alm(self.handle, nmaps, _dev_ptr(maps, torch.float64, nmaps * 3 * self.npix, "map"),
+                                     _dev_ptr(alm, torch.complex128, nmaps * 3 * self.nalm, "alm"),
+                                     _stream_handle(stream)))
+        return alm
+
+    def alm2map(self, alm, maps=None, stream=None):
+        import torch
+        nmaps = 1 if alm.dim() == 2 else alm.shape[0]
+        if maps is None:
+            shape = (3, self.npix) if alm.dim() == 2 else (nmaps, 3, self.npix)
+            maps = torch.empty(shape, dtype=torch.float64, device=alm.device)
+        _check(lib().sht_pol_alm2map(self.handle, nmaps, _dev_ptr(alm, torch.complex128, nmaps * 3 * self.nalm, "alm"),
+                                     _dev_ptr(maps, torch.float64, nmaps * 3 * self.npix, "map"),
+                                     _stream_handle(stream)))
+        return maps
+
+    def sync(self):
+        _check(lib().wf_pol_sync(self.handle))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().wf_pol_destroy(self._h)
             self._h = None
 
     def __del__(self):
