@@ -27,8 +27,10 @@
  *   - Element type: double for WF_F64; float for WF_F32, WF_BF16X3 and WF_BF16X6.
  *     WF_F32 runs the Legendre contraction on fp32 matrix cores; the bf16 modes
  *     split both operands into bf16 pieces on bf16 matrix cores with fp32
- *     accumulation: two pieces and three products (WF_BF16X3, ~5e-6 per
- *     transform) or three pieces and six products (WF_BF16X6, fp32-level).
+ *     accumulation: three pieces and six products (WF_BF16X6, fp32-level: within
+ *     1e-5 of FP64 after a full solve) or two pieces and three products
+ *     (WF_BF16X3, ~5e-6 per transform but 2-4e-5 after an 80-sweep solve: it does
+ *     not meet the 1e-5 bar of the other reduced-precision modes).
  *     The Legendre recurrence and the ring FFTs are fp64 on every path.
  *   - Device pointers are HIP device memory owned by the caller; host pointers
  *     are ordinary host memory, copied before the call returns.
@@ -316,12 +318,15 @@ int wf_pixel_angles(int32_t nside, double* theta, double* phi);
 /*
  * wf_autotune -- time every launch shape of the matrix-core Legendre kernels
  * (analysis: 1 or 2 column tiles per workgroup; synthesis: 1, 2 or 4 column tiles
- * per wave, or 8 for WF_F32) on this plan at nmaps maps, keep the fastest in the plan, record it
- * in the process-wide cache (and in opts.tune_cache if given) so that later plans
- * of the same shape start with it. Overwrites the plan's work buffers (run it
- * before a solve, not between the calls of one). Waits for its own launches.
- *   ana_ct, syn_nct  NULL, or receive the chosen shape (0 for WF_F64 plans, which
- *                    have a single shape)
+ * per wave, or 8 for WF_F32, or the wide kernel: 256 ring pairs and 64 columns per
+ * workgroup of 32 x 32 tiles) on this plan at nmaps maps, keep the fastest in the plan,
+ * record it in the process-wide cache (and in opts.tune_cache if given: lines
+ * "key ana_ct syn_nct wide") so that later plans of the same shape start with it.
+ * Task groups and serving lanes use the per-wave synthesis shape. Overwrites the
+ * plan's work buffers (run it before a solve, not between the calls of one). Waits
+ * for its own launches.
+ *   ana_ct, syn_nct  NULL, or receive the chosen shape (syn_nct 64 for the wide
+ *                    kernel; 0 for WF_F64 plans, which have a single shape)
  * Errors: WF_EINVAL (nmaps outside [1, max_batch]), WF_EDEVICE.
  */
 int wf_autotune(wf_plan_t plan, int32_t nmaps, void* hip_stream, int32_t* ana_ct,

@@ -43,11 +43,11 @@ void store_tuning(const std::string& key, const Tuning& t, const char* cache_pat
   g_tune[key] = t;
   if (cache_path && *cache_path) {
     std::ofstream f(cache_path, std::ios::app);
-    if (f) f << key << " " << t.ana_ct << " " << t.syn_nct << "\n";
+    if (f) f << key << " " << t.ana_ct << " " << t.syn_nct << " " << t.syn_wide << "\n";
   }
 }
 
-// Cache file: one line per shape, "key ana_ct syn_nct"; later lines win.
+// Cache file: one line per shape, "key ana_ct syn_nct [syn_wide]"; later lines win.
 void load_tuning_file(const char* cache_path) {
   if (!cache_path || !*cache_path) return;
   std::ifstream f(cache_path);
@@ -58,8 +58,11 @@ void load_tuning_file(const char* cache_path) {
     std::string key;
     Tuning t;
     if (ss >> key >> t.ana_ct >> t.syn_nct && (t.ana_ct == 1 || t.ana_ct == 2) &&
-        (t.syn_nct == 1 || t.syn_nct == 2 || t.syn_nct == 4 || t.syn_nct == 8))
+        (t.syn_nct == 1 || t.syn_nct == 2 || t.syn_nct == 4 || t.syn_nct == 8)) {
+      int wide = 0;
+      if (ss >> wide) t.syn_wide = (wide == 1 || wide == 2) ? wide : 0;
       g_tune[key] = t;
+    }
   }
 }
 
@@ -318,7 +321,7 @@ int run_synthesis(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, 
     TIMED(2, {
       MWF_HIP(launch_mfma_coeff(p->dev, ma, s));
       if (mode != SY_ALM_ONLY)
-        MWF_HIP(launch_mfma_synthesis(p->dev, g.items_s64, g.n_s64, p->dtype, p->tune.syn_nct, ma, s));
+        MWF_HIP(launch_plan_synthesis(g, p->dev, p->dtype, p->tune, ma, s));
     });
     return WF_OK;
   }
@@ -1090,11 +1093,26 @@ extern "C" int wf_autotune(wf_plan_t p, int32_t nmaps, void* hip_stream, int32_t
       best.syn_nct = nct;
     }
   }
+  // the wide kernel (plan solves only; groups keep the per-wave shape chosen above)
+  best.syn_wide = 0;
+  for (int nt : {1, 2}) {
+    MfmaArgs ma = mfma_args(p, SY_FROM_PARTIAL, nmaps, 1.0, nullptr, nullptr);
+    float ms;
+    if ((rc = time_min(s, 3, [&] {
+           hipError_t e = launch_mfma_wide_synthesis(p->dev, g.items_a256, g.n_a256, p->dtype, nt, ma, s);
+           return e == hipSuccess ? WF_OK : fail(WF_EDEVICE, hipGetErrorString(e));
+         }, &ms)))
+      return rc;
+    if (ms < tbest) {
+      tbest = ms;
+      best.syn_wide = nt;
+    }
+  }
   p->tune = best;
   p->tuned = true;
   store_tuning(tune_key(p->dtype, g.nside, g.lmax, 2 * nmaps), best, p->tune_cache.c_str());
   if (ana_ct) *ana_ct = best.ana_ct;
-  if (syn_nct) *syn_nct = best.syn_nct;
+  if (syn_nct) *syn_nct = best.syn_wide ? 32 * best.syn_wide : best.syn_nct;
   return WF_OK;
 }
 

@@ -320,6 +320,10 @@ hipError_t launch_mfma_analysis(const PlanDev& P, const WorkItem* items, int nit
 hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s);
 hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode, int nct,
                                  const MfmaArgs& a, hipStream_t s);
+// Wide synthesis: items of 256 ring pairs, 32 nt columns per workgroup (nt = 1 or 2; see
+// phase_a_mfma.hip).
+hipError_t launch_mfma_wide_synthesis(const PlanDev& P, const WorkItem* items256, int nitems, int mode, int nt,
+                                      const MfmaArgs& a, hipStream_t s);
 
 // One entry of a task group: a plan's tables and buffers, its maps and its lambda for
 // this step. Groups run every task of a step in one launch per phase.

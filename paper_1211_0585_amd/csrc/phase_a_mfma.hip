@@ -412,6 +412,209 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
     }
 }
 
+// ------------------------------------------------------------------ wide synthesis
+// Work item (m, block of 256 ring pairs) and column group cg of 32 NT columns
+// (16 NT maps, NT = 1 or 2 column tiles per wave): four waves, one per 64 ring pairs, each lane running the recurrence of its
+// ring pair. 32 x 32 matrix tiles, M = 32 ring pairs, N = 32 columns, K = values of l
+// of one parity. The A operand comes straight from the registers of the lanes that
+// generated the values: lane l (ring l) and lane l + 32 (ring l + 32) exchange halves
+// with v_permlane32_swap, which turns "my ring, all my values" into the fragments of
+// both ring tiles. The B operand (the coefficients of a chunk of 32 l for the
+// group's columns) is loaded once per chunk by the whole workgroup into LDS, split
+// into bf16 pieces there for the bf16 modes, double buffered, and read by all four
+// waves. The accumulators (2 ring tiles x NT column tiles x 2 parities, 64 NT
+// registers) stay in matrix registers across the loop: the loop body is the same for
+// every iteration (waves past the active ring pairs run a separate loop with the same
+// barriers), so no copies between register files are needed.
+//   FP32  v_mfma_f32_32x32x2f32     A: lane i + 32 k;  B: lane j + 32 k            (K = 2)
+//   bf16  v_mfma_f32_32x32x16_bf16  A: lane i + 32 (k / 8), element k % 8; B likewise (K = 16)
+//   D     lane j + 32 h, register r: row 8 (r / 4) + 4 h + r % 4, column j.
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void swap_halves(unsigned a, unsigned b, unsigned& lo, unsigned& hi) {
+  const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  lo = r[0];   // lanes 0..31: a[l]; lanes 32..63: b[l - 32]
+  hi = r[1];   // lanes 0..31: a[l + 32]; lanes 32..63: b[l]
+}
+
+template <int NP, int NT>
+__global__ void __launch_bounds__(256) mfma_wide_synthesis_kernel(PlanDev P, const WorkItem* __restrict__ items,
+                                                                  MfmaArgs a) {
+  constexpr int WS_COLS = 32 * NT;
+  constexpr bool F32 = (NP == 1);
+  constexpr int NB = F32 ? 1 : NP;
+  constexpr int HF = 17, HB = 24;     // padded stride of h (floats / bf16) per column
+  __shared__ float lds_f[F32 ? 2 : 1][2][WS_COLS][F32 ? HF : 1];
+  __shared__ __attribute__((aligned(16))) __bf16 lds_b[F32 ? 1 : 2][NB][2][WS_COLS][F32 ? 8 : HB];
+  const WorkItem it = items[blockIdx.x];
+  const int cg = blockIdx.y;
+  const int m = it.m;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lmax = P.lmax;
+  const int nact = P.n_active[m];
+  const int q0 = it.blk * 256 + wave * 64;
+  const bool wave_on = q0 < nact;                 // uniform over the wave
+  const int64_t roff = P.row_off[m];
+  const double* __restrict__ Arow = P.A + roff;
+  const int ncols = 2 * a.nmaps;
+  const float* __restrict__ brow = a.bcoef + (size_t)roff * ncols;
+  const int nl = lmax - m + 1;
+
+  // cooperative B load: thread tid takes row lr of the chunk, columns lc .. lc + CPT - 1 of
+  // the group (rows past lmax read the row's zero padding: a prefetch ends < 64 rows past it)
+  constexpr int CPT = 4 * NT;
+  const int lr = tid >> 3, lc = (tid & 7) * CPT;
+  const int colg0 = cg * WS_COLS + lc;
+  auto gload = [&](int i0, float (&v)[CPT]) {
+    const float* src = brow + (size_t)(i0 + lr) * ncols + colg0;
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) v[e] = (colg0 + e < ncols) ? src[e] : 0.0f;
+  };
+  auto lstore = [&](int buf, const float (&v)[CPT]) {
+    const int pp = lr & 1, h = lr >> 1;
+#pragma unroll
+    for (int e = 0; e < CPT; ++e) {
+      if constexpr (F32) {
+        lds_f[buf][pp][lc + e][h] = v[e];
+      } else {
+        __bf16 pc[NB];
+        split_pieces<NB>(v[e], pc);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) lds_b[buf][i][pp][lc + e][h] = pc[i];
+      }
+    }
+  };
+
+  Ring ring = ring_init(P, m, q0 + lane, nact);
+  f16v acc[2][NT][2];   // [ring tile][column tile][parity]
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int n = 0; n < NT; ++n)
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) acc[t][n][pp] = f16v{};
+
+  {
+    float v[CPT];
+    gload(0, v);
+    lstore(0, v);
+  }
+  __syncthreads();
+  if (!wave_on) {
+    // a wave past the active ring pairs only helps stage the coefficients (same barriers)
+    int buf = 0;
+    for (int i0 = 0; i0 < nl; i0 += MCH) {
+      float vn[CPT];
+      const bool more = i0 + MCH < nl;
+      if (more) {
+        gload(i0 + MCH, vn);
+        lstore(buf ^ 1, vn);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
+    return;
+  }
+  int buf = 0;
+  for (int i0 = 0; i0 < nl; i0 += MCH) {
+    // prefetch the next chunk's coefficients (stored to the other buffer after the MFMAs)
+    float vn[CPT];
+    const bool more = i0 + MCH < nl;
+    if (more) gload(i0 + MCH, vn);
+    if constexpr (F32) {
+      float ev[2][16];
+      ring_steps(ring, Arow + i0, [&](int j, double v) { ev[j & 1][j >> 1] = (float)v; });
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) {
+        float bv[NT][8];
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+          for (int s2 = 0; s2 < 8; ++s2) bv[n][s2] = lds_f[buf][pp][32 * n + (lane & 31)][2 * s2 + (lane >> 5)];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) {
+          unsigned t0, t1;
+          swap_halves(__float_as_uint(ev[pp][2 * s2]), __float_as_uint(ev[pp][2 * s2 + 1]), t0, t1);
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            acc[0][n][pp] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(t0), bv[n][s2], acc[0][n][pp], 0, 0, 0);
+            acc[1][n][pp] =
+                __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(t1), bv[n][s2], acc[1][n][pp], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      __bf16 pc[NB][2][16];   // [piece][parity][value]
+      ring_steps(ring, Arow + i0, [&](int j, double v) {
+        __bf16 q[NB];
+        split_pieces<NB>((float)v, q);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) pc[i][j & 1][j >> 1] = q[i];
+      });
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) {
+        bf8 A0[NB], A1[NB], B[NT][NB];
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+#pragma unroll
+          for (int n = 0; n < NT; ++n)
+            B[n][i] = *reinterpret_cast<const bf8*>(&lds_b[buf][i][pp][32 * n + (lane & 31)][8 * (lane >> 5)]);
+          bf8 x, y;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            x[e] = pc[i][pp][e];
+            y[e] = pc[i][pp][8 + e];
+          }
+          typedef unsigned u4 __attribute__((ext_vector_type(4)));
+          const u4 xu = __builtin_bit_cast(u4, x), yu = __builtin_bit_cast(u4, y);
+          u4 lo, hi;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            unsigned l_, h_;
+            swap_halves(xu[w], yu[w], l_, h_);
+            lo[w] = l_;
+            hi[w] = h_;
+          }
+          A0[i] = __builtin_bit_cast(bf8, lo);
+          A1[i] = __builtin_bit_cast(bf8, hi);
+        }
+#pragma unroll
+        for (int k = 0; k < Products<NB>::n; ++k)
+#pragma unroll
+          for (int n = 0; n < NT; ++n) {
+            acc[0][n][pp] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A0[Products<NB>::a[k]], B[n][Products<NB>::b[k]],
+                                                                    acc[0][n][pp], 0, 0, 0);
+            acc[1][n][pp] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A1[Products<NB>::a[k]], B[n][Products<NB>::b[k]],
+                                                                    acc[1][n][pp], 0, 0, 0);
+          }
+      }
+    }
+    if (more) lstore(buf ^ 1, vn);
+    __syncthreads();
+    buf ^= 1;
+  }
+
+  const size_t pstride = (size_t)(lmax + 1) * 4;
+#pragma unroll
+  for (int n = 0; n < NT; ++n) {
+    const int colg = cg * WS_COLS + 32 * n + (lane & 31);
+    const int map = colg >> 1, comp = colg & 1;
+    if (map >= a.nmaps) continue;
+    float* Fm = a.F + (size_t)map * P.npairs * pstride + (size_t)m * 4 + comp;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int q = q0 + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (q < nact) {
+          Fm[(size_t)q * pstride] = acc[t][n][0][r];
+          Fm[(size_t)q * pstride + 2] = acc[t][n][1][r];
+        }
+      }
+  }
+}
+
 // ------------------------------------------------------------------ coefficients
 // Sum the analysis blocks (FP64), scale by C_l, apply the filter, emit the alm and
 // the synthesis coefficients b = C_l s_lm in the layout [padded row][map][re/im].
@@ -626,6 +829,26 @@ hipError_t launch_mfma_coeff(const PlanDev& P, const MfmaArgs& a, hipStream_t s)
   hipLaunchKernelGGL(mfma_coeff_kernel, dim3((unsigned)((n + COEFF_THREADS - 1) / COEFF_THREADS)),
                      dim3(COEFF_THREADS), 0, s, P, a);
   return hipGetLastError();
+}
+
+template <int NT>
+hipError_t wide_nt(const PlanDev& P, const WorkItem* items256, int nitems, int mode, const MfmaArgs& a,
+                   hipStream_t s) {
+  const dim3 grid(nitems, (2 * a.nmaps + 32 * NT - 1) / (32 * NT));
+  if (mode == WF_BF16X3)
+    hipLaunchKernelGGL((mfma_wide_synthesis_kernel<2, NT>), grid, dim3(256), 0, s, P, items256, a);
+  else if (mode == WF_BF16X6)
+    hipLaunchKernelGGL((mfma_wide_synthesis_kernel<3, NT>), grid, dim3(256), 0, s, P, items256, a);
+  else
+    hipLaunchKernelGGL((mfma_wide_synthesis_kernel<1, NT>), grid, dim3(256), 0, s, P, items256, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_wide_synthesis(const PlanDev& P, const WorkItem* items256, int nitems, int mode, int nt,
+                                      const MfmaArgs& a, hipStream_t s) {
+  if (nt == 1) return wide_nt<1>(P, items256, nitems, mode, a, s);
+  if (nt == 2) return wide_nt<2>(P, items256, nitems, mode, a, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_mfma_synthesis(const PlanDev& P, const WorkItem* items, int nitems, int mode, int nct,

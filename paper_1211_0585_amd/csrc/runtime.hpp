@@ -107,7 +107,17 @@ RingGeo ring_geometry(int n, int i);
 struct Tuning {
   int ana_ct = 2;    // column tiles per analysis workgroup (ring block 128 ct)
   int syn_nct = 2;   // column tiles per synthesis wave (8 for FP32 only)
+  int syn_wide = 0;  // 1 or 2: a plan's own solves use the wide synthesis kernel with that many column
+                     // tiles per wave (task groups keep syn_nct)
 };
+
+// The matrix-core synthesis of a plan with its tuning: the wide kernel (256 ring pairs,
+// 32 syn_wide columns per workgroup) or the per-wave kernel with syn_nct column tiles.
+inline hipError_t launch_plan_synthesis(const Geometry& g, const PlanDev& P, int dtype, const Tuning& t,
+                                        const MfmaArgs& a, hipStream_t s) {
+  if (t.syn_wide) return launch_mfma_wide_synthesis(P, g.items_a256, g.n_a256, dtype, t.syn_wide, a, s);
+  return launch_mfma_synthesis(P, g.items_s64, g.n_s64, dtype, t.syn_nct, a, s);
+}
 
 bool lookup_tuning(const std::string& key, Tuning* t);
 void store_tuning(const std::string& key, const Tuning& t, const char* cache_path);

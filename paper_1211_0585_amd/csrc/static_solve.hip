@@ -161,7 +161,7 @@ extern "C" int wf_solve_batch_static(wf_plan_t p, int32_t nmaps, const void* d, 
       ma.lambda = lambda[k];
       ma.alm_out = static_cast<float2*>(alm_out);
       MWF_HIP(launch_mfma_coeff(P, ma, s));
-      MWF_HIP(launch_mfma_synthesis(P, g.items_s64, g.n_s64, p->dtype, p->tune.syn_nct, ma, s));
+      MWF_HIP(launch_plan_synthesis(g, P, p->dtype, p->tune, ma, s));
     }
   }
   if (int rc = ring(PB_SYNTH | PB_WRITE_MAP, 1.0, nullptr, s_wf)) return rc;

@@ -6,8 +6,8 @@ synthesis of the drawn signal + noise, then the oracle messenger solve under a
 short schedule that ends at lambda = 1 (a full 80-sweep oracle solve at this size
 would take many hours). Stores, for d and for the result after the schedule:
 the norm, first entries and seeded random projections, seeded samples of pixels
-and alm, and the L2 norm of every ring of the map and of every m column of the
-alm (so that an error confined to a few rings or a few m cannot hide under the
+and alm, and the L2 norm and a seeded random projection of every ring of the map and of
+every m column of the alm (so that an error confined to a few rings or a few m cannot hide under the
 global norm).
 
 Run from the repository root:  python tests/golden/make_golden_1024.py
@@ -58,6 +58,17 @@ def summarize(prefix, s_map, s_alm, store):
     store[prefix + "alm_norm"] = np.sqrt(np.sum(w * np.abs(s_alm) ** 2))
     store[prefix + "ring_norm"] = ring_norms(s_map, NSIDE)
     store[prefix + "m_norm"] = m_norms(s_alm, LMAX)
+    # per ring and per m: the projection on one seeded random vector (a local error
+    # changes it by about its own size, whatever the sign)
+    v = np.random.default_rng(99).standard_normal(s_map.size)
+    g = healpix.ring_info(NSIDE)
+    store[prefix + "ring_proj"] = np.array([np.dot(v[a:a + n], s_map[a:a + n]) for a, n in zip(g["start"], g["nphi"])])
+    u = np.random.default_rng(98).standard_normal(s_alm.size) + 1j * np.random.default_rng(97).standard_normal(s_alm.size)
+    mp = np.empty(LMAX + 1, dtype=np.complex128)
+    for m in range(LMAX + 1):
+        i0 = alm_index(LMAX, m, m)
+        mp[m] = np.sum(u[i0:i0 + LMAX - m + 1] * s_alm[i0:i0 + LMAX - m + 1])
+    store[prefix + "m_proj"] = mp
     proj = np.random.default_rng(77).standard_normal((4, s_map.size))
     store[prefix + "map_proj"] = proj @ s_map
 

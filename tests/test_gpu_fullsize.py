@@ -8,15 +8,19 @@ the oracle alone: sampled pixels and alm, norms, projections on seeded random
 vectors). The GPU builds the same data map with its FP64 synthesis, checked
 against the oracle's map through the stored norm, head and projections, then
 solves: plain FP64 one map (<= 1e-10), and the 64-map matrix-core batch with
-the case as map 0 (FP32 and bf16x6 <= 1e-5, bf16x3 <= 1e-4), plus batch
+the case as map 0 (FP32 and bf16x6 <= 1e-5; bf16x3 <= 5e-5, its stated accuracy, below
+the 1e-5 bar), plus batch
 composition: maps solved alone equal their batch results (<= 1e-6).
 
-Nside 1024: no oracle solve fits in a test, so the checks are sampled outputs
-the oracle computes directly (whole m columns of the analysis, the synthesis of
-alm restricted to those columns at every pixel), the full-sky uniform-noise
-closed form of the solve (every sweep sets t = d, so s_lm = f_l(lambda_last)
-map2alm(d)_lm) on those columns, and the agreement of the reduced-precision
-solves with the FP64 one on the satellite recipe (N_obs / 4).
+Nside 1024: the FP64 oracle's solve of the seed-0 precision case (satellite recipe,
+N_obs / 4) under a 4-sweep schedule ending at lambda = 1 is stored in
+tests/golden/nside1024_satellite.npz (tests/golden/make_golden_1024.py, oracle only):
+FP64 <= 1e-10, FP32 and bf16x6 <= 1e-5 on sampled pixels, sampled alm, norms,
+projections and the worst ring and worst m of per-ring / per-m projections. Besides:
+sampled outputs the oracle computes directly (whole m columns of the analysis, the
+synthesis of alm restricted to those columns at every pixel), the full-sky
+uniform-noise closed form of the solve on those columns, and the agreement of the
+reduced-precision 80-sweep solves with the FP64 one.
 """
 import os
 import sys
@@ -32,10 +36,15 @@ from tests.helpers import rel_l2
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "nside512_satellite.npz")
+GOLDEN10 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "nside1024_satellite.npz")
 N5, L5 = 512, 1024
 N10, L10 = 1024, 2048
 MS = [0, 1, 2, 255, 1023, 1024, 2000, 2047, 2048]
-SOLVE_TOL = {1: 1e-5, 3: 1e-5, 2: 1e-4}
+# Solve bars against the FP64 oracle: FP32 and bf16x6 meet the 1e-5 bar. bf16x3 (two bf16
+# pieces, three products) does not: its pieces leave ~2^-18 of each operand unrepresented
+# and it drops lo*lo, so a full 80-sweep solve lands at ~2-4e-5; it is checked against
+# that stated accuracy, 5e-5, and is not counted as meeting the bar.
+SOLVE_TOL = {1: 1e-5, 3: 1e-5, 2: 5e-5}
 MODES = [("f32", 1), ("bf16x6", 3), ("bf16x3", 2)]
 
 
@@ -123,6 +132,73 @@ def test_batched64_nside512_vs_oracle_and_alone(torch_dev, case512, name, dt):
             e = rel_l2(si.cpu().numpy(), s[i].cpu().numpy())
             _log(f"batched {name}: map {i} alone vs in the batch {e:.2e} (bitwise {bool(torch.equal(si, s[i]))})")
             assert e <= 1e-6
+
+
+def _vs_golden_full(prefix, g, s_map, s_alm, lmax, nside):
+    """_vs_golden plus the worst ring and worst m: per-ring / per-m projections on seeded
+    random vectors against the stored ones, relative to that ring's / m's norm."""
+    rs = np.random.default_rng(77)
+    proj = rs.standard_normal((4, s_map.size))
+    w = sht.alm_weights(lmax)[g[prefix + "alm_idx"]]
+    out = {"pix": rel_l2(s_map[g[prefix + "pix_idx"]], g[prefix + "pix_val"]),
+           "alm": rel_l2(s_alm[g[prefix + "alm_idx"]], g[prefix + "alm_val"], w),
+           "norm": abs(np.linalg.norm(s_map) - g[prefix + "map_norm"]) / g[prefix + "map_norm"],
+           "proj": rel_l2(proj @ s_map, g[prefix + "map_proj"])}
+    if prefix + "ring_proj" in g:
+        ri = healpix.ring_info(nside)
+        v = np.random.default_rng(99).standard_normal(s_map.size)
+        rp = np.add.reduceat(v * s_map, ri["start"])
+        # relative to each ring's (m's) norm, floored at 1e-6 of the largest: columns of
+        # almost no power (the highest m, where the GPU leaves out values below 2^-448)
+        # are compared at the precision they contribute to the whole
+        rn = np.maximum(g[prefix + "ring_norm"], 1e-6 * g[prefix + "ring_norm"].max())
+        out["worst_ring"] = float(np.max(np.abs(rp - g[prefix + "ring_proj"]) / rn))
+        u = np.random.default_rng(98).standard_normal(s_alm.size) + 1j * np.random.default_rng(97).standard_normal(
+            s_alm.size)
+        mp = np.add.reduceat(u * s_alm, np.array([alm_index(lmax, m, m) for m in range(lmax + 1)]))
+        mn = np.maximum(g[prefix + "m_norm"], 1e-6 * g[prefix + "m_norm"].max())
+        out["worst_m"] = float(np.max(np.abs(mp - g[prefix + "m_proj"]) / mn))
+    return out
+
+
+@pytest.fixture(scope="module")
+def case1024(torch_dev):
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    if not os.path.exists(GOLDEN10):
+        pytest.skip("golden file missing (python tests/golden/make_golden_1024.py)")
+    g = dict(np.load(GOLDEN10))
+    theta, phi = healpix.pixel_angles(N10)
+    model = synth.satellite_model(theta, phi, L10, nobs_scale=0.25)
+    dr = synth.draw(model, 0)
+    with mwf.Plan(N10, L10, model["cl"], model["ninv"], mask=~model["mask"]) as p:
+        d = (p.alm2map(torch.from_numpy(dr["signal_alm"]).cuda()) + torch.from_numpy(dr["noise"]).cuda()).cpu().numpy()
+    proj = np.random.default_rng(77).standard_normal((4, d.size))
+    e_in = max(abs(np.linalg.norm(d) - g["d_norm"]) / g["d_norm"], rel_l2(d[:64], g["d_head"]),
+               rel_l2(proj @ d, g["d_proj"]))
+    _log(f"Nside 1024 input: GPU synthesis vs oracle data map {e_in:.2e}")
+    assert e_in <= 1e-12
+    return model, d, g
+
+
+@pytest.mark.parametrize("name,dt", [("f64", 0)] + MODES)
+def test_nside1024_solve_vs_oracle(torch_dev, case1024, name, dt):
+    """The precision workload (Nside 1024, lmax 2048) per dtype against the oracle's solve."""
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    model, d, g = case1024
+    tol = 1e-10 if dt == 0 else SOLVE_TOL[dt]
+    dd = torch.from_numpy(d if dt == 0 else d.astype(np.float32)).cuda()
+    with mwf.Plan(N10, L10, model["cl"], model["ninv"], mask=~model["mask"], dtype=dt) as p:
+        s, a = p.solve(dd, g["schedule"])
+        p.sync()
+        e = _vs_golden_full("sol_", g, s.double().cpu().numpy(), a.to(torch.complex128).cpu().numpy(), L10, N10)
+    _log(f"Nside 1024 lmax 2048 {name}, {len(g['schedule'])} sweeps vs oracle: {e}")
+    assert max(e[k] for k in ("pix", "alm", "norm", "proj")) <= tol
+    if "worst_ring" in e:
+        # a projection on a random vector: |error| is about the local error norm, so a
+        # factor 10 above the bar still flags any ring or m with a local error near it
+        assert e["worst_ring"] <= 10 * tol and e["worst_m"] <= 10 * tol
 
 
 @pytest.fixture(scope="module")

@@ -6,9 +6,11 @@ pieces and sums six bf16 products in FP32; WF_BF16X3 uses two pieces and three
 products. The Legendre recurrence and the ring FFTs stay FP64.
 
 Bars, relative L2 against the FP64 oracle fed the same inputs (rounded to FP32
-for the GPU): WF_F32 and WF_BF16X6 <= 1e-5 on s_WF and on the alm. WF_BF16X3
-drops the lo*lo product (about 2^-18 relative per product): <= 1e-5 per
-transform and <= 1e-4 after a full solve, which is what it guarantees.
+for the GPU): WF_F32 and WF_BF16X6 <= 1e-5 on s_WF and on the alm, the bar of
+every reduced-precision result. WF_BF16X3 does not meet that bar after a full
+solve: two pieces leave ~2^-18 of each operand unrepresented and lo*lo (~2^-18)
+is dropped, ~5e-6 per transform, accumulating to 2-4e-5 over 80-140 sweeps. Its
+transforms are held to 1e-5 and its solves to its stated accuracy, 5e-5.
 """
 import sys
 
@@ -21,7 +23,7 @@ from tests.helpers import alm_rel_l2, random_alm, rel_l2, small_band_inputs
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-SOLVE_TOL = {1: 1e-5, 3: 1e-5, 2: 1e-4}
+SOLVE_TOL = {1: 1e-5, 3: 1e-5, 2: 5e-5}   # bf16x3: stated accuracy, below the bar
 MODES = [("f32", 1), ("bf16x6", 3), ("bf16x3", 2)]
 
 
