@@ -200,3 +200,58 @@ def test_pol_rejects_bad_inputs(torch_dev):
         mwf.PolPlan(nside, lmax, c["cl4"], n6)
     with pytest.raises(mwf.WFError):                         # nside not a power of two
         mwf.PolPlan(3, 4, np.zeros((4, 5)), np.ones((6, 108)) * [[1], [1], [1], [0], [0], [0]])
+
+
+GOLDEN_POL = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)),
+                                        "golden", "nside512_pol.npz")
+
+
+def _field_errs(g, prefix, maps, alm, lmax, nside):
+    """Per field: sampled pixels and alm, norms, worst ring and worst m of the seeded
+    per-ring / per-m projections (norms floored at 1e-6 of the largest)."""
+    ri = healpix.ring_info(nside)
+    v = np.random.default_rng(99).standard_normal(maps.shape[1])
+    u = (np.random.default_rng(98).standard_normal(alm.shape[1])
+         + 1j * np.random.default_rng(97).standard_normal(alm.shape[1]))
+    mstart = np.array([m * (2 * lmax + 1 - m) // 2 + m for m in range(lmax + 1)])
+    w = sht.alm_weights(lmax)[g[prefix + "alm_idx"]]
+    out = {}
+    for f in range(3):
+        k, ka = prefix + "TQU"[f] + "_", prefix + "TEB"[f] + "_"
+        rp = np.add.reduceat(v * maps[f], ri["start"])
+        rn = np.maximum(g[k + "ring_norm"], 1e-6 * g[k + "ring_norm"].max())
+        mp = np.add.reduceat(u * alm[f], mstart)
+        mn = np.maximum(g[ka + "m_norm"], 1e-6 * g[ka + "m_norm"].max())
+        out["TQU"[f]] = max(rel_l2(maps[f][g[prefix + "pix_idx"]], g[k + "pix_val"]),
+                            abs(np.linalg.norm(maps[f]) - g[k + "map_norm"]) / g[k + "map_norm"],
+                            float(np.max(np.abs(rp - g[k + "ring_proj"]) / rn)) / 10)
+        out["TEB"[f]] = max(rel_l2(alm[f][g[prefix + "alm_idx"]], g[ka + "alm_val"], w),
+                            float(np.max(np.abs(mp - g[ka + "m_proj"]) / mn)) / 10)
+    return out
+
+
+def test_pol_nside512_vs_stored_oracle(torch_dev):
+    """The satellite-scale polarised case (Nside 512, lmax 1024, 3-sweep schedule) against
+    the oracle's stored solve (tests/golden/make_golden_pol.py): <= 1e-10 per field on
+    sampled pixels and alm and norms, and <= 1e-9 on the worst ring / m projection."""
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    import os
+    if not os.path.exists(GOLDEN_POL):
+        pytest.skip("golden file missing (python tests/golden/make_golden_pol.py)")
+    g = dict(np.load(GOLDEN_POL))
+    nside, lmax = 512, 1024
+    theta, phi = healpix.pixel_angles(nside)
+    c = synth.pol_satellite_case(theta, phi, lmax, seed=0)
+    with mwf.PolPlan(nside, lmax, c["cl4"], c["ninv6"], mask=c["mask"]) as p:
+        d = p.alm2map(torch.from_numpy(c["signal_alm"]).cuda()) + torch.from_numpy(c["noise"]).cuda()
+        a_d = p.map2alm(d)
+        p.sync()
+        e_in = _field_errs(g, "d_", d.cpu().numpy(), a_d.cpu().numpy(), lmax, nside)
+        _log(f"Nside 512 polarised data map and its alm vs oracle: {e_in}")
+        assert max(e_in.values()) <= 1e-12
+        s, a = p.solve(d, g["schedule"])
+        p.sync()
+        e = _field_errs(g, "sol_", s.cpu().numpy(), a.cpu().numpy(), lmax, nside)
+    _log(f"Nside 512 polarised solve, {len(g['schedule'])} sweeps vs oracle: {e}")
+    assert max(e.values()) <= 1e-10
