@@ -190,16 +190,22 @@ double chi_of_record(const double* rec, double tau) {
   return prior + data / tau;
 }
 
-// chi^2 history buffer ([map][CHI_REC chi2_cap]) for at least `maps` maps and n
-// iterates, cleared on s. Kernels find map i at chi2 + i CHI_REC chi2_cap.
+// chi^2 history buffer ([map][CHI_REC chi2_cap]) laid out for this solve's `maps`
+// maps and n iterates (chi2_cap = n), its records cleared on s. The allocation is
+// replaced only when it is too small, so it stays at the largest maps x n asked of
+// the plan. Kernels find map i at chi2 + i CHI_REC chi2_cap.
 int ensure_chi2(wf_plan_s* p, int maps, int n, hipStream_t s) {
-  if (n > p->chi2_cap || maps > p->chi2_maps) {
-    const int cap = std::max(n, p->chi2_cap), nm = std::max(maps, p->chi2_maps);
-    if (int rc = p->mem.alloc(&p->chi2_buf, (size_t)nm * CHI_REC * cap)) return rc;
-    p->chi2_cap = cap;
-    p->chi2_maps = nm;
+  const size_t need = (size_t)maps * CHI_REC * n;
+  if (need > p->chi2_alloc) {
+    p->mem.release(p->chi2_buf);
+    p->chi2_buf = nullptr;
+    p->chi2_alloc = 0;
+    if (int rc = p->mem.alloc(&p->chi2_buf, need)) return rc;
+    p->chi2_alloc = need;
   }
-  MWF_HIP(hipMemsetAsync(p->chi2_buf, 0, (size_t)p->chi2_maps * CHI_REC * p->chi2_cap * sizeof(double), s));
+  p->chi2_cap = n;
+  p->chi2_maps = maps;
+  MWF_HIP(launch_zero_fill(p->chi2_buf, need * sizeof(double), s));
   return WF_OK;
 }
 

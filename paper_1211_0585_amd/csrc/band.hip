@@ -1,9 +1,15 @@
+// Small device utilities of the host runtime.
+//
 // Band-limit changes of the truncated solves (Sect. 3: the transforms of a sweep
-// stop at l_max^SHT = l_iter + margin while lambda is large). A packed alm array of
+// stop at l_max^SHT = l_iter + margin while lambda is large): a packed alm array of
 // band limit ls is copied into the packed layout of band limit ld >= ls, with the
 // modes l > ls set to zero.
+//
+// Zero fills by a kernel rather than hipMemsetAsync, so that a caller may record
+// the work in a HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 namespace mwf {
@@ -27,7 +33,21 @@ __global__ void alm_repack_kernel(const T2* __restrict__ src, int ls, T2* __rest
   }
 }
 
+__global__ void zero_fill_kernel(uint4* __restrict__ p, size_t n16) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
 }  // namespace
+
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return hipSuccess;
+  if (!p || bytes % 16 != 0 || reinterpret_cast<uintptr_t>(p) % 16 != 0) return hipErrorInvalidValue;
+  const size_t n16 = bytes / 16;
+  const unsigned blocks = (unsigned)std::min<size_t>(1024, (n16 + 255) / 256);
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(blocks), dim3(256), 0, s, static_cast<uint4*>(p), n16);
+  return hipGetLastError();
+}
 
 hipError_t launch_alm_repack(const void* src, int ls, void* dst, int ld, bool fp64, hipStream_t s) {
   if (ls < 0 || ld < ls || !src || !dst) return hipErrorInvalidValue;

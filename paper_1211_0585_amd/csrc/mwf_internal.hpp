@@ -256,6 +256,8 @@ inline size_t ring_lds_bytes(int fft_len, size_t elem) {
 }
 
 // cls: NRING_CLASSES classes, launched in order (empty ones skipped).
+// Zero `bytes` (a multiple of 16, 16-byte aligned) at p on s with a kernel.
+hipError_t launch_zero_fill(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_phase_b(const PlanDev& P, const PhaseBArgs& a, const RingClass* cls, bool fp32, hipStream_t s);
 // One class alone (cls: its index, which fixes the workgroup size).
 hipError_t launch_phase_b_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, int cls, bool fp32,

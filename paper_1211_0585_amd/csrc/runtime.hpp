@@ -22,6 +22,17 @@ struct DevMem {
   ~DevMem() {
     for (void* p : ptrs) hipFree(p);
   }
+  // Free one allocation made by alloc (no-op for nullptr). hipFree waits for the
+  // device, so work already enqueued on it has finished.
+  void release(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < ptrs.size(); ++i)
+      if (ptrs[i] == p) {
+        hipFree(p);
+        ptrs.erase(ptrs.begin() + i);
+        return;
+      }
+  }
   template <class T>
   int alloc(T** out, size_t count) {
     void* v = nullptr;
@@ -175,6 +186,7 @@ struct wf_plan_s {
   float* bcoef32 = nullptr;            // matrix cores: [rows_total][batch][2]
   double* chi2_buf = nullptr;          // chi^2 history: [chi2_maps][CHI_REC chi2_cap], one record per iterate
   int chi2_cap = 0, chi2_maps = 0, chi2_nsweeps = 0, chi2_nmaps = 0;
+  size_t chi2_alloc = 0;               // doubles allocated at chi2_buf
   mwf::PlanDev dev{};
   mwf::DevMem mem;
   // second stream for ring classes that run side by side (default priority),

@@ -45,10 +45,6 @@ int workspace(int device, unsigned char** out) {
   return WF_OK;
 }
 
-__global__ void ws_fill_zero(uint4* __restrict__ p, size_t n16) {
-  const size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
-}
 
 constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -111,8 +107,7 @@ extern "C" int wf_solve_batch_static(wf_plan_t p, int32_t nmaps, const void* d, 
   const bool fp64 = p->dtype == WF_F64;
 
   // F entries of polar-skipped (m, ring pair) combinations are read but never written
-  hipLaunchKernelGGL(ws_fill_zero, dim3(1024), dim3(256), 0, s, reinterpret_cast<uint4*>(F), L.gf_bytes / 16);
-  MWF_HIP(hipGetLastError());
+  MWF_HIP(launch_zero_fill(F, L.gf_bytes, s));
 
   // ring phase: every class on this one stream (no second stream is made)
   const RingClass* cls = g.ring_cls[nmaps >= RING_SPLIT_MAPS ? 1 : 0];

@@ -81,3 +81,39 @@ def test_chi2_requires_flag_and_sizes(torch_dev):
             p.chi2(1, 4)
         p.solve(d, np.ones(5))   # a longer schedule grows the history
         assert p.chi2(1, 5).shape == (1, 5)
+
+
+@pytest.mark.parametrize("name,dt,tol", [("f64", 0, 1e-10), ("f32", 1, 1e-5)])
+def test_chi2_batch_after_adaptive_solve(torch_dev, name, dt, tol):
+    """The history buffer is laid out per solve: an adaptive solve (one map, a long
+    sweep cap) followed by a 3-map batch on the same plan records the batch's history
+    as a fresh plan does, and as the oracle evaluates it; a shorter batch after that
+    (fewer sweeps, fewer maps) too."""
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf
+    nside, lmax, nm = 8, 16, 3
+    cs = [small_band_inputs(nside, lmax, seed=60 + i) for i in range(nm)]
+    c = cs[0]
+    rt = np.float64 if dt == 0 else np.float32
+    D = np.stack([x["d"] for x in cs]).astype(rt)
+    lams = np.geomspace(1e3, 1.0, 14)
+    with mwf.Plan(nside, lmax, c["cl"], c["ninv"], dtype=dt, max_batch=nm, flags=mwf.WF_FLAG_CHI2) as p:
+        _, _, info = p.solve_adaptive(torch.from_numpy(D[0]).cuda(), 300)
+        assert len(info["chi2"]) > len(lams)
+        p.solve(torch.from_numpy(D).cuda(), lams)
+        hist = p.chi2(nm, len(lams))
+        p.solve(torch.from_numpy(D[1:2].copy()).cuda(), lams[:5])
+        hist_short = p.chi2(1, 5)
+    with mwf.Plan(nside, lmax, c["cl"], c["ninv"], dtype=dt, max_batch=nm, flags=mwf.WF_FLAG_CHI2) as q:
+        q.solve(torch.from_numpy(D).cuda(), lams)
+        fresh = q.chi2(nm, len(lams))
+    e_fresh = np.max(np.abs(hist - fresh) / np.abs(fresh))
+    worst = 0.0
+    for i in range(nm):
+        ref = _oracle_history(D[i].astype(np.float64), c, lams, nside, lmax)
+        worst = max(worst, np.max(np.abs(hist[i] - ref) / np.abs(ref)))
+    ref_short = _oracle_history(D[1].astype(np.float64), c, lams[:5], nside, lmax)
+    e_short = np.max(np.abs(hist_short[0] - ref_short) / np.abs(ref_short))
+    _log(f"chi2 {name} batch after adaptive ({len(info['chi2'])} sweeps): vs fresh plan {e_fresh:.2e}, "
+         f"vs oracle {worst:.2e}; shorter batch vs oracle {e_short:.2e}")
+    assert e_fresh <= tol and worst <= tol and e_short <= tol
