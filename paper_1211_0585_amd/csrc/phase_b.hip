@@ -376,108 +376,145 @@ struct Vec4<float> {
   using type = float4;
 };
 
+// exp(i k phi0) at k = tid and exp(i NT phi0), the factor that advances k by NT: the
+// phases of the synthesis bins and (conjugated) of the analysis coefficients, which
+// share them (bin k and coefficient m = k). Both 1 on rings with phi0 = 0.
+struct RingPhase {
+  double2 ph0, step;
+};
+template <int NT>
+__device__ __forceinline__ RingPhase ring_phase(const RingPair& rp) {
+  RingPhase r;
+  if (rp.ph_num == 0) {
+    r.ph0 = make_double2(1.0, 0.0);
+    r.step = r.ph0;
+  } else {
+    r.ph0 = expipi<double>((int64_t)threadIdx.x * rp.ph_num, rp.nphi);
+    r.step = expipi<double>((int64_t)NT * rp.ph_num, rp.nphi);
+  }
+  return r;
+}
+
+// Bins of a ring pair a thread folds with its loads issued up front: the largest
+// number of bins k = tid + u NT a launch class has, at most four.
+constexpr int fold_depth(int kind, int maxb) {
+  const int u = (kind == 1 ? 2 : 4) * maxb;
+  return u < 4 ? u : 4;
+}
+
 // Synthesis loading step of one ring pair: the bins B[k] = sum over m = k (mod n) of
 // F(m) exp(i m phi0) (F(-m) = conj F(m)) of the north and south rings, from the E/O
-// coefficients Fp[m][4] of this map and pair, into buf as B_N + i B_S (k < n). Short
-// rings use lds_raw for partial sums (consumed before the function returns). Every
-// thread of the workgroup calls it.
-template <class T, class C, int NT>
+// coefficients Fp[m][4] of this map and pair, into buf as B_N + i B_S (k < n), in the
+// transform's arithmetic type C. Long rings: thread tid folds bins tid + u NT; the
+// first alias of its first KU bins is loaded before any is folded. Short rings use
+// lds_raw for partial sums (consumed before the function returns). Every thread of
+// the workgroup calls it.
+template <class T, class C, int NT, int KU>
 __device__ __forceinline__ void fold_synthesis(const PlanDev& P, const T* __restrict__ Fp, const RingPair& rp,
-                                               typename CT<C>::V* buf, unsigned char* lds_raw) {
+                                               typename CT<C>::V* buf, unsigned char* lds_raw,
+                                               const RingPhase& rph) {
   using V4 = typename Vec4<T>::type;
   using V = typename CT<C>::V;
   const int n = rp.nphi;
   const int lmax = P.lmax;
   const int tid = threadIdx.x;
-  const double sig = rp.ph_num ? -1.0 : 1.0;      // exp(i n phi0)
-  // exp(i k phi0) for k = tid + s * NT, advanced by one complex multiply
-  double2 ph = expipi<double>((int64_t)tid * rp.ph_num, n);
-  const double2 step = expipi<double>((int64_t)NT * rp.ph_num, n);
+  const C sig = rp.ph_num ? (C)-1 : (C)1;          // exp(i n phi0)
+  auto eo_load = [&](int m) { return *reinterpret_cast<const V4*>(Fp + (size_t)m * 4); };
   if (n > FOLD_PARTS) {
-    // the first positive and negative alias of the next bin are loaded while the
-    // current bin is folded (one bin ahead)
-    V4 pos_nx{}, neg_nx{};
-    {
-      const int k = tid, mn = (k == 0) ? n : n - k;
-      if (k < n && k <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k * 4);
-      if (k < n && mn <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn * 4);
-    }
-    for (int k = tid; k < n; k += NT) {
-      const V4 pos0 = pos_nx, neg0 = neg_nx;
-      {
-        const int k1 = k + NT, mn1 = n - k1;
-        if (k1 < n && k1 <= lmax) pos_nx = *reinterpret_cast<const V4*>(Fp + (size_t)k1 * 4);
-        if (k1 < n && mn1 <= lmax) neg_nx = *reinterpret_cast<const V4*>(Fp + (size_t)mn1 * 4);
-      }
-      double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
-      double s = 1.0;                               // sig^t for m = k + t n
-      for (int m = k; m <= lmax; m += n) {          // m >= 0 with m = k (mod n)
-        const V4 eo = (m == k) ? pos0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-        double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
-        double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
+    // bin k: positive aliases m = k + t n, negative ones |m| = t n - k (t >= 1); its
+    // first alias is m = k if k <= lmax, else n - k (there is then no positive one)
+    auto fold_bin = [&](const int k, const V4 f1, const double2 phd) {
+      const V ph = CT<C>::make((C)phd.x, (C)phd.y);
+      V bn = CT<C>::make(0, 0), bs = CT<C>::make(0, 0);
+      C sg = (C)1;                                  // sig^t
+      for (int m = k; m <= lmax; m += n) {
+        const V4 eo = (m == k) ? f1 : eo_load(m);
+        V fn = CT<C>::make((C)eo.x + (C)eo.z, (C)eo.y + (C)eo.w);
+        V fs = CT<C>::make((C)eo.x - (C)eo.z, (C)eo.y - (C)eo.w);
         if (m == 0) {
-          fn.y = 0.0;
-          fs.y = 0.0;
+          fn.y = (C)0;
+          fs.y = (C)0;
         } else {
-          const double2 phm = make_double2(s * ph.x, s * ph.y);
+          const V phm = CT<C>::make(sg * ph.x, sg * ph.y);
           fn = cmul(fn, phm);
           fs = cmul(fs, phm);
         }
         bn = cadd(bn, fn);
         bs = cadd(bs, fs);
-        s *= sig;
+        sg *= sig;
       }
-      // m < 0 terms: |m| = t n - k (t >= 1), exp(i |m| phi0) = sig^t conj(exp(i k phi0))
-      s = sig;
+      // exp(i |m| phi0) = sig^t conj(exp(i k phi0))
+      sg = sig;
       const int mn = (k == 0) ? n : n - k;
       for (int m = mn; m <= lmax; m += n) {
-        const V4 eo = (m == mn) ? neg0 : *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-        const double2 phm = make_double2(s * ph.x, -s * ph.y);
-        const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
-        const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
+        const V4 eo = (m == mn && k > lmax) ? f1 : eo_load(m);
+        const V phm = CT<C>::make(sg * ph.x, -sg * ph.y);
+        const V fn = cmul(CT<C>::make((C)eo.x + (C)eo.z, (C)eo.y + (C)eo.w), phm);
+        const V fs = cmul(CT<C>::make((C)eo.x - (C)eo.z, (C)eo.y - (C)eo.w), phm);
         bn = cadd(bn, cconj(fn));
         bs = cadd(bs, cconj(fs));
-        s *= sig;
+        sg *= sig;
       }
-      buf[k] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
-      ph = cmul(ph, step);
+      return CT<C>::make(bn.x - bs.y, bn.y + bs.x);   // B_N + i B_S
+    };
+    V4 first[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = tid + u * NT;
+      const int m1 = k <= lmax ? k : n - k;
+      if (k < n && m1 <= lmax) first[u] = eo_load(m1);
+    }
+    double2 ph = rph.ph0;
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = tid + u * NT;
+      if (k < n) buf[k] = fold_bin(k, first[u], ph);
+      ph = cmul(ph, rph.step);
+    }
+    for (int k = tid + KU * NT; k < n; k += NT) {
+      const int m1 = k <= lmax ? k : n - k;
+      V4 f1{};
+      if (m1 <= lmax) f1 = eo_load(m1);
+      buf[k] = fold_bin(k, f1, ph);
+      ph = cmul(ph, rph.step);
     }
   } else {
     // short rings carry many aliases per bin: G partial sums per bin, each over
     // every G-th alias, spread over the whole workgroup, then added in a fixed order
     const int G = FOLD_PARTS / n, np = G * n;
-    const double sigG = (G & 1) ? sig : 1.0;
-    double2* part = reinterpret_cast<double2*>(lds_raw);    // [np][N, S]
+    const C sigG = (G & 1) ? sig : (C)1;
+    V* part = reinterpret_cast<V*>(lds_raw);    // [np][N, S]
     for (int p = tid; p < np; p += NT) {
       const int k = p % n, g = p / n;
-      const double2 phk = expipi<double>((int64_t)k * rp.ph_num, n);   // exp(i k phi0)
-      double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
-      double s = (g & 1) ? sig : 1.0;               // sig^t, t = g + u G
+      const double2 phd = rp.ph_num ? expipi<double>((int64_t)k, n) : make_double2(1.0, 0.0);   // exp(i k phi0)
+      const V phk = CT<C>::make((C)phd.x, (C)phd.y);
+      V bn = CT<C>::make(0, 0), bs = CT<C>::make(0, 0);
+      C sg = (g & 1) ? sig : (C)1;                  // sig^t, t = g + u G
       for (int m = k + g * n; m <= lmax; m += G * n) {
-        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-        double2 fn = make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w);
-        double2 fs = make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w);
+        const V4 eo = eo_load(m);
+        V fn = CT<C>::make((C)eo.x + (C)eo.z, (C)eo.y + (C)eo.w);
+        V fs = CT<C>::make((C)eo.x - (C)eo.z, (C)eo.y - (C)eo.w);
         if (m == 0) {
-          fn.y = 0.0;
-          fs.y = 0.0;
+          fn.y = (C)0;
+          fs.y = (C)0;
         } else {
-          const double2 phm = make_double2(s * phk.x, s * phk.y);
+          const V phm = CT<C>::make(sg * phk.x, sg * phk.y);
           fn = cmul(fn, phm);
           fs = cmul(fs, phm);
         }
         bn = cadd(bn, fn);
         bs = cadd(bs, fs);
-        s *= sigG;
+        sg *= sigG;
       }
-      s = ((g + 1) & 1) ? sig : 1.0;               // negative aliases |m| = t n - k, t = 1 + g + u G
+      sg = ((g + 1) & 1) ? sig : (C)1;             // negative aliases |m| = t n - k, t = 1 + g + u G
       for (int m = (g + 1) * n - k; m <= lmax; m += G * n) {
-        const V4 eo = *reinterpret_cast<const V4*>(Fp + (size_t)m * 4);
-        const double2 phm = make_double2(s * phk.x, -s * phk.y);
-        const double2 fn = cmul(make_double2((double)eo.x + (double)eo.z, (double)eo.y + (double)eo.w), phm);
-        const double2 fs = cmul(make_double2((double)eo.x - (double)eo.z, (double)eo.y - (double)eo.w), phm);
+        const V4 eo = eo_load(m);
+        const V phm = CT<C>::make(sg * phk.x, -sg * phk.y);
+        const V fn = cmul(CT<C>::make((C)eo.x + (C)eo.z, (C)eo.y + (C)eo.w), phm);
+        const V fs = cmul(CT<C>::make((C)eo.x - (C)eo.z, (C)eo.y - (C)eo.w), phm);
         bn = cadd(bn, cconj(fn));
         bs = cadd(bs, cconj(fs));
-        s *= sigG;
+        sg *= sigG;
       }
       part[2 * p] = bn;
       part[2 * p + 1] = bs;
@@ -489,12 +526,12 @@ __device__ __forceinline__ void fold_synthesis(const PlanDev& P, const T* __rest
     for (int b = 0; b < KB; ++b) {
       const int k = tid + b * NT;
       if (k < n) {
-        double2 bn = make_double2(0.0, 0.0), bs = make_double2(0.0, 0.0);
+        V bn = CT<C>::make(0, 0), bs = CT<C>::make(0, 0);
         for (int g = 0; g < G; ++g) {
           bn = cadd(bn, part[2 * (g * n + k)]);
           bs = cadd(bs, part[2 * (g * n + k) + 1]);
         }
-        bk[b] = CT<C>::make((C)(bn.x - bs.y), (C)(bn.y + bs.x));   // B_N + i B_S
+        bk[b] = CT<C>::make(bn.x - bs.y, bn.y + bs.x);   // B_N + i B_S
       }
     }
     __syncthreads();
@@ -508,28 +545,29 @@ __device__ __forceinline__ void fold_synthesis(const PlanDev& P, const T* __rest
 
 // Analysis unfolding step of one ring pair, after the forward DFT of x_N + i x_S in
 // buf: G(m) = Omega exp(-i m phi0) X[m mod n] of each ring (Hermitian unfold), written
-// as S = G_N + G_S and D = G_N - G_S to Gp[m][4], m = 0..lmax.
+// as S = G_N + G_S and D = G_N - G_S to Gp[m][4], m = 0..lmax, in the transform's
+// arithmetic type C.
 template <class T, class C, int NT>
 __device__ __forceinline__ void unfold_analysis(const PlanDev& P, T* __restrict__ Gp, const RingPair& rp,
-                                                const typename CT<C>::V* buf) {
+                                                const typename CT<C>::V* buf, const RingPhase& rph) {
   using V4 = typename Vec4<T>::type;
   using V = typename CT<C>::V;
   const int n = rp.nphi;
   const int lmax = P.lmax;
   const int tid = threadIdx.x;
-  const double half_omega = 0.5 * P.omega;
-  double2 ph = expipi<double>(-(int64_t)tid * rp.ph_num, n);          // exp(-i m phi0)
-  const double2 step = expipi<double>(-(int64_t)NT * rp.ph_num, n);
+  const C half_omega = (C)(0.5 * P.omega);
+  double2 ph = cconj(rph.ph0);                      // exp(-i m phi0)
+  const double2 step = cconj(rph.step);
+  int k = tid % n;                                  // m mod n
+  const int kstep = NT % n;
   for (int m = tid; m <= lmax; m += NT) {
-    const int k = m % n;
     const int nk = (k == 0) ? 0 : n - k;
-    const V zkv = buf[k], znkv = buf[nk];
-    const double2 zk = make_double2((double)zkv.x, (double)zkv.y);
-    const double2 znk = make_double2((double)znkv.x, (double)znkv.y);
+    const V zk = buf[k], znk = buf[nk];
     // X_N = (Z_k + conj Z_nk) / 2, X_S = (Z_k - conj Z_nk) / (2 i); Omega folded in
-    const double2 xn = make_double2((zk.x + znk.x) * half_omega, (zk.y - znk.y) * half_omega);
-    const double2 xs = make_double2((zk.y + znk.y) * half_omega, -(zk.x - znk.x) * half_omega);
-    const double2 gn = cmul(xn, ph), gs = cmul(xs, ph);
+    const V xn = CT<C>::make((zk.x + znk.x) * half_omega, (zk.y - znk.y) * half_omega);
+    const V xs = CT<C>::make((zk.y + znk.y) * half_omega, -(zk.x - znk.x) * half_omega);
+    const V phc = CT<C>::make((C)ph.x, (C)ph.y);
+    const V gn = cmul(xn, phc), gs = cmul(xs, phc);
     V4 o;
     o.x = (T)(gn.x + gs.x);
     o.y = (T)(gn.y + gs.y);
@@ -537,7 +575,19 @@ __device__ __forceinline__ void unfold_analysis(const PlanDev& P, T* __restrict_
     o.w = (T)(gn.y - gs.y);
     *reinterpret_cast<V4*>(Gp + (size_t)m * 4) = o;
     ph = cmul(ph, step);
+    k += kstep;
+    if (k >= n) k -= n;
   }
+}
+
+// The messenger weight of Eq. (3), w = lambda q / (1 + (lambda - 1) q) with
+// q = tau N^-1 in [0, 1]: an IEEE division in FP64, the hardware reciprocal (1 ulp)
+// in FP32.
+__device__ __forceinline__ double messenger_weight(double lam, double q) {
+  return lam * q / (1.0 + (lam - 1.0) * q);
+}
+__device__ __forceinline__ float messenger_weight(float lam, float q) {
+  return lam * q * __builtin_amdgcn_rcpf(1.0f + (lam - 1.0f) * q);
 }
 
 template <class T, class C, int NT, int MAXB, int KIND>
@@ -582,9 +632,19 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
     for (int e = tid + TWP * NT; e < tw_n; e += NT) twl[e] = twg[twiddle_glob_index(tw_lg, e, P.tw_len)];
   };
 
+  // ---- d and tau N^-1 of the pixels of the update (Eq. 3): thread tid updates
+  // pixel pairs j = tid + u NT; those of its first KU pairs are loaded in one go,
+  // right after the synthesis (so they hold no registers across the transform)
+  constexpr int KU = fold_depth(KIND, MAXB);
+  const bool chi = a.chi2 != nullptr && (mode & PB_SYNTH) && (mode & (PB_UPDATE | PB_CHI2));
+  const bool pix_pass = (mode & (PB_WRITE_MAP | PB_UPDATE)) != 0;
+  const bool upd = pix_pass && ((mode & PB_UPDATE) != 0 || chi);
+  const T* __restrict__ d = static_cast<const T*>(a.d) + mbase;
+  const RingPhase rph = ring_phase<NT>(rp);
+
   // ---- ring values into buf (x = north + i south)
   if (mode & PB_SYNTH) {
-    fold_synthesis<T, C, NT>(P, static_cast<const T*>(a.F) + pbase, rp, buf, lds_raw);
+    fold_synthesis<T, C, NT, KU>(P, static_cast<const T*>(a.F) + pbase, rp, buf, lds_raw, rph);
     stage_twiddles();
     __syncthreads();
     ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, +1, P);
@@ -600,60 +660,65 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
     __syncthreads();
   }
 
-  // ---- map output and the messenger update (Eq. 3)
-  // chi^2 data term of the synthesised iterate (block-uniform)
-  const bool chi = a.chi2 != nullptr && (mode & PB_SYNTH) && (mode & (PB_UPDATE | PB_CHI2));
+  // ---- map output and the messenger update (Eq. 3), in the transform's type C;
+  // the chi^2 data term of the synthesised iterate in FP64
   double chi_acc = 0.0;
-  if (mode & (PB_WRITE_MAP | PB_UPDATE)) {
-    const double lam = a.slots ? a.slots[map].lambda : a.lambda;
-    const T* __restrict__ d = static_cast<const T*>(a.d) + mbase;
+  if (pix_pass) {
+    const C lam = (C)(a.slots ? a.slots[map].lambda : a.lambda);
     T* out = static_cast<T*>(a.map_out) + mbase;
-    // d and tau N^-1 of the next pixel pair are loaded while the current one is updated
-    const bool upd = (mode & PB_UPDATE) != 0 || chi;
-    T qn_nx{}, dn_nx{}, qs_nx{}, ds_nx{};
-    if (upd && tid < n) {
-      qn_nx = q_tab[rp.start_n + tid];
-      dn_nx = d[rp.start_n + tid];
-      if (!equator) {
-        qs_nx = q_tab[rp.start_s + tid];
-        ds_nx = d[rp.start_s + tid];
-      }
-    }
-    for (int j = tid; j < n; j += NT) {
-      const T qn = qn_nx, dn = dn_nx, qs = qs_nx, ds = ds_nx;
-      const int j1 = j + NT;
-      if (upd && j1 < n) {
-        qn_nx = q_tab[rp.start_n + j1];
-        dn_nx = d[rp.start_n + j1];
-        if (!equator) {
-          qs_nx = q_tab[rp.start_s + j1];
-          ds_nx = d[rp.start_s + j1];
-        }
-      }
+    auto pixel_pair = [&](const int j, const T qn_, const T dn_, const T qs_, const T ds_) {
       const V xv = buf[j];
-      double2 x = make_double2((double)xv.x, (double)xv.y);
+      C xn = xv.x, xs = xv.y;
       if (mode & PB_WRITE_MAP) {
-        out[rp.start_n + j] = (T)x.x;
-        if (!equator) out[rp.start_s + j] = (T)x.y;
+        out[rp.start_n + j] = (T)xn;
+        if (!equator) out[rp.start_s + j] = (T)xs;
       }
       if (chi) {
-        const double rn = (double)dn - x.x;
-        chi_acc += (double)qn * rn * rn;
+        const double rn = (double)dn_ - (double)xn;
+        chi_acc += (double)qn_ * rn * rn;
         if (!equator) {
-          const double rs = (double)ds - x.y;
-          chi_acc += (double)qs * rs * rs;
+          const double rs = (double)ds_ - (double)xs;
+          chi_acc += (double)qs_ * rs * rs;
         }
       }
       if (mode & PB_UPDATE) {
-        const double wn = lam * (double)qn / (1.0 + (lam - 1.0) * (double)qn);
-        x.x = x.x + wn * ((double)dn - x.x);
-        if (!equator) {
-          const double ws = lam * (double)qs / (1.0 + (lam - 1.0) * (double)qs);
-          x.y = x.y + ws * ((double)ds - x.y);
+        xn = xn + messenger_weight(lam, (C)qn_) * ((C)dn_ - xn);
+        if (!equator) xs = xs + messenger_weight(lam, (C)qs_) * ((C)ds_ - xs);
+      }
+      if (equator) xs = (C)0;
+      buf[j] = CT<C>::make(xn, xs);
+    };
+    T qn[KU] = {}, dn[KU] = {}, qs[KU] = {}, ds[KU] = {};
+    if (upd) {
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int j = tid + u * NT;
+        if (j < n) {
+          qn[u] = q_tab[rp.start_n + j];
+          dn[u] = d[rp.start_n + j];
+          if (!equator) {
+            qs[u] = q_tab[rp.start_s + j];
+            ds[u] = d[rp.start_s + j];
+          }
         }
       }
-      if (equator) x.y = 0.0;
-      buf[j] = CT<C>::make((C)x.x, (C)x.y);
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int j = tid + u * NT;
+      if (j < n) pixel_pair(j, qn[u], dn[u], qs[u], ds[u]);
+    }
+    for (int j = tid + KU * NT; j < n; j += NT) {
+      T q0{}, d0{}, q1{}, d1{};
+      if (upd) {
+        q0 = q_tab[rp.start_n + j];
+        d0 = d[rp.start_n + j];
+        if (!equator) {
+          q1 = q_tab[rp.start_s + j];
+          d1 = d[rp.start_s + j];
+        }
+      }
+      pixel_pair(j, q0, d0, q1, d1);
     }
     __syncthreads();
   }
@@ -662,7 +727,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   // ---- analysis: forward DFT and unfold into S/D per m
   if (mode & PB_ANALYSIS) {
     ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, -1, P);
-    unfold_analysis<T, C, NT>(P, static_cast<T*>(a.G) + pbase, rp, buf);
+    unfold_analysis<T, C, NT>(P, static_cast<T*>(a.G) + pbase, rp, buf, rph);
   }
 }
 
@@ -717,11 +782,12 @@ __device__ __forceinline__ void phase_b_pol_body(const PlanDev& P, const PolRing
     for (int e = tid; e < tw_n; e += NT) twl[e] = twg[twiddle_glob_index(tw_lg, e, P.tw_len)];
   };
 
+  const RingPhase rph = ring_phase<NT>(rp);
   V sx[3][PPT];
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     if (mode & PB_SYNTH) {
-      fold_synthesis<double, C, NT>(P, a.F + pbase(f), rp, buf, lds_raw);
+      fold_synthesis<double, C, NT, fold_depth(KIND, MAXB)>(P, a.F + pbase(f), rp, buf, lds_raw, rph);
       stage_twiddles();
       __syncthreads();
       ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, +1, P);
@@ -795,7 +861,7 @@ __device__ __forceinline__ void phase_b_pol_body(const PlanDev& P, const PolRing
       }
       __syncthreads();
       ring_dft<C, NT, MAXB, KIND>(buf, twl, rp, -1, P);
-      unfold_analysis<double, C, NT>(P, a.G + pbase(f), rp, buf);
+      unfold_analysis<double, C, NT>(P, a.G + pbase(f), rp, buf, rph);
       __syncthreads();
     }
   }
