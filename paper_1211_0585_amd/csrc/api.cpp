@@ -421,6 +421,7 @@ int plan_alloc(wf_plan_s* p) {
   D.A = g.A;
   D.C = g.C;
   D.row_off = g.row_off;
+  D.row_m = g.row_m;
   D.norm_m = g.norm;
   D.n_active = g.nact;
   D.nblk = g.nblk_ana;
@@ -1125,8 +1126,8 @@ extern "C" int wf_autotune(wf_plan_t p, int32_t nmaps, void* hip_stream, int32_t
 // ---------------------------------------------------------------- task groups
 namespace mwf {
 
-// Block offsets of the five phases of a task list (ring pairs of the 512-thread
-// class, ring pairs of the one-wave class, analysis, coefficients, synthesis)
+// Block offsets of the five phases of a task list (ring pairs of the two classes of
+// larger workgroups, ring pairs of the one-wave class, analysis, coefficients, synthesis)
 // under a tuning: offs holds 5 x (ntasks + 1) entries. Tasks whose gemm flag is 0
 // get no blocks in the three Legendre phases. lds receives the dynamic LDS bytes
 // of the two ring launches.

@@ -18,7 +18,8 @@ namespace {
 
 constexpr long double PI_L = 3.141592653589793238462643383279502884L;
 // Ring pairs whose transform (n, or the Bluestein length M) has at most this many
-// points run one wave per pair when batched; longer ones a 512-thread workgroup.
+// points run one wave per pair when batched; longer ones a larger workgroup (512
+// threads for Bluestein rings, 256 for power-of-two rings).
 constexpr int SMALL_FFT = 1024;
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
@@ -138,6 +139,7 @@ int build_geometry(Geometry& g) {
 
   // ---- recurrence tables mu_l = (A z) mu_{l-1} - mu_{l-2}, lambda = C mu; padded rows
   std::vector<int64_t> row_off(lmax + 1);
+  std::vector<int32_t> row_m;             // m of every padded row
   std::vector<double> A, C, norm(lmax + 1);
   {
     int64_t off = 0;
@@ -146,6 +148,9 @@ int build_geometry(Geometry& g) {
       off += (lmax - m + 1) + ROW_PAD;
     }
     g.rows_total = off;
+    row_m.resize(off);
+    for (int m = 0; m <= lmax; ++m)
+      for (int64_t r = row_off[m]; r < (m < lmax ? row_off[m + 1] : off); ++r) row_m[r] = m;
     A.assign(off, 0.0);
     C.assign(off, 0.0);
     long double nm = 1.0L / sqrtl(4.0L * PI_L);
@@ -179,6 +184,7 @@ int build_geometry(Geometry& g) {
   if ((rc = M.upload(&g.A, A))) return rc;
   if ((rc = M.upload(&g.C, C))) return rc;
   if ((rc = M.upload(&g.row_off, row_off))) return rc;
+  if ((rc = M.upload(&g.row_m, row_m))) return rc;
   if ((rc = M.upload(&g.norm, norm))) return rc;
   if ((rc = M.upload(&g.tw, tw))) return rc;
   if ((rc = M.upload(&g.chirp, chirp))) return rc;
@@ -234,6 +240,7 @@ int build_geometry(Geometry& g) {
   D.A = g.A;
   D.C = g.C;
   D.row_off = g.row_off;
+  D.row_m = g.row_m;
   D.norm_m = g.norm;
   std::vector<uint16_t> wake((size_t)(lmax + 1) * g.npairs);
   {

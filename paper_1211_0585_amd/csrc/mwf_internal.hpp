@@ -125,6 +125,7 @@ struct PlanDev {
   const float2* chirp32;
   const float2* bluestein32;
   int64_t rows_total;        // length of the padded per-m row layout of A / C / bcoef
+  const int32_t* row_m;      // [rows_total] m of each padded row
 };
 
 __host__ __device__ inline int64_t alm_index(int lmax, int l, int m) {

@@ -625,12 +625,7 @@ __device__ __forceinline__ void coeff_elem(const PlanDev& P, const MfmaArgs& a, 
   const int64_t r = e / nm;
   const int map = (int)(e - r * nm);
   const int lmax = P.lmax;
-  // row_off[m] = m (2 (lmax + ROW_PAD) + 3 - m) / 2: invert, then settle on the table
-  const double B = 2.0 * (lmax + ROW_PAD) + 3.0;
-  int m = (int)(0.5 * (B - sqrt(fmax(B * B - 8.0 * (double)r, 0.0))));
-  m = max(0, min(m, lmax));
-  while (m < lmax && P.row_off[m + 1] <= r) ++m;
-  while (m > 0 && P.row_off[m] > r) --m;
+  const int m = P.row_m[r];
   const int64_t roff = P.row_off[m];
   const int i = (int)(r - roff);
   const int nl = lmax - m + 1;

@@ -26,7 +26,7 @@
 // M >= 2 n - 1, multiply by the plan-time filter spectrum, inverse FFT, chirp.
 // The FFT arithmetic type C is double for FP64 plans and float for plans that
 // store maps and ring coefficients in float. Ring pairs are launched in classes:
-// Bluestein rings and power-of-two rings separately (512 threads each, LDS sized
+// Bluestein rings and power-of-two rings separately (512 and 256 threads, LDS sized
 // to the class: the Bluestein length is about twice the ring's), and, from 4 maps
 // on, transforms of at most 1024 points one wave per ring pair, so short polar
 // rings do not leave most of a large workgroup idle. Each workgroup stages the
@@ -395,8 +395,8 @@ __device__ __forceinline__ RingPhase ring_phase(const RingPair& rp) {
   return r;
 }
 
-// Bins of a ring pair a thread folds with its loads issued up front: the largest
-// number of bins k = tid + u NT a launch class has, at most four.
+// Bins (and pixel pairs) of a ring pair a thread handles with their loads issued
+// together: the largest number k = tid + u NT a launch class has, at most four.
 constexpr int fold_depth(int kind, int maxb) {
   const int u = (kind == 1 ? 2 : 4) * maxb;
   return u < 4 ? u : 4;
@@ -405,8 +405,8 @@ constexpr int fold_depth(int kind, int maxb) {
 // Synthesis loading step of one ring pair: the bins B[k] = sum over m = k (mod n) of
 // F(m) exp(i m phi0) (F(-m) = conj F(m)) of the north and south rings, from the E/O
 // coefficients Fp[m][4] of this map and pair, into buf as B_N + i B_S (k < n), in the
-// transform's arithmetic type C. Long rings: thread tid folds bins tid + u NT; the
-// first alias of its first KU bins is loaded before any is folded. Short rings use
+// transform's arithmetic type C. Long rings: thread tid folds bins tid + u NT, KU at a
+// time, the first alias of each of the KU loaded before any of them is folded. Short rings use
 // lds_raw for partial sums (consumed before the function returns). Every thread of
 // the workgroup calls it.
 template <class T, class C, int NT, int KU>
@@ -457,26 +457,21 @@ __device__ __forceinline__ void fold_synthesis(const PlanDev& P, const T* __rest
       }
       return CT<C>::make(bn.x - bs.y, bn.y + bs.x);   // B_N + i B_S
     };
-    V4 first[KU];
-#pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const int k = tid + u * NT;
-      const int m1 = k <= lmax ? k : n - k;
-      if (k < n && m1 <= lmax) first[u] = eo_load(m1);
-    }
     double2 ph = rph.ph0;
+    for (int k0 = tid; k0 < n; k0 += KU * NT) {
+      V4 first[KU];
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const int k = tid + u * NT;
-      if (k < n) buf[k] = fold_bin(k, first[u], ph);
-      ph = cmul(ph, rph.step);
-    }
-    for (int k = tid + KU * NT; k < n; k += NT) {
-      const int m1 = k <= lmax ? k : n - k;
-      V4 f1{};
-      if (m1 <= lmax) f1 = eo_load(m1);
-      buf[k] = fold_bin(k, f1, ph);
-      ph = cmul(ph, rph.step);
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + u * NT;
+        const int m1 = k <= lmax ? k : n - k;
+        if (k < n && m1 <= lmax) first[u] = eo_load(m1);
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const int k = k0 + u * NT;
+        if (k < n) buf[k] = fold_bin(k, first[u], ph);
+        ph = cmul(ph, rph.step);
+      }
     }
   } else {
     // short rings carry many aliases per bin: G partial sums per bin, each over
@@ -633,8 +628,8 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   };
 
   // ---- d and tau N^-1 of the pixels of the update (Eq. 3): thread tid updates
-  // pixel pairs j = tid + u NT; those of its first KU pairs are loaded in one go,
-  // right after the synthesis (so they hold no registers across the transform)
+  // pixel pairs j = tid + u NT, KU at a time, their loads issued together right
+  // after the synthesis (so they hold no registers across the transform)
   constexpr int KU = fold_depth(KIND, MAXB);
   const bool chi = a.chi2 != nullptr && (mode & PB_SYNTH) && (mode & (PB_UPDATE | PB_CHI2));
   const bool pix_pass = (mode & (PB_WRITE_MAP | PB_UPDATE)) != 0;
@@ -688,37 +683,27 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
       if (equator) xs = (C)0;
       buf[j] = CT<C>::make(xn, xs);
     };
-    T qn[KU] = {}, dn[KU] = {}, qs[KU] = {}, ds[KU] = {};
-    if (upd) {
+    for (int j0 = tid; j0 < n; j0 += KU * NT) {
+      T qn[KU] = {}, dn[KU] = {}, qs[KU] = {}, ds[KU] = {};
+      if (upd) {
 #pragma unroll
-      for (int u = 0; u < KU; ++u) {
-        const int j = tid + u * NT;
-        if (j < n) {
-          qn[u] = q_tab[rp.start_n + j];
-          dn[u] = d[rp.start_n + j];
-          if (!equator) {
-            qs[u] = q_tab[rp.start_s + j];
-            ds[u] = d[rp.start_s + j];
+        for (int u = 0; u < KU; ++u) {
+          const int j = j0 + u * NT;
+          if (j < n) {
+            qn[u] = q_tab[rp.start_n + j];
+            dn[u] = d[rp.start_n + j];
+            if (!equator) {
+              qs[u] = q_tab[rp.start_s + j];
+              ds[u] = d[rp.start_s + j];
+            }
           }
         }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < KU; ++u) {
-      const int j = tid + u * NT;
-      if (j < n) pixel_pair(j, qn[u], dn[u], qs[u], ds[u]);
-    }
-    for (int j = tid + KU * NT; j < n; j += NT) {
-      T q0{}, d0{}, q1{}, d1{};
-      if (upd) {
-        q0 = q_tab[rp.start_n + j];
-        d0 = d[rp.start_n + j];
-        if (!equator) {
-          q1 = q_tab[rp.start_s + j];
-          d1 = d[rp.start_s + j];
-        }
+      for (int u = 0; u < KU; ++u) {
+        const int j = j0 + u * NT;
+        if (j < n) pixel_pair(j, qn[u], dn[u], qs[u], ds[u]);
       }
-      pixel_pair(j, q0, d0, q1, d1);
     }
     __syncthreads();
   }
@@ -902,6 +887,12 @@ __global__ void __launch_bounds__(NT) group_phase_b_kernel(GroupArgs g, int buf_
                                                         (int)(local % t.nmaps), buf_elems);
 }
 
+// Threads of a ring workgroup per launch class: Bluestein rings 512, power-of-two
+// rings 256 (the longest, 4 nside points, then take eight points a thread, which
+// keeps every lane busy in the radix-8 passes and lets four workgroups share a CU),
+// the one-wave class 64.
+constexpr int ring_threads(int cls) { return cls == 0 ? 512 : (cls == 1 ? 256 : 64); }
+
 // Radix-4 butterflies per thread and pass for a transform of fft_len points.
 int maxb_for(int fft_len, int nt) {
   const int b = (fft_len + 4 * nt - 1) / (4 * nt);
@@ -931,7 +922,7 @@ hipError_t launch_class_b(const PlanDev& P, const PhaseBArgs& a, const RingClass
 template <class T, class C, int CLS>
 hipError_t launch_class(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
   if (rc.count == 0) return hipSuccess;
-  constexpr int NT = CLS < 2 ? 512 : 64;
+  constexpr int NT = ring_threads(CLS);
   switch (maxb_for(rc.fft_len, NT)) {
     case 1: return launch_class_b<T, C, NT, 1, CLS>(P, a, rc, s);
     case 2: return launch_class_b<T, C, NT, 2, CLS>(P, a, rc, s);
@@ -995,9 +986,9 @@ hipError_t launch_pol_class(const PlanDev& P, const PolRingArgs& a, const RingCl
 hipError_t launch_group_phase_b(const GroupLaunch& g, int cls, int fft_len, hipStream_t s) {
   if (g.nblocks == 0) return hipSuccess;
   switch (cls) {
-    case 0: return group_class<512, 0>(g, fft_len, s);
-    case 1: return group_class<512, 1>(g, fft_len, s);
-    default: return group_class<64, 2>(g, fft_len, s);
+    case 0: return group_class<ring_threads(0), 0>(g, fft_len, s);
+    case 1: return group_class<ring_threads(1), 1>(g, fft_len, s);
+    default: return group_class<ring_threads(2), 2>(g, fft_len, s);
   }
 }
 

@@ -360,6 +360,7 @@ int wf_pol_plan(wf_pol_plan_t* out, int32_t nside, int32_t lmax, const double* c
   D.A = g.A;
   D.C = g.C;
   D.row_off = g.row_off;
+  D.row_m = g.row_m;
   D.norm_m = g.norm;
   D.n_active = g.nact;
   D.nblk = g.nblk_ana;

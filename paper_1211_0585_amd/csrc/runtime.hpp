@@ -74,6 +74,7 @@ struct Geometry {
   double* A = nullptr;
   double* C = nullptr;
   int64_t* row_off = nullptr;
+  int32_t* row_m = nullptr;
   double* norm = nullptr;
   int32_t* nact = nullptr;
   int32_t* nblk_ana = nullptr;
