@@ -51,6 +51,15 @@ def parse():
                     help="length of the Poisson request stream (0 skips serving)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="requests per second")
     ap.add_argument("--serve-nsides", default="64,128,256,512,1024")
+    ap.add_argument("--serve-signal", choices=("request", "pool"), default="request",
+                    help="signal of each request: its own seed, synthesised on the GPU (request), or one "
+                         "of 4 pre-drawn maps per nside (pool)")
+    ap.add_argument("--serve-budget-gb", type=float, default=128.0,
+                    help="HBM budget of the server's admission (GiB)")
+    ap.add_argument("--serve-builders", type=int, default=3,
+                    help="host threads that build the requests of the stream ahead of their arrival")
+    ap.add_argument("--serve-check", type=int, default=8,
+                    help="sampled requests run again alone after the stream and compared with the mix")
     ap.add_argument("--adaptive-repeats", type=int, default=3,
                     help="timed runs of the adaptive solve (Sect. 3 cooling with band-limited "
                          "transforms) on the plain workload; 0 skips it")
@@ -564,86 +573,156 @@ def run_serving(args, np, torch, mwf, synth, dev):
     """Poisson request stream into the continuous-batching server. Each request:
     nside uniform over the configured set, lmax = 2 nside, its own galactic cut
     U[5, 25] deg, noise amplitude sigma0 ~ U[0.5, 5] mK with N_obs of the satellite
-    recipe scaled by (512/nside)^2, its own noise draw, FP32, 30 cooling + 50 final
-    sweeps. Signal maps come from a pool of 4 draws per nside and unit noise from a
-    pool of 4 per nside (scaled per request), drawn before the clock starts so the
-    host keeps pace with the arrival rate. Latency = scheduled arrival -> s_WF in
-    host memory."""
+    recipe scaled by (512/nside)^2, its own signal seed, FP32, 30 cooling + 50 final
+    sweeps. A producer thread builds the requests ahead of their arrival: the signal
+    alm drawn on the host from the request's seed and synthesised on the GPU (an FP32
+    alm2map plan per nside, on a stream of its own), unit noise from a pool of 4 draws
+    per nside scaled by the request's sigma0 (--serve-signal pool: signal maps from a
+    pool of 4 draws per nside as well). A collector thread takes the results as they
+    finish. Latency = scheduled arrival -> s_WF in host memory (the server's own part,
+    submit -> s_WF, reported beside it). Sampled requests are run again alone afterwards
+    and compared with their result in the mix."""
     import queue
     import threading
     nsides = [int(x) for x in args.serve_nsides.split(",")]
     rate, T = args.serve_rate, args.serve_seconds
+    per_request = args.serve_signal == "request"
     rs = np.random.default_rng(2024)
     pools = {}
+    syn_stream = torch.cuda.Stream(device=dev)
     for nside in nsides:
         lmax = 2 * nside
         th, ph = mwf.pixel_angles(nside)
         model = synth.satellite_model(th, ph, lmax, nobs_scale=(512.0 / nside) ** 2, ndisc=0)
         nobs = (2200.0 ** 2) / model["sigma2"]            # N_obs of the recipe
-        with mwf.Plan(nside, lmax, model["cl"], np.ones(th.size), dtype=mwf.WF_F32, max_batch=4) as p:
-            alms = np.stack([synth.draw(model, s)["signal_alm"] for s in range(4)]).astype(np.complex64)
-            sig = p.alm2map(torch.from_numpy(alms).to(dev)).double().cpu().numpy()
+        plan = mwf.Plan(nside, lmax, model["cl"], np.ones(th.size), dtype=mwf.WF_F32, max_batch=4)
+        alms = np.stack([synth.draw(model, s)["signal_alm"] for s in range(4)]).astype(np.complex64)
+        sig = plan.alm2map(torch.from_numpy(alms).to(dev)).double().cpu().numpy()
         unit = np.stack([synth.rng(100 + s, 1).standard_normal(th.size) for s in range(4)])
-        pools[nside] = dict(theta=th, cl=model["cl"], nobs=nobs, sig=sig, unit=unit,
+        pools[nside] = dict(theta=th, cl=model["cl"], nobs=nobs, sig=sig, unit=unit, plan=plan,
                             sched=model["schedule"], lmax=lmax)
         log(f"[bench] serving: pools ready for Nside {nside}")
     arrivals = np.cumsum(rs.exponential(1.0 / rate, int(2 * rate * T) + 64))
     arrivals = arrivals[arrivals < T]
     specs = [dict(nside=int(rs.choice(nsides)), cut=float(rs.uniform(5, 25)), s0=float(rs.uniform(0.5, 5.0)),
-                  sig=int(rs.integers(4)), noi=int(rs.integers(4))) for _ in arrivals]
+                  sig=int(rs.integers(4)), seed=10000 + i, noi=int(rs.integers(4))) for i in range(arrivals.size)]
+
+    gpu_lock = threading.Lock()     # one synthesis at a time per plan (its work buffers)
+
+    def signal(sp):
+        P = pools[sp["nside"]]
+        if not per_request:
+            return P["sig"][sp["sig"]]
+        alm = synth.random_alm(P["cl"], P["lmax"], sp["seed"]).astype(np.complex64)
+        with gpu_lock, torch.cuda.stream(syn_stream):
+            a = torch.from_numpy(alm).to(dev)
+            m = P["plan"].alm2map(a, stream=syn_stream)
+            out = m.cpu().numpy()
+        return out
 
     def build(sp):
         P = pools[sp["nside"]]
         mask = synth.galactic_cut(P["theta"], sp["cut"])
         sigma2 = (sp["s0"] * 1000.0) ** 2 / P["nobs"]
         ninv = np.where(mask, 0.0, 1.0 / sigma2)
-        d = P["sig"][sp["sig"]] + np.sqrt(sigma2) * P["unit"][sp["noi"]]
+        d = signal(sp) + np.sqrt(sigma2) * P["unit"][sp["noi"]]
         return ninv, d
 
-    srv = mwf.Server(hbm_budget=128 << 30, max_slots=64)
+    srv = mwf.Server(hbm_budget=int(args.serve_budget_gb * (1 << 30)), max_slots=64)
     # one short request per shape first, so lanes and tables exist before the clock
     for nside in nsides:
         P = pools[nside]
-        ninv, d = build(dict(nside=nside, cut=10.0, s0=1.0, sig=0, noi=0))
+        ninv, d = build(dict(nside=nside, cut=10.0, s0=1.0, sig=0, seed=0, noi=0))
         srv.wait(srv.submit(nside, P["lmax"], P["cl"], ninv, d, P["sched"][:2]), timeout=300)
-    log(f"[bench] serving: {len(specs)} requests over {T:.0f} s at {rate:.0f}/s")
+    nsamp = min(args.serve_check, len(specs))
+    sample = set(np.linspace(0, len(specs) - 1, nsamp).astype(int).tolist()) if nsamp else set()
+    log(f"[bench] serving: {len(specs)} requests over {T:.0f} s at {rate:.0f}/s, "
+        f"{'per-request' if per_request else 'pooled'} signal draws, HBM budget {args.serve_budget_gb:g} GB")
     q = queue.Queue(maxsize=16)
 
     def producer():
-        for sp in specs:
-            q.put((sp, build(sp)))
+        # requests built by a few threads (the host work of one Nside-1024 request is
+        # ~0.1 s), handed over in arrival order, at most 16 ahead
+        import collections
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=args.serve_builders) as ex:
+            window = collections.deque()
+            for sp in specs:
+                window.append((sp, ex.submit(build, sp)))
+                if len(window) >= 16:
+                    sp0, f = window.popleft()
+                    q.put((sp0, f.result()))
+            while window:
+                sp0, f = window.popleft()
+                q.put((sp0, f.result()))
     th_prod = threading.Thread(target=producer, daemon=True)
     th_prod.start()
-    tickets = []
+    tq = queue.Queue()
+    lat = np.zeros(len(specs))
+    lat_srv = np.zeros(len(specs))
+    kept = {}
+    lags = np.zeros(len(specs))
+    done = [0]
+
+    def collector():
+        for _ in range(len(specs)):
+            i, tk = tq.get()
+            s_wf, l = srv.wait(tk, timeout=900)
+            lat[i] = l + lags[i]
+            lat_srv[i] = l
+            if i in kept:
+                kept[i]["mix"] = s_wf
+            done[0] += 1
+    th_col = threading.Thread(target=collector, daemon=True)
+    th_col.start()
     t_start = time.perf_counter()
-    lags = []
+    next_note = 30.0
     for i, t_arr in enumerate(arrivals):
         sp, (ninv, d) = q.get()
         now = time.perf_counter() - t_start
         if now < t_arr:
             time.sleep(t_arr - now)
         P = pools[sp["nside"]]
+        if i in sample:
+            kept[i] = dict(nside=sp["nside"], ninv=ninv, d=d)
         tk = srv.submit(sp["nside"], P["lmax"], P["cl"], ninv, d, P["sched"])
-        lags.append(max(0.0, time.perf_counter() - t_start - t_arr))
-        tickets.append(tk)
-    lat, done_at, sweeps = [], [], 0
-    for i, tk in enumerate(tickets):
-        s_wf, l = srv.wait(tk, timeout=600)
-        lat.append(l + lags[i])
-        sweeps += len(pools[specs[i]["nside"]]["sched"])
+        lags[i] = max(0.0, time.perf_counter() - t_start - t_arr)
+        tq.put((i, tk))
+        if t_arr >= next_note:
+            log(f"[bench] serving: t = {t_arr:.0f} s, {i + 1} submitted, {done[0]} done")
+            next_note += 30.0
+    th_col.join()
     t_end = time.perf_counter() - t_start
     st = srv.stats()
+    sweeps = sum(len(pools[sp["nside"]]["sched"]) for sp in specs)
+    # the sampled requests alone, on the idle server, against their result in the mix
+    diffs, identical = [], 0
+    for i, k in sorted(kept.items()):
+        P = pools[k["nside"]]
+        alone, _ = srv.wait(srv.submit(k["nside"], P["lmax"], P["cl"], k["ninv"], k["d"], P["sched"]), timeout=300)
+        diffs.append(float(np.linalg.norm(alone - k["mix"]) / np.linalg.norm(alone)))
+        identical += int(np.array_equal(alone, k["mix"]))
     srv.close()
-    lat = np.array(lat)
-    res = {"requests": len(tickets), "offered_rate": rate, "seconds": T, "dtype": "f32",
+    for P in pools.values():
+        P["plan"].close()
+    res = {"requests": len(specs), "offered_rate": rate, "seconds": T, "dtype": "f32",
            "nsides": nsides, "sweeps_per_request": int(len(pools[nsides[0]]["sched"])),
-           "throughput_req_per_s": len(tickets) / t_end, "map_iters_per_s": sweeps / t_end,
+           "signal": "per-request seed, synthesised on the GPU" if per_request else "pool of 4 per nside",
+           "hbm_budget_gb": args.serve_budget_gb,
+           "throughput_req_per_s": len(specs) / t_end, "map_iters_per_s": sweeps / t_end,
            "latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3), "p99": float(np.percentile(lat, 99) * 1e3),
                           "max": float(lat.max() * 1e3)},
-           "submit_lag_ms_max": float(max(lags) * 1e3) if lags else 0.0,
-           "peak_slots": st["peak_slots"], "steps": st["steps"], "peak_hbm_gb": st["peak_bytes"] / 1e9}
+           "server_latency_ms": {"p50": float(np.percentile(lat_srv, 50) * 1e3),
+                                 "p99": float(np.percentile(lat_srv, 99) * 1e3), "max": float(lat_srv.max() * 1e3)},
+           "submit_lag_ms": {"p50": float(np.percentile(lags, 50) * 1e3), "p99": float(np.percentile(lags, 99) * 1e3),
+                             "max": float(lags.max() * 1e3)},
+           "peak_slots": st["peak_slots"], "steps": st["steps"], "peak_hbm_gb": st["peak_bytes"] / 1e9,
+           "alone_vs_mix": {"sampled": len(diffs), "max_rel_l2": max(diffs) if diffs else None,
+                            "bitwise_identical": identical}}
     log(f"[bench] serving: {res['throughput_req_per_s']:.1f} req/s, p50 {res['latency_ms']['p50']:.0f} ms, "
-        f"p99 {res['latency_ms']['p99']:.0f} ms, peak slots {st['peak_slots']}")
+        f"p99 {res['latency_ms']['p99']:.0f} ms, peak slots {st['peak_slots']}, peak HBM "
+        f"{res['peak_hbm_gb']:.1f} GB; alone vs mix: {identical}/{len(diffs)} identical, "
+        f"max rel diff {res['alone_vs_mix']['max_rel_l2']}")
     return res
 
 
