@@ -738,13 +738,14 @@ def run_cpu_baseline(args, np, d_host, case, sched, nside, lmax):
     threads = _blas_threads()
     log(f"[bench] oracle: {args.cpu_sweeps} sweep(s) on the host ({threads} threads)")
 
-    def sweeps(n):
+    def sweeps(n, label=""):
         s0 = np.zeros(d_host.size)
         ts = []
         for k in range(n):
             a = time.perf_counter()
             s0, _ = messenger.sweep(s0, d_host, ninv, case["cl"], float(sched[k]), tau, nside, lmax)
             ts.append(time.perf_counter() - a)
+            log(f"[bench] oracle{label}: sweep {k + 1}/{n} {ts[-1]:.1f} s")
         return ts
 
     ts = sweeps(args.cpu_sweeps)
@@ -763,9 +764,9 @@ def run_cpu_baseline(args, np, d_host, case, sched, nside, lmax):
                                      "seconds": t_small, "iters_per_s": len(small["schedule"]) / t_small}}
     if args.cpu_full:
         from threadpoolctl import threadpool_limits
-        ts3 = sweeps(3)
+        ts3 = sweeps(3, f" ({threads} threads)")
         with threadpool_limits(limits=1):
-            t1 = sweeps(1)
+            t1 = sweeps(1, " (1 thread)")
         cpu["full"] = {"all_threads": {"threads": threads, "sweeps": 3, "mean_s": float(np.mean(ts3)),
                                        "std_s": float(np.std(ts3)), "iters_per_s": 3 / sum(ts3)},
                        "one_thread": {"sweeps": 1, "seconds": t1[0], "iters_per_s": 1 / t1[0]}}

@@ -272,11 +272,19 @@ __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
         alm = a.alm_in[(size_t)map * P.nalm + row + i];
         if (m == 0) alm.y = 0.0;
       } else {
+        // the blocks' partial sums, KB at a time with their loads issued together
+        constexpr int KB = 4;
+        const double2* pb = a.partial + (size_t)map * P.nblk_max * P.nalm + row + i;
         double sr = 0.0, si = 0.0;
-        for (int k = 0; k < nb; ++k) {
-          const double2 p = a.partial[((size_t)map * P.nblk_max + k) * P.nalm + row + i];
-          sr += p.x;
-          si += p.y;
+        for (int k0 = 0; k0 < nb; k0 += KB) {
+          double2 p[KB];
+#pragma unroll
+          for (int u = 0; u < KB; ++u) p[u] = k0 + u < nb ? pb[(size_t)(k0 + u) * P.nalm] : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int u = 0; u < KB; ++u) {
+            sr += p[u].x;
+            si += p[u].y;
+          }
         }
         // the ring phase already applied Omega to G
         alm = make_double2(sr * Crow[i], si * Crow[i]);

@@ -641,10 +641,21 @@ __device__ __forceinline__ void coeff_elem(const PlanDev& P, const MfmaArgs& a, 
     } else {
       const int nb = (P.n_active[m] + a.ana_rb - 1) / a.ana_rb;
       sr = si = 0.0;
-      for (int k = 0; k < nb; ++k) {
-        const float2 pk = *reinterpret_cast<const float2*>(a.partial + (((size_t)k * P.nalm + row + i) * nm + map) * 2);
-        sr += pk.x;
-        si += pk.y;
+      // the blocks' partial sums, KB at a time with their loads issued together
+      constexpr int KB = 4;
+      const float* pbase = a.partial + ((size_t)(row + i) * nm + map) * 2;
+      const size_t kstride = (size_t)P.nalm * nm * 2;
+      for (int k0 = 0; k0 < nb; k0 += KB) {
+        float2 pk[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+          pk[u] = k0 + u < nb ? *reinterpret_cast<const float2*>(pbase + (size_t)(k0 + u) * kstride)
+                              : make_float2(0.0f, 0.0f);
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+          sr += pk[u].x;
+          si += pk[u].y;
+        }
       }
       sr *= c;
       si *= c;
