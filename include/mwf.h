@@ -317,7 +317,9 @@ int wf_pixel_angles(int32_t nside, double* theta, double* phi);
 
 /*
  * wf_autotune -- time every launch shape of the matrix-core Legendre kernels
- * (analysis: 1 or 2 column tiles per workgroup; synthesis: 1, 2 or 4 column tiles
+ * (analysis: 1, 2, 4 or, for WF_F32, 8 column tiles per workgroup -- from 4 tiles on,
+ * the Legendre values of a 256-pair block are generated once for 64 or 128 columns;
+ * synthesis: 1, 2 or 4 column tiles
  * per wave, or 8 for WF_F32, or the wide kernel: 256 ring pairs and 64 columns per
  * workgroup of 32 x 32 tiles) on this plan at nmaps maps, keep the fastest in the plan,
  * record it in the process-wide cache (and in opts.tune_cache if given: lines

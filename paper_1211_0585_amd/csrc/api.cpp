@@ -57,7 +57,7 @@ void load_tuning_file(const char* cache_path) {
     std::istringstream ss(line);
     std::string key;
     Tuning t;
-    if (ss >> key >> t.ana_ct >> t.syn_nct && (t.ana_ct == 1 || t.ana_ct == 2) &&
+    if (ss >> key >> t.ana_ct >> t.syn_nct && (t.ana_ct == 1 || t.ana_ct == 2 || t.ana_ct == 4 || t.ana_ct == 8) &&
         (t.syn_nct == 1 || t.syn_nct == 2 || t.syn_nct == 4 || t.syn_nct == 8)) {
       int wide = 0;
       if (ss >> wide) t.syn_wide = (wide == 1 || wide == 2) ? wide : 0;
@@ -287,7 +287,7 @@ MfmaArgs mfma_args(wf_plan_s* p, int mode, int nmaps, double lam, const void* al
   a.mode = mode;
   a.nmaps = nmaps;
   a.lambda = lam;
-  a.ana_rb = 128 * p->tune.ana_ct;
+  a.ana_rb = ana_block(p->tune.ana_ct);
   a.G = static_cast<const float*>(p->G);
   a.F = static_cast<float*>(p->F);
   a.partial = p->partial32;
@@ -300,7 +300,7 @@ MfmaArgs mfma_args(wf_plan_s* p, int mode, int nmaps, double lam, const void* al
 int launch_mfma_ana(wf_plan_s* p, const Tuning& t, int nmaps, hipStream_t s) {
   const Geometry& g = *p->geo;
   MfmaArgs a = mfma_args(p, 0, nmaps, 1.0, nullptr, nullptr);
-  a.ana_rb = 128 * t.ana_ct;
+  a.ana_rb = ana_block(t.ana_ct);
   MWF_HIP(launch_mfma_analysis(p->dev, t.ana_ct == 1 ? g.items_a128 : g.items_a256,
                                t.ana_ct == 1 ? g.n_a128 : g.n_a256, p->dtype, t.ana_ct, a, s));
   return WF_OK;
@@ -1075,7 +1075,8 @@ extern "C" int wf_autotune(wf_plan_t p, int32_t nmaps, void* hip_stream, int32_t
   const Geometry& g = *p->geo;
   Tuning best = p->tune;
   float tbest = 1e30f;
-  for (int ct : {1, 2}) {
+  for (int ct : {1, 2, 4, 8}) {
+    if (!ana_ct_valid(ct, p->dtype == WF_F32)) continue;
     Tuning t = p->tune;
     t.ana_ct = ct;
     float ms;
@@ -1216,10 +1217,10 @@ int run_group_step(const TaskDev* tasks, const int64_t* offs, const int64_t* nbl
   TIMED(2, {
     g.offs = offs + (a0 + 1) * stride;
     g.nblocks = nblocks[a0 + 1];
-    MWF_HIP(launch_group_coeff(g, 128 * tune.ana_ct, s));
+    MWF_HIP(launch_group_coeff(g, ana_block(tune.ana_ct), s));
     g.offs = offs + (a0 + 2) * stride;
     g.nblocks = nblocks[a0 + 2];
-    MWF_HIP(launch_group_synthesis(g, dtype, tune.syn_nct, 128 * tune.ana_ct, s));
+    MWF_HIP(launch_group_synthesis(g, dtype, tune.syn_nct, ana_block(tune.ana_ct), s));
   });
   return WF_OK;
 }

@@ -298,6 +298,13 @@ hipError_t launch_legendre_synthesis_f64(const PlanDev& P, const WorkItem* items
 // Threads per workgroup of the matrix-core coefficient kernel (one element each).
 constexpr int COEFF_THREADS = 256;
 
+// Ring pairs per block of the matrix-core analysis with ct column tiles per
+// workgroup (2 ct waves): 128 for one tile, 256 from two on (from four tiles on,
+// the first four waves generate the Legendre values that all waves contract).
+constexpr int ana_block(int ct) { return ct == 1 ? 128 : 256; }
+// Column tiles a matrix-core analysis workgroup may take: 1, 2, 4, 8 (8: FP32 only).
+constexpr bool ana_ct_valid(int ct, bool fp32) { return ct == 1 || ct == 2 || ct == 4 || (ct == 8 && fp32); }
+
 struct MfmaArgs {
   int32_t mode;             // SynthMode of the coefficient step
   int32_t nmaps;

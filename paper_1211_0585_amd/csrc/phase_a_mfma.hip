@@ -150,14 +150,18 @@ struct Products<3> {
 };
 
 // ------------------------------------------------------------------ analysis
-// Work item (m, block of RB = 128 CT ring pairs) and column group cg of 16 CT
-// columns (8 CT maps); 2 CT waves, one ring pair per thread for the recurrence.
+// Work item (m, block of RB = ana_block(CT) ring pairs) and column group cg of 16 CT
+// columns (8 CT maps); 2 CT waves. The first RB threads run the recurrence, one ring
+// pair each, and stage the values in LDS once per chunk of l for every wave of the
+// workgroup (from CT = 4 on, half or more of the waves only contract, so the values
+// are generated once per 64 or 128 columns rather than once per 32).
 // Wave w owns the output tile (parity w & 1, column tile w >> 1).
 // NP = 1: FP32 matrix cores; NP = 2 or 3: bf16 pieces.
 template <int NP, int CT>
 __device__ __forceinline__ void analysis_body(const PlanDev& P, const MfmaArgs& a, const WorkItem it,
                                               const int cg) {
-  constexpr int RB = 128 * CT;
+  constexpr int RB = ana_block(CT);
+  static_assert(RB <= 128 * CT && RB % LANES == 0, "generating threads are whole waves of the workgroup");
   constexpr bool F32 = (NP == 1);
   constexpr int NB = F32 ? 1 : NP;
   // staged Legendre values [parity][row][ring]; FP32 or bf16 pieces (rows 16 B aligned)
@@ -172,7 +176,8 @@ __device__ __forceinline__ void analysis_body(const PlanDev& P, const MfmaArgs& 
   const size_t pstride = (size_t)(lmax + 1) * 4;
   const float* __restrict__ G = a.G;
 
-  Ring ring = ring_init(P, m, q0 + tid, nact);
+  const bool gen = tid < RB;                      // uniform over the wave
+  Ring ring = ring_init(P, m, gen ? q0 + tid : nact, nact);
 
   const int par = wave & 1, ct = wave >> 1;
   const int col = cg * (16 * CT) + ct * 16 + (lane & 15);
@@ -213,15 +218,17 @@ __device__ __forceinline__ void analysis_body(const PlanDev& P, const MfmaArgs& 
 
   for (int l0 = m; l0 <= lmax; l0 += MCH) {
     const double* Ac = Arow + (l0 - m);
-    if constexpr (F32) {
-      ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][tid] = (float)v; });
-    } else {
-      ring_steps(ring, Ac, [&](int j, double v) {
-        __bf16 pc[NB];
-        split_pieces<NB>((float)v, pc);
+    if (gen) {
+      if constexpr (F32) {
+        ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][tid] = (float)v; });
+      } else {
+        ring_steps(ring, Ac, [&](int j, double v) {
+          __bf16 pc[NB];
+          split_pieces<NB>((float)v, pc);
 #pragma unroll
-        for (int i = 0; i < NB; ++i) lam_b[i][j & 1][j >> 1][tid] = pc[i];
-      });
+          for (int i = 0; i < NB; ++i) lam_b[i][j & 1][j >> 1][tid] = pc[i];
+        });
+      }
     }
     __syncthreads();
     f4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -741,7 +748,7 @@ __global__ void __launch_bounds__(128 * CT) group_analysis_kernel(GroupArgs g) {
   const int64_t local = blockIdx.x - g.offs[t];
   const int ncg = (2 * T.nmaps + 16 * CT - 1) / (16 * CT);
   const WorkItem* items = CT == 1 ? T.items_a128 : T.items_a256;
-  analysis_body<NP, CT>(T.P, task_args(T, 128 * CT), items[local / ncg], (int)(local % ncg));
+  analysis_body<NP, CT>(T.P, task_args(T, ana_block(CT)), items[local / ncg], (int)(local % ncg));
 }
 
 template <int NP, int NCT>
@@ -764,12 +771,18 @@ __global__ void __launch_bounds__(COEFF_THREADS) group_coeff_kernel(GroupArgs g,
 template <int NP>
 hipError_t ana_np(const PlanDev& P, const WorkItem* items, int nitems, int ct, const MfmaArgs& a,
                   hipStream_t s) {
-  if (ct == 1) {
-    hipLaunchKernelGGL((mfma_analysis_kernel<NP, 1>), dim3(nitems, (2 * a.nmaps + 15) / 16), dim3(128), 0, s,
-                       P, items, a);
-  } else {
-    hipLaunchKernelGGL((mfma_analysis_kernel<NP, 2>), dim3(nitems, (2 * a.nmaps + 31) / 32), dim3(256), 0, s,
-                       P, items, a);
+  const dim3 grid(nitems, (2 * a.nmaps + 16 * ct - 1) / (16 * ct));
+  switch (ct) {
+    case 1: hipLaunchKernelGGL((mfma_analysis_kernel<NP, 1>), grid, dim3(128), 0, s, P, items, a); break;
+    case 2: hipLaunchKernelGGL((mfma_analysis_kernel<NP, 2>), grid, dim3(256), 0, s, P, items, a); break;
+    case 4: hipLaunchKernelGGL((mfma_analysis_kernel<NP, 4>), grid, dim3(512), 0, s, P, items, a); break;
+    case 8:
+      if constexpr (NP == 1) {
+        hipLaunchKernelGGL((mfma_analysis_kernel<NP, 8>), grid, dim3(1024), 0, s, P, items, a);
+        break;
+      }
+      return hipErrorInvalidValue;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
@@ -797,10 +810,18 @@ hipError_t syn_np(const PlanDev& P, const WorkItem* items, int nitems, int nct, 
 template <int NP>
 hipError_t gana_np(const GroupLaunch& g, int ct, hipStream_t s) {
   return for_each_group_part(g, [&](const GroupArgs& a, int64_t nb) {
-    if (ct == 1)
-      hipLaunchKernelGGL((group_analysis_kernel<NP, 1>), dim3(nb), dim3(128), 0, s, a);
-    else
-      hipLaunchKernelGGL((group_analysis_kernel<NP, 2>), dim3(nb), dim3(256), 0, s, a);
+    switch (ct) {
+      case 1: hipLaunchKernelGGL((group_analysis_kernel<NP, 1>), dim3(nb), dim3(128), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((group_analysis_kernel<NP, 2>), dim3(nb), dim3(256), 0, s, a); break;
+      case 4: hipLaunchKernelGGL((group_analysis_kernel<NP, 4>), dim3(nb), dim3(512), 0, s, a); break;
+      case 8:
+        if constexpr (NP == 1) {
+          hipLaunchKernelGGL((group_analysis_kernel<NP, 8>), dim3(nb), dim3(1024), 0, s, a);
+          break;
+        }
+        return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   });
 }

@@ -117,7 +117,7 @@ RingGeo ring_geometry(int n, int i);
 
 // Launch-shape choices of the matrix-core kernels (see the autotuner).
 struct Tuning {
-  int ana_ct = 2;    // column tiles per analysis workgroup (ring block 128 ct)
+  int ana_ct = 2;    // column tiles per analysis workgroup (ring block ana_block(ana_ct))
   int syn_nct = 2;   // column tiles per synthesis wave (8 for FP32 only)
   int syn_wide = 0;  // 1 or 2: a plan's own solves use the wide synthesis kernel with that many column
                      // tiles per wave (task groups keep syn_nct)

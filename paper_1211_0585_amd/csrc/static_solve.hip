@@ -125,7 +125,7 @@ extern "C" int wf_solve_batch_static(wf_plan_t p, int32_t nmaps, const void* d, 
   };
   MfmaArgs ma{};
   ma.nmaps = nmaps;
-  ma.ana_rb = 128 * p->tune.ana_ct;
+  ma.ana_rb = ana_block(p->tune.ana_ct);
   ma.G = static_cast<const float*>(G);
   ma.F = static_cast<float*>(F);
   ma.partial = reinterpret_cast<float*>(ws + L.part_off);
