@@ -101,7 +101,10 @@ typedef struct {
  * wf_plan -- build the geometry, coefficient tables and device work buffers for
  * one (nside, lmax, C_l, N^-1, mask) problem (Sect. 2: T = min(diag N) fixes tau).
  *   out      receives the plan handle (set to NULL on failure)
- *   nside    HEALPix resolution, a power of two in [1, 1024]
+ *   nside    HEALPix resolution, a power of two in [1, 1024] (a ring pair's transform
+ *            runs in one workgroup's LDS: at 1024 the longest polar rings take a
+ *            Bluestein transform of 8192 points, 136 KiB in FP64 with its padding, of
+ *            the 160 KiB a CU has; at 2048 it would not fit)
  *   lmax     band limit, 0 <= lmax <= 4 nside - 1 (and <= 2048)
  *   cl       host, lmax+1 doubles, finite and >= 0 (signal power C_l; 0 filters the mode out)
  *   ninv     host, npix doubles, finite and >= 0 (inverse noise variance per pixel)

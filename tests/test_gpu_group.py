@@ -168,3 +168,45 @@ def test_group_of_more_tasks_than_one_launch_holds(torch_dev):
     g.close()
     for p in plans:
         p.close()
+
+
+def test_uneven_batch_real_shapes_vs_oracle(torch_dev):
+    """The uneven batch at its real shapes (32 maps at Nside 128 / lmax 256, 16 at
+    256 / 512, 8 at 512 / 1024; satellite recipe at each Nside with N_obs scaled by
+    (512 / Nside)^2) as one FP32 task group, two sweeps (lambda = 100, 1): the first
+    and last member of each shape against the oracle's solve of the same data
+    (<= 1e-5), every member against its plan solved alone (<= 1e-6)."""
+    torch = torch_dev
+    from paper_1211_0585_amd import mwf, synth
+    shapes = [(128, 256, 32), (256, 512, 16), (512, 1024, 8)]
+    lams = np.array([100.0, 1.0])
+    plans, ds, host, models = [], [], [], []
+    for i, (nside, lmax, n) in enumerate(shapes):
+        th, ph = mwf.pixel_angles(nside)
+        model = synth.satellite_model(th, ph, lmax, nobs_scale=(512.0 / nside) ** 2)
+        # data: a seeded noise draw of the model plus a seeded white field (all from the
+        # input generator)
+        d = np.stack([synth.draw(model, s)["noise"] + 50.0 * synth.rng(500 + 10 * i + s, 3).standard_normal(th.size)
+                      for s in range(n)]).astype(np.float32)
+        plans.append(mwf.Plan(nside, lmax, model["cl"], model["ninv"], dtype=mwf.WF_F32, max_batch=n))
+        ds.append(torch.from_numpy(d).cuda())
+        host.append(d)
+        models.append(model)
+    g = mwf.Group(plans, [n for _, _, n in shapes])
+    gw, ga = g.solve(ds, lams)
+    torch.cuda.synchronize()
+    for i, ((nside, lmax, n), p) in enumerate(zip(shapes, plans)):
+        sw, sa = p.solve(ds[i], lams)
+        p.sync()
+        gwi, gai = gw[i].cpu().numpy(), ga[i].cpu().numpy()
+        e_sep = max(rel_l2(gwi[k], sw[k].cpu().numpy()) for k in range(n))
+        e_or = 0.0
+        for k in (0, n - 1):
+            ref_map, ref_alm = messenger.solve(host[i][k].astype(np.float64), models[i]["ninv"], models[i]["cl"],
+                                               lams, nside, lmax)
+            e_or = max(e_or, rel_l2(gwi[k], ref_map), alm_rel_l2(gai[k], ref_alm, lmax))
+        _log(f"uneven batch {n}@({nside},{lmax}): members vs alone {e_sep:.2e}, first/last vs oracle {e_or:.2e}")
+        assert e_sep <= 1e-6 and e_or <= 1e-5
+    g.close()
+    for p in plans:
+        p.close()

@@ -19,9 +19,10 @@ def _rand_alm(lmax, rs, real_m0=True):
     return a
 
 
-@pytest.mark.parametrize("nside,lmax", [(1, 3), (2, 5), (4, 8), (4, 15)])
+@pytest.mark.parametrize("nside,lmax", [(1, 3), (2, 5), (4, 8), (4, 15), (8, 16), (8, 31), (16, 33), (16, 63)])
 def test_ring_sums_match_direct(nside, lmax):
-    """FFT + bin folding equals the term-by-term sums, aliasing included."""
+    """FFT + bin folding equals the term-by-term sums, aliasing included (lmax up to
+    4 nside - 1: every polar ring folds several frequencies into each bin)."""
     rs = np.random.default_rng(nside * 100 + lmax)
     f = rs.standard_normal(healpix.npix(nside))
     G = sht.ring_analysis(f, nside, lmax)
