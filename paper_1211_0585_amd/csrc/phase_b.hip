@@ -33,6 +33,10 @@
 // twiddles of its ring's transform in LDS next to the data, one table per pass
 // read by consecutive lanes at consecutive entries, and the data sit in a padded
 // layout between passes: both keep the passes' LDS accesses off shared banks.
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "mwf_internal.hpp"
 
 namespace mwf {
@@ -899,21 +903,27 @@ int maxb_for(int fft_len, int nt) {
   return b <= 1 ? 1 : (b <= 2 ? 2 : (b <= 4 ? 4 : 0));
 }
 
-template <class K>
-hipError_t set_lds(K kernel, size_t lds, size_t* attr) {
-  if (lds > *attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    *attr = lds;
-  }
+// Raise the dynamic-LDS limit of `kernel` on the current device to at least `lds`
+// (never lower it). One lock for every kernel and device: launches of one kernel
+// from several host threads (plans, the server's stepping thread) must not undo
+// each other's limit.
+hipError_t ensure_dynamic_lds(const void* kernel, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, size_t> limit;
+  int dev = 0;
+  if (hipError_t e = hipGetDevice(&dev)) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& cur = limit[{kernel, dev}];
+  if (lds <= cur) return hipSuccess;
+  if (hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return e;
+  cur = lds;
   return hipSuccess;
 }
 
 template <class T, class C, int NT, int MAXB, int CLS>
 hipError_t launch_class_b(const PlanDev& P, const PhaseBArgs& a, const RingClass& rc, hipStream_t s) {
-  static size_t attr = 0;
   const size_t lds = ring_lds_bytes(rc.fft_len, sizeof(typename CT<C>::V));
-  if (hipError_t e = set_lds(phase_b_kernel<T, C, NT, MAXB, CLS>, lds, &attr)) return e;
+  if (hipError_t e = ensure_dynamic_lds((const void*)phase_b_kernel<T, C, NT, MAXB, CLS>, lds)) return e;
   hipLaunchKernelGGL((phase_b_kernel<T, C, NT, MAXB, CLS>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q,
                      rc.fft_len);
   return hipGetLastError();
@@ -941,9 +951,8 @@ hipError_t launch_t(const PlanDev& P, const PhaseBArgs& a, const RingClass* cls,
 
 template <int NT, int CLS, int MAXB>
 hipError_t group_class_b(const GroupLaunch& g, int fft_len, hipStream_t s) {
-  static size_t attr = 0;
   const size_t lds = ring_lds_bytes(fft_len, sizeof(float2));
-  if (hipError_t e = set_lds(group_phase_b_kernel<NT, CLS, MAXB>, lds, &attr)) return e;
+  if (hipError_t e = ensure_dynamic_lds((const void*)group_phase_b_kernel<NT, CLS, MAXB>, lds)) return e;
   return for_each_group_part(g, [&](const GroupArgs& a, int64_t nb) {
     hipLaunchKernelGGL((group_phase_b_kernel<NT, CLS, MAXB>), dim3(nb), dim3(NT), lds, s, a, fft_len);
     return hipGetLastError();
@@ -962,9 +971,8 @@ hipError_t group_class(const GroupLaunch& g, int fft_len, hipStream_t s) {
 
 template <int NT, int MAXB, int CLS>
 hipError_t launch_pol_class_b(const PlanDev& P, const PolRingArgs& a, const RingClass& rc, hipStream_t s) {
-  static size_t attr = 0;
   const size_t lds = ring_lds_bytes(rc.fft_len, sizeof(double2));
-  if (hipError_t e = set_lds(phase_b_pol_kernel<NT, MAXB, CLS>, lds, &attr)) return e;
+  if (hipError_t e = ensure_dynamic_lds((const void*)phase_b_pol_kernel<NT, MAXB, CLS>, lds)) return e;
   hipLaunchKernelGGL((phase_b_pol_kernel<NT, MAXB, CLS>), dim3(rc.count, a.nmaps), dim3(NT), lds, s, P, a, rc.q,
                      rc.fft_len);
   return hipGetLastError();
