@@ -64,7 +64,8 @@ enum { WF_F64 = 0, WF_F32 = 1, WF_BF16X3 = 2, WF_BF16X6 = 3 };
 
 /* Plan flags. WF_FLAG_TIMING: record HIP events around every kernel launch of a
  * solve on the caller's stream and report the summed durations in wf_stats; the
- * solve then waits for its own completion before returning.
+ * events are created without the system-scope fence (they only time), and the solve
+ * then synchronises the stream before returning.
  * WF_FLAG_CHI2: every solve also records, for each map and each sweep k, the chi^2
  * of the iterate after that sweep (Sect. 3's convergence monitor, at lambda = 1):
  *   chi2_k = sum_lm w_m |s_lm|^2 / C_l + sum_p N^-1_p (d_p - s_p)^2,

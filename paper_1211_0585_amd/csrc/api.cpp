@@ -100,7 +100,7 @@ size_t plan_buffer_bytes(int nside, int lmax, int dtype, int nmaps) {
   const size_t nalm = (size_t)(lmax + 1) * (lmax + 2) / 2;
   const size_t rows = nalm + (size_t)(lmax + 1) * ROW_PAD;
   const size_t el = dtype == WF_F64 ? 8 : 4;
-  size_t b = 2 * (size_t)nmaps * npairs * (lmax + 1) * 4 * el + npix * el + (lmax + 1) * 8;
+  size_t b = 2 * (size_t)nmaps * npairs * gf_stride(lmax) * el + npix * el + (lmax + 1) * 8;
   if (dtype == WF_F64) {
     const size_t rb = npairs <= 64 ? 64 : (npairs <= 128 ? 128 : 256);
     b += (size_t)nmaps * ((npairs + rb - 1) / rb) * nalm * 16 + (size_t)nmaps * rows * 16;
@@ -138,10 +138,16 @@ struct Timer {
   ~Timer() {
     for (auto e : ev) hipEventDestroy(e);
   }
+  // The events only time launches: without the system-scope fence an event does not write
+  // back and invalidate the caches, which would slow the launch after it and add its own time.
+  static int make(hipEvent_t* e) {
+    MWF_HIP(hipEventCreateWithFlags(e, hipEventDisableSystemFence));
+    return WF_OK;
+  }
   int begin() {
     if (!on) return WF_OK;
     hipEvent_t e;
-    MWF_HIP(hipEventCreate(&e));
+    if (int rc = make(&e)) return rc;
     MWF_HIP(hipEventRecord(e, s));
     ev.push_back(e);
     return WF_OK;
@@ -149,7 +155,7 @@ struct Timer {
   int end(int k) {
     if (!on) return WF_OK;
     hipEvent_t e;
-    MWF_HIP(hipEventCreate(&e));
+    if (int rc = make(&e)) return rc;
     MWF_HIP(hipEventRecord(e, s));
     ev.push_back(e);
     kind.push_back(k);
@@ -157,7 +163,7 @@ struct Timer {
   }
   int collect(wf_stats* st) {
     if (!on || !st || ev.empty()) return WF_OK;
-    MWF_HIP(hipEventSynchronize(ev.back()));
+    MWF_HIP(hipStreamSynchronize(s));
     double ms[3] = {0, 0, 0};
     int cnt[3] = {0, 0, 0};
     for (size_t i = 0; i < kind.size(); ++i) {
@@ -381,7 +387,7 @@ int plan_alloc(wf_plan_s* p) {
   const int dtype = p->dtype, nside = g.nside, lmax = g.lmax;
   // ---- work buffers
   p->elem = (dtype == WF_F64) ? 8 : 4;
-  const size_t gf = (size_t)p->max_batch * g.npairs * (lmax + 1) * 4 * p->elem;
+  const size_t gf = (size_t)p->max_batch * g.npairs * gf_stride(lmax) * p->elem;
   {
     uint8_t *G = nullptr, *F = nullptr;
     if ((rc = p->mem.alloc(&G, gf))) return rc;
@@ -741,11 +747,12 @@ int band_plan(wf_plan_s* p, int L, wf_plan_s** out) {
 // `from`) into the buffer of a plan of higher band limit; m above `from`'s limit is
 // zero there, as the iterate has no such modes.
 int carry_F(const wf_plan_s* from, wf_plan_s* to, hipStream_t s) {
-  const size_t sp = (size_t)(from->geo->lmax + 1) * 4 * from->elem;
-  const size_t dp = (size_t)(to->geo->lmax + 1) * 4 * to->elem;
+  const size_t w = (size_t)(from->geo->lmax + 1) * 4 * from->elem;   // bytes of a row's values
+  const size_t sp = gf_stride(from->geo->lmax) * from->elem;         // row pitches
+  const size_t dp = gf_stride(to->geo->lmax) * to->elem;
   const size_t rows = (size_t)from->geo->npairs;
-  MWF_HIP(hipMemcpy2DAsync(to->F, dp, from->F, sp, sp, rows, hipMemcpyDeviceToDevice, s));
-  if (dp > sp) MWF_HIP(hipMemset2DAsync(static_cast<uint8_t*>(to->F) + sp, dp, 0, dp - sp, rows, s));
+  MWF_HIP(hipMemcpy2DAsync(to->F, dp, from->F, sp, w, rows, hipMemcpyDeviceToDevice, s));
+  if (dp > w) MWF_HIP(hipMemset2DAsync(static_cast<uint8_t*>(to->F) + w, dp, 0, dp - w, rows, s));
   return WF_OK;
 }
 

@@ -287,6 +287,35 @@ int build_geometry(Geometry& g) {
     if (items.empty()) items.push_back({0, 0});
     return items;
   };
+  // Matrix-core lists, ordered for the L2 caches of the XCDs. A row of G or F holds the
+  // entries of consecutive m side by side (16 bytes each in FP32), so the items of one ring
+  // block and eight consecutive m read or write the same one or two 128-byte lines of every
+  // row. Such a group, taken in the
+  // order of its most costly item, is dealt with seven others so that group g of the eight
+  // holds positions g, g + 8, ..., g + 56: a dispatch that deals workgroups to the XCDs in
+  // turn runs each group on one XCD, its members one after another. Missing members are
+  // empty items (m = -1, the kernels return at once).
+  auto xcd_order = [&](const std::vector<WorkItem>& items) {
+    std::vector<std::vector<WorkItem>> groups;
+    std::map<std::pair<int, int>, int> index;
+    for (const WorkItem& w : items) {
+      const auto key = std::make_pair(w.blk, w.m >> 3);
+      auto f = index.find(key);
+      if (f == index.end()) {
+        f = index.emplace(key, (int)groups.size()).first;
+        groups.emplace_back();
+      }
+      groups[f->second].push_back(w);
+    }
+    for (auto& g : groups)
+      std::sort(g.begin(), g.end(), [](const WorkItem& a, const WorkItem& b) { return a.m < b.m; });
+    std::vector<WorkItem> out;
+    for (size_t s0 = 0; s0 < groups.size(); s0 += 8)
+      for (size_t k = 0; k < 8; ++k)
+        for (size_t g = s0; g < s0 + 8; ++g)
+          out.push_back(g < groups.size() && k < groups[g].size() ? groups[g][k] : WorkItem{-1, 0});
+    return out;
+  };
   // FP64 lists: one bin per wave of a launch (FP64_WAVES_PER_SIMD per SIMD, at most one
   // per item); items, most costly first, each go to the least-loaded bin; bins are
   // stored in turn, with off[b] .. off[b + 1] the items of bin b
@@ -324,7 +353,7 @@ int build_geometry(Geometry& g) {
   std::vector<int32_t> bins_ana, bins_syn;
   const auto ia = pack_bins(g.ring_block_ana, FP64_SCALED_COST_ANA, &bins_ana);
   const auto is = pack_bins(g.ring_block_syn, FP64_SCALED_COST_SYN, &bins_syn);
-  const auto i128 = make_items(128), i256 = make_items(256), i64 = make_items(64);
+  const auto i128 = xcd_order(make_items(128)), i256 = xcd_order(make_items(256)), i64 = xcd_order(make_items(64));
   g.n_ana = (int)ia.size();
   g.n_syn = (int)is.size();
   g.nbins_ana = (int)bins_ana.size() - 1;

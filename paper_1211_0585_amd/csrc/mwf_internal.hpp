@@ -128,6 +128,12 @@ struct PlanDev {
   const int32_t* row_m;      // [rows_total] m of each padded row
 };
 
+// Elements per ring pair in the G and F buffers ([map][pair][m][E re, E im, O re, O im]):
+// 4 per m <= lmax, unpadded. (Rows padded to whole 128-byte lines made the per-map stride a
+// multiple of 2^17 bytes at Nside 512, and the matrix-core Legendre kernels ran 12-18 %
+// slower on it despite fetching fewer lines.)
+__host__ __device__ inline size_t gf_stride(int lmax) { return (size_t)(lmax + 1) * 4; }
+
 __host__ __device__ inline int64_t alm_index(int lmax, int l, int m) {
   return (int64_t)m * (2 * lmax + 1 - m) / 2 + l;
 }

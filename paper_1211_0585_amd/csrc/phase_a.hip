@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(FP64_WG_WAVES * LANES) legendre_analysis_f64_k
     const int lmax = P.lmax;
     const int nact = P.n_active[m];
     const double* __restrict__ Arow = P.A + P.row_off[m];
-    const size_t pstride = (size_t)(lmax + 1) * 4;
+    const size_t pstride = gf_stride(lmax);
     const double* Gm = G + (size_t)map * P.npairs * pstride + (size_t)m * 4;
 
     RingState<R> st;
@@ -394,7 +394,7 @@ __global__ void __launch_bounds__(FP64_WG_WAVES * LANES) legendre_synthesis_f64_
       }
     }
 
-    const size_t pstride = (size_t)(lmax + 1) * 4;
+    const size_t pstride = gf_stride(lmax);
     double* Fm = a.F + (size_t)map * P.npairs * pstride + (size_t)m * 4;
 #pragma unroll
     for (int r = 0; r < R; ++r) {

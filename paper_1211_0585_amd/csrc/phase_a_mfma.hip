@@ -111,6 +111,11 @@ __device__ __forceinline__ void ring_steps(Ring& r, const double* __restrict__ A
   }
 }
 
+// x of lane l ^ 1 (DPP quad permutation 1, 0, 3, 2).
+__device__ __forceinline__ float swap_lane_pair(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
   hi = (__bf16)x;
   lo = (__bf16)(x - (float)hi);
@@ -168,12 +173,13 @@ __device__ __forceinline__ void analysis_body(const PlanDev& P, const MfmaArgs& 
   __shared__ float lam_f[F32 ? 2 : 1][16][RB + 4];
   __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][16][RB + 8];
   const int m = it.m, blk = it.blk;
+  if (m < 0) return;   // empty item of the XCD-ordered list
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lmax = P.lmax;
   const int nact = P.n_active[m];
   const int q0 = blk * RB;
   const double* __restrict__ Arow = P.A + P.row_off[m];
-  const size_t pstride = (size_t)(lmax + 1) * 4;
+  const size_t pstride = gf_stride(lmax);
   const float* __restrict__ G = a.G;
 
   const bool gen = tid < RB;                      // uniform over the wave
@@ -279,6 +285,7 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
   __shared__ float lam_f[F32 ? 2 : 1][16][64 + 4];
   __shared__ __attribute__((aligned(16))) __bf16 lam_b[NB][F32 ? 1 : 2][64][ROWS + 8];
   const int m = it.m, blk = it.blk;
+  if (m < 0) return;   // empty item of the XCD-ordered list
   const int lane = threadIdx.x;
   constexpr int CW = 16 * NCT;   // columns of this wave
   const int lmax = P.lmax;
@@ -400,21 +407,26 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
     __syncthreads();
   }
 
-  const size_t pstride = (size_t)(lmax + 1) * 4;
+  // lanes 2j and 2j + 1 (real and imaginary column of one map) swap values so that each
+  // writes whole 16-byte entries: the even lane rows r = 0, 2, the odd lane rows r = 1, 3
+  const int odd = lane & 1;
+  const size_t pstride = gf_stride(lmax);
+  float* const Fm = a.F + (size_t)m * 4;
 #pragma unroll
   for (int qt = 0; qt < 4; ++qt)
 #pragma unroll
     for (int ct = 0; ct < NCT; ++ct) {
-      const int colg = cg * CW + ct * 16 + (lane & 15);
-      const int map = colg >> 1, comp = colg & 1;
-      if (map >= a.nmaps) continue;
+      const int map = (cg * CW + ct * 16 + (lane & 15)) >> 1;
+      const bool map_ok = map < a.nmaps;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int q = q0 + qt * 16 + 4 * (lane >> 4) + r;
-        if (q >= nact) continue;
-        float* Fq = a.F + ((size_t)map * P.npairs + q) * pstride + (size_t)m * 4;
-        Fq[comp] = acc[qt][ct][0][r];
-        Fq[2 + comp] = acc[qt][ct][1][r];
+      for (int i = 0; i < 2; ++i) {
+        const float eA = acc[qt][ct][0][2 * i], eB = acc[qt][ct][0][2 * i + 1];
+        const float oA = acc[qt][ct][1][2 * i], oB = acc[qt][ct][1][2 * i + 1];
+        const float seA = swap_lane_pair(eA), seB = swap_lane_pair(eB);
+        const float soA = swap_lane_pair(oA), soB = swap_lane_pair(oB);
+        const float4 v = make_float4(odd ? seB : eA, odd ? eB : seA, odd ? soB : oA, odd ? oB : soA);
+        const int q = q0 + qt * 16 + 4 * (lane >> 4) + 2 * i + odd;
+        if (map_ok && q < nact) *reinterpret_cast<float4*>(Fm + ((size_t)map * P.npairs + q) * pstride) = v;
       }
     }
 }
@@ -456,6 +468,7 @@ __global__ void __launch_bounds__(256) mfma_wide_synthesis_kernel(PlanDev P, con
   const WorkItem it = items[blockIdx.x];
   const int cg = blockIdx.y;
   const int m = it.m;
+  if (m < 0) return;   // empty item of the XCD-ordered list
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lmax = P.lmax;
   const int nact = P.n_active[m];
@@ -602,22 +615,29 @@ __global__ void __launch_bounds__(256) mfma_wide_synthesis_kernel(PlanDev P, con
     buf ^= 1;
   }
 
-  const size_t pstride = (size_t)(lmax + 1) * 4;
+  // Lanes 2j and 2j + 1 hold the real and the imaginary column of one map for the same ring
+  // pairs. They swap values (lane ^ 1) so that each writes whole 16-byte entries (E re, E im,
+  // O re, O im): the even lane those of rows r = 0, 2, ..., 14, the odd lane those of rows
+  // r = 1, 3, ..., 15 — a quarter of the stores, each of one entry.
+  const int odd = lane & 1;
+  const size_t pstride = gf_stride(lmax);
+  float* const Fm = a.F + (size_t)m * 4;
 #pragma unroll
   for (int n = 0; n < NT; ++n) {
-    const int colg = cg * WS_COLS + 32 * n + (lane & 31);
-    const int map = colg >> 1, comp = colg & 1;
-    if (map >= a.nmaps) continue;
-    float* Fm = a.F + (size_t)map * P.npairs * pstride + (size_t)m * 4 + comp;
+    const int map = (cg * WS_COLS + 32 * n + (lane & 31)) >> 1;
+    const bool map_ok = map < a.nmaps;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int q = q0 + 32 * t + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (q < nact) {
-          Fm[(size_t)q * pstride] = acc[t][n][0][r];
-          Fm[(size_t)q * pstride + 2] = acc[t][n][1][r];
-        }
+      for (int i = 0; i < 8; ++i) {
+        const float eA = acc[t][n][0][2 * i], eB = acc[t][n][0][2 * i + 1];
+        const float oA = acc[t][n][1][2 * i], oB = acc[t][n][1][2 * i + 1];
+        const float seA = swap_lane_pair(eA), seB = swap_lane_pair(eB);
+        const float soA = swap_lane_pair(oA), soB = swap_lane_pair(oB);
+        const float4 v = make_float4(odd ? seB : eA, odd ? eB : seA, odd ? soB : oA, odd ? oB : soA);
+        const int q = q0 + 32 * t + 8 * (i >> 1) + 4 * (lane >> 5) + 2 * (i & 1) + odd;
+        if (map_ok && q < nact)
+          *reinterpret_cast<float4*>(Fm + ((size_t)map * P.npairs + q) * pstride) = v;
       }
   }
 }

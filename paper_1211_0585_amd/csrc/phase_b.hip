@@ -600,7 +600,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   const int lmax = P.lmax;
   const bool equator = rp.start_s < 0;
   const int tid = threadIdx.x;
-  const size_t pstride = (size_t)(lmax + 1) * 4;
+  const size_t pstride = gf_stride(lmax);
   const size_t pbase = ((size_t)map * P.npairs + q) * pstride;
   const int64_t mbase = (int64_t)map * P.npix;
   const int mode = a.slots ? a.slots[map].pb_mode : a.mode;
@@ -759,7 +759,7 @@ __device__ __forceinline__ void phase_b_pol_body(const PlanDev& P, const PolRing
   const bool equator = rp.start_s < 0;
   const int tid = threadIdx.x;
   const int mode = a.mode;
-  const size_t pstride = (size_t)(lmax + 1) * 4;
+  const size_t pstride = gf_stride(lmax);
   auto pbase = [&](int f) { return (((size_t)f * a.field_maps + map) * P.npairs + q) * pstride; };
   const int64_t mbase = (int64_t)map * 3 * P.npix;
 

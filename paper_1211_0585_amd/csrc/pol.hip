@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(S2_WAVES * LANES) spin2_analysis_kernel(PlanDe
   double(*red)[LANES / 2 + 1] = red_w[wave];
   double* sA = sA_w[wave];
   double* sB = sB_w[wave];
-  const size_t pstride = (size_t)(lmax + 1) * 4;
+  const size_t pstride = gf_stride(lmax);
   const double* Gq = G + (((size_t)1 * S2.field_maps + map) * P.npairs) * pstride + (size_t)m * 4;
   const double* Gu = G + (((size_t)2 * S2.field_maps + map) * P.npairs) * pstride + (size_t)m * 4;
 
@@ -340,7 +340,7 @@ __global__ void __launch_bounds__(S2_WAVES * LANES) spin2_synthesis_kernel(PlanD
     }
   }
   if (valid) {
-    const size_t pstride = (size_t)(lmax + 1) * 4;
+    const size_t pstride = gf_stride(lmax);
     double* Fq = F + (((size_t)1 * S2.field_maps + map) * P.npairs + q) * pstride + (size_t)m * 4;
     double* Fu = F + (((size_t)2 * S2.field_maps + map) * P.npairs + q) * pstride + (size_t)m * 4;
     *reinterpret_cast<double4*>(Fq) = make_double4(EQr, EQi, OQr, OQi);

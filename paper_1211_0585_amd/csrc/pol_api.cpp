@@ -91,14 +91,15 @@ struct PolTimer {
   int mark() {
     if (!on) return WF_OK;
     hipEvent_t e;
-    MWF_HIP(hipEventCreate(&e));
+    // Timing only: no system-scope fence (no cache write-back and invalidation per event).
+    MWF_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     MWF_HIP(hipEventRecord(e, s));
     ev.push_back(e);
     return WF_OK;
   }
   int collect(wf_stats* st) {
     if (!on || !st || ev.empty()) return WF_OK;
-    MWF_HIP(hipEventSynchronize(ev.back()));
+    MWF_HIP(hipStreamSynchronize(s));
     double ms[3] = {0, 0, 0};
     int cnt[3] = {0, 0, 0};
     for (size_t i = 0; i < kind.size(); ++i) {
@@ -331,7 +332,7 @@ int wf_pol_plan(wf_pol_plan_t* out, int32_t nside, int32_t lmax, const double* c
   p->s2.field_maps = p->max_batch;
 
   // work buffers: G, F [3][max_batch][pair][m][4]; partial sums; synthesis coefficients
-  const size_t gf = (size_t)3 * p->max_batch * g.npairs * (lmax + 1) * 4;
+  const size_t gf = (size_t)3 * p->max_batch * g.npairs * gf_stride(lmax);
   if ((rc = p->mem.alloc(&p->G, gf)) || (rc = p->mem.alloc(&p->F, gf)) ||
       (rc = p->mem.alloc(&p->partial_t, (size_t)p->max_batch * g.nblk_max_ana * g.nalm)) ||
       (rc = p->mem.alloc(&p->partial_eb, (size_t)p->max_batch * p->nblk2 * g.nalm * 4)) ||

@@ -56,7 +56,7 @@ struct WsLayout {
 WsLayout ws_layout(const wf_plan_s* p, int nmaps) {
   const Geometry& g = *p->geo;
   WsLayout L{};
-  L.gf_bytes = (size_t)nmaps * g.npairs * (g.lmax + 1) * 4 * p->elem;
+  L.gf_bytes = (size_t)nmaps * g.npairs * gf_stride(g.lmax) * p->elem;
   size_t part, coef;
   if (p->dtype == WF_F64) {
     part = (size_t)nmaps * g.nblk_max_ana * g.nalm * sizeof(double2);
