@@ -252,21 +252,23 @@ __global__ void __launch_bounds__(FP64_WG_WAVES * LANES) legendre_analysis_f64_k
 //   SY_FROM_ALM      s = caller's alm (imaginary part of m = 0 dropped)
 // s goes to alm_out when requested; bcoef = C_l s, in the padded row layout of
 // the recurrence tables (zeros beyond lmax) so the synthesis can read whole chunks.
+// A flat grid over the padded rows r of every m (m = row_m[r], l = m + r - row_off[m];
+// padding rows get zeros) and the maps: with one workgroup per m instead, the long rows
+// of small m went to a few waves in turn, each waiting on its loads.
 __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
-  const int m = blockIdx.x;
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int map = blockIdx.y;
-  const int lmax = P.lmax;
-  const int nl = lmax - m + 1;
-  const int64_t row = alm_index(lmax, m, m);
-  const int64_t roff = P.row_off[m];
-  const double* __restrict__ Crow = P.C + roff;
-  const double lam_t_o = a.lambda * P.tau * P.omega;
-  const int nb = P.nblk[m];
   const bool chi = a.chi2 != nullptr && a.mode == SY_FROM_PARTIAL;
   double chi_acc = 0.0;
-  for (int i = threadIdx.x; i < nl + CHUNK; i += blockDim.x) {
+  if (r < P.rows_total) {
+    const int lmax = P.lmax;
+    const int m = P.row_m[r];
+    const int i = (int)(r - P.row_off[m]);
+    const int nl = lmax - m + 1;
     double2 b = make_double2(0.0, 0.0);
     if (i < nl) {
+      const int64_t row = alm_index(lmax, m, m);
+      const double c = P.C[r];
       double2 alm;
       if (a.mode == SY_FROM_ALM) {
         alm = a.alm_in[(size_t)map * P.nalm + row + i];
@@ -274,6 +276,7 @@ __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
       } else {
         // the blocks' partial sums, KB at a time with their loads issued together
         constexpr int KB = 4;
+        const int nb = P.nblk[m];
         const double2* pb = a.partial + (size_t)map * P.nblk_max * P.nalm + row + i;
         double sr = 0.0, si = 0.0;
         for (int k0 = 0; k0 < nb; k0 += KB) {
@@ -287,20 +290,20 @@ __global__ void legendre_coeff_kernel(PlanDev P, SynthArgs a) {
           }
         }
         // the ring phase already applied Omega to G
-        alm = make_double2(sr * Crow[i], si * Crow[i]);
+        alm = make_double2(sr * c, si * c);
         if (a.mode == SY_FROM_PARTIAL) {
           const double cl = P.cl[m + i];
-          const double f = cl > 0.0 ? cl / (cl + lam_t_o) : 0.0;
+          const double f = cl > 0.0 ? cl / (cl + a.lambda * P.tau * P.omega) : 0.0;
           alm.x *= f;
           alm.y *= f;
           // chi^2 prior term of the new iterate: w_m |s_lm|^2 / C_l (w = 1 at m = 0, else 2)
-          if (chi && cl > 0.0) chi_acc += (m == 0 ? 1.0 : 2.0) * (alm.x * alm.x + alm.y * alm.y) / cl;
+          if (chi && cl > 0.0) chi_acc = (m == 0 ? 1.0 : 2.0) * (alm.x * alm.x + alm.y * alm.y) / cl;
         }
       }
       if (a.alm_out) a.alm_out[(size_t)map * P.nalm + row + i] = alm;
-      b = make_double2(alm.x * Crow[i], alm.y * Crow[i]);
+      b = make_double2(alm.x * c, alm.y * c);
     }
-    if (a.mode != SY_ALM_ONLY) a.bcoef[(size_t)map * P.rows_total + roff + i] = b;
+    if (a.mode != SY_ALM_ONLY) a.bcoef[(size_t)map * P.rows_total + r] = b;
   }
   if (chi) block_sum_add(chi_acc, a.chi2 + map * a.chi2_stride);
 }
@@ -468,7 +471,8 @@ hipError_t launch_legendre_analysis_f64(const PlanDev& P, const WorkItem* items,
 }
 
 hipError_t launch_legendre_coeff(const PlanDev& P, const SynthArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(legendre_coeff_kernel, dim3(P.lmax + 1, a.nmaps), dim3(256), 0, s, P, a);
+  hipLaunchKernelGGL(legendre_coeff_kernel, dim3((unsigned)((P.rows_total + 255) / 256), a.nmaps), dim3(256), 0, s,
+                     P, a);
   return hipGetLastError();
 }
 
