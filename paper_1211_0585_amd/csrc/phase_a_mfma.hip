@@ -116,11 +116,6 @@ __device__ __forceinline__ float swap_lane_pair(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));
 }
 
-__device__ __forceinline__ void split_bf16(float x, __bf16& hi, __bf16& lo) {
-  hi = (__bf16)x;
-  lo = (__bf16)(x - (float)hi);
-}
-
 // x = p[0] + p[1] (+ p[2]): successive bf16 roundings of the remainder.
 template <int NP>
 __device__ __forceinline__ void split_pieces(float x, __bf16 (&p)[NP]) {
@@ -128,6 +123,22 @@ __device__ __forceinline__ void split_pieces(float x, __bf16 (&p)[NP]) {
   for (int i = 0; i < NP; ++i) {
     p[i] = (__bf16)x;
     x = x - (float)p[i];
+  }
+}
+
+// The same split for two values at once, each piece a packed dword (a in the low half):
+// one v_cvt_pk_bf16_f32 per piece for both values, and the dword is already laid out as
+// two consecutive elements of a bf16 operand.
+template <int NP>
+__device__ __forceinline__ void split_pieces2(float a, float b, unsigned (&p)[NP]) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  f2 x = {a, b};
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    const b2 h = __builtin_convertvector(x, b2);
+    p[i] = __builtin_bit_cast(unsigned, h);
+    if (i + 1 < NP) x = x - __builtin_convertvector(h, f2);
   }
 }
 
@@ -203,17 +214,25 @@ __device__ __forceinline__ void analysis_body(const PlanDev& P, const MfmaArgs& 
       bf[t] = (colok && q < nact) ? Gc[(size_t)q * pstride] : 0.0f;
     }
   } else {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int t = 0; t < KB; ++t) {
+      float v[8];
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int q = q0 + 32 * t + 8 * (lane >> 4) + e;
-        const float v = (colok && q < nact) ? Gc[(size_t)q * pstride] : 0.0f;
-        __bf16 pc[NB];
-        split_pieces<NB>(v, pc);
-#pragma unroll
-        for (int i = 0; i < NB; ++i) bb[i][t][e] = pc[i];
+        v[e] = (colok && q < nact) ? Gc[(size_t)q * pstride] : 0.0f;
       }
+      u4 bw[NB];
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        unsigned pk[NB];
+        split_pieces2<NB>(v[2 * w], v[2 * w + 1], pk);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) bw[i][w] = pk[i];
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) bb[i][t] = __builtin_bit_cast(bf8, bw[i]);
     }
   }
 
@@ -228,12 +247,23 @@ __device__ __forceinline__ void analysis_body(const PlanDev& P, const MfmaArgs& 
       if constexpr (F32) {
         ring_steps(ring, Ac, [&](int j, double v) { lam_f[j & 1][j >> 1][tid] = (float)v; });
       } else {
-        ring_steps(ring, Ac, [&](int j, double v) {
-          __bf16 pc[NB];
-          split_pieces<NB>((float)v, pc);
+        float ev[2][16];   // [parity][row]
+        ring_steps(ring, Ac, [&](int j, double v) { ev[j & 1][j >> 1] = (float)v; });
+        // lanes 2k and 2k + 1 (adjacent rings) swap values so that each writes dwords holding
+        // the pieces of both rings: the even lane those of rows 2r, the odd lane rows 2r + 1
+        const int odd = tid & 1;
 #pragma unroll
-          for (int i = 0; i < NB; ++i) lam_b[i][j & 1][j >> 1][tid] = pc[i];
-        });
+        for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+          for (int r = 0; r < 8; ++r) {
+            const float a0 = ev[pp][2 * r], a1 = ev[pp][2 * r + 1];
+            const float s0 = swap_lane_pair(a0), s1 = swap_lane_pair(a1);
+            unsigned pk[NB];
+            split_pieces2<NB>(odd ? s1 : a0, odd ? a1 : s0, pk);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+              *reinterpret_cast<unsigned*>(&lam_b[i][pp][2 * r + odd][tid & ~1]) = pk[i];
+          }
       }
     }
     __syncthreads();
@@ -366,26 +396,38 @@ __device__ __forceinline__ void synthesis_body(const PlanDev& P, const MfmaArgs&
         }
 #pragma unroll
       for (int half = 0; half < 2; ++half) {
-        ring_steps(ring, Ac + half * MCH, [&](int j, double v) {
-          __bf16 pc[NB];
-          split_pieces<NB>((float)v, pc);
+        float ev[2][MCH / 2];   // [parity][row]
+        ring_steps(ring, Ac + half * MCH, [&](int j, double v) { ev[j & 1][j >> 1] = (float)v; });
+        // the pieces of rows 2w and 2w + 1 (adjacent in the row-contiguous layout) as dwords
 #pragma unroll
-          for (int i = 0; i < NB; ++i) lam_b[i][j & 1][lane][half * (MCH / 2) + (j >> 1)] = pc[i];
-        });
+        for (int pp = 0; pp < 2; ++pp)
+#pragma unroll
+          for (int w = 0; w < MCH / 4; ++w) {
+            unsigned pk[NB];
+            split_pieces2<NB>(ev[pp][2 * w], ev[pp][2 * w + 1], pk);
+#pragma unroll
+            for (int i = 0; i < NB; ++i)
+              *reinterpret_cast<unsigned*>(&lam_b[i][pp][lane][half * (MCH / 2) + 2 * w]) = pk[i];
+          }
       }
       __syncthreads();
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp) {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
         bf8 bv[NB][NCT];
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct)
+        for (int ct = 0; ct < NCT; ++ct) {
+          u4 bw[NB];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            __bf16 pc[NB];
-            split_pieces<NB>(bvf[pp][ct][e], pc);
+          for (int w = 0; w < 4; ++w) {
+            unsigned pk[NB];
+            split_pieces2<NB>(bvf[pp][ct][2 * w], bvf[pp][ct][2 * w + 1], pk);
 #pragma unroll
-            for (int i = 0; i < NB; ++i) bv[i][ct][e] = pc[i];
+            for (int i = 0; i < NB; ++i) bw[i][w] = pk[i];
           }
+#pragma unroll
+          for (int i = 0; i < NB; ++i) bv[i][ct] = __builtin_bit_cast(bf8, bw[i]);
+        }
 #pragma unroll
         for (int qt = 0; qt < 4; ++qt) {
           bf8 av[NB];
@@ -565,34 +607,27 @@ __global__ void __launch_bounds__(256) mfma_wide_synthesis_kernel(PlanDev P, con
         }
       }
     } else {
-      __bf16 pc[NB][2][16];   // [piece][parity][value]
-      ring_steps(ring, Arow + i0, [&](int j, double v) {
-        __bf16 q[NB];
-        split_pieces<NB>((float)v, q);
-#pragma unroll
-        for (int i = 0; i < NB; ++i) pc[i][j & 1][j >> 1] = q[i];
-      });
+      float ev[2][16];   // [parity][value]
+      ring_steps(ring, Arow + i0, [&](int j, double v) { ev[j & 1][j >> 1] = (float)v; });
 #pragma unroll
       for (int pp = 0; pp < 2; ++pp) {
+        // pieces of this parity's 16 values, two values per dword: dwords 0..3 hold values
+        // 0..7, dwords 4..7 values 8..15
+        unsigned pk[8][NB];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) split_pieces2<NB>(ev[pp][2 * w], ev[pp][2 * w + 1], pk[w]);
         bf8 A0[NB], A1[NB], B[NT][NB];
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
 #pragma unroll
           for (int n = 0; n < NT; ++n)
             B[n][i] = *reinterpret_cast<const bf8*>(&lds_b[buf][i][pp][32 * n + (lane & 31)][8 * (lane >> 5)]);
-          bf8 x, y;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            x[e] = pc[i][pp][e];
-            y[e] = pc[i][pp][8 + e];
-          }
           typedef unsigned u4 __attribute__((ext_vector_type(4)));
-          const u4 xu = __builtin_bit_cast(u4, x), yu = __builtin_bit_cast(u4, y);
           u4 lo, hi;
 #pragma unroll
           for (int w = 0; w < 4; ++w) {
             unsigned l_, h_;
-            swap_halves(xu[w], yu[w], l_, h_);
+            swap_halves(pk[w][i], pk[4 + w][i], l_, h_);
             lo[w] = l_;
             hi[w] = h_;
           }
