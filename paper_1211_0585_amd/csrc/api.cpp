@@ -438,6 +438,8 @@ int plan_alloc(wf_plan_s* p) {
   D.twiddle32 = g.tw32;
   D.chirp32 = g.chirp32;
   D.bluestein32 = g.blue32;
+  D.mixtw = g.mixtw;
+  D.mixtw32 = g.mixtw32;
   D.rows_total = g.rows_total;
   return WF_OK;
 }

@@ -85,6 +85,12 @@ int build_geometry(Geometry& g) {
       rp.log2n = ilog2_ceil(gn.nphi);
       rp.bl_M = 0;
       g.tw_len = std::max(g.tw_len, gn.nphi);
+    } else if ((rp.mix = mixed_radix_passes(gn.nphi)) != 0) {
+      // 2^a 3^b 5^c 7^d points: radix-2/4/8 passes (their twiddles from the power-of-two
+      // table, as for a 2^a-point transform), then the odd passes
+      rp.log2n = -1;
+      rp.bl_M = 0;
+      g.tw_len = std::max(g.tw_len, gn.nphi & -gn.nphi);
     } else {
       rp.log2n = -1;
       rp.bl_M = 1 << ilog2_ceil(2 * gn.nphi - 1);
@@ -119,12 +125,30 @@ int build_geometry(Geometry& g) {
       for (int k = 0; k < M; ++k) blue.push_back(make_double2((double)h[k].real(), (double)h[k].imag()));
     }
     for (auto& rp : pairs)
-      if (rp.log2n < 0) {
+      if (rp.bl_M > 0) {
         rp.bl_off = off_of[rp.nphi];
         rp.chirp_off = coff_of[rp.nphi];
       }
     if (blue.empty()) blue.push_back(make_double2(0.0, 0.0));
     if (chirp.empty()) chirp.push_back(make_double2(0.0, 0.0));
+  }
+  // ---- mixed-radix rings: exp(-2 pi i t / n), t < n, per distinct length
+  std::vector<double2> mixtw;
+  {
+    std::vector<int64_t> off_of(4 * nside + 1, -1);
+    for (auto& rp : pairs) {
+      if (!rp.mix) continue;
+      const int n = rp.nphi;
+      if (off_of[n] < 0) {
+        off_of[n] = (int64_t)mixtw.size();
+        for (int t = 0; t < n; ++t) {
+          const long double ang = -2.0L * PI_L * (long double)t / (long double)n;
+          mixtw.push_back(make_double2((double)cosl(ang), (double)sinl(ang)));
+        }
+      }
+      rp.bl_off = off_of[n];
+    }
+    if (mixtw.empty()) mixtw.push_back(make_double2(0.0, 0.0));
   }
   std::vector<double2> tw(g.tw_len / 2);
   for (int k = 0; k < g.tw_len / 2; ++k) {
@@ -192,6 +216,8 @@ int build_geometry(Geometry& g) {
   if ((rc = M.upload(&g.tw32, to32(tw)))) return rc;
   if ((rc = M.upload(&g.chirp32, to32(chirp)))) return rc;
   if ((rc = M.upload(&g.blue32, to32(blue)))) return rc;
+  if ((rc = M.upload(&g.mixtw, mixtw))) return rc;
+  if ((rc = M.upload(&g.mixtw32, to32(mixtw)))) return rc;
 
   // ---- ring launch classes by transform kind and length
   {
@@ -199,10 +225,15 @@ int build_geometry(Geometry& g) {
     int lens[2][NRING_CLASSES];
     for (auto& row : lens)
       for (int& l : row) l = 4;
+    // a ring that is not a power of two (mixed radix or Bluestein) goes with the Bluestein
+    // rings, its class length at least twice its own (the kernels of that kind assume it)
+    auto class_len = [&](const RingPair& rp) {
+      return rp.bl_M > 0 ? rp.bl_M : (rp.mix ? 2 * rp.nphi : rp.nphi);
+    };
     for (int q = 0; q < g.npairs; ++q) {
-      const bool blue = pairs[q].log2n < 0;
-      const int L = blue ? pairs[q].bl_M : pairs[q].nphi;
-      const int c0 = blue ? 0 : 1;                    // few maps: by kind only
+      const bool npot = pairs[q].log2n < 0;
+      const int L = class_len(pairs[q]);
+      const int c0 = npot ? 0 : 1;                    // few maps: by kind only
       const int c1 = L <= SMALL_FFT ? 2 : c0;          // batched: short ones apart
       lists[0][c0].push_back(q);
       lens[0][c0] = std::max(lens[0][c0], L);
@@ -216,13 +247,17 @@ int build_geometry(Geometry& g) {
         g.ring_cls[k][c] = RingClass{d, (int32_t)lists[k][c].size(), lens[k][c]};
       }
     // Bluestein rings of the longest transform apart from the shorter ones: at the
-    // longest length alone they can hold all of the chip's LDS
+    // longest length alone they can hold all of the chip's LDS. The mixed-radix rings go
+    // with the shorter ones at their own length: these two launches run only the plain
+    // ring kernel, whose transforms need n <= 4 MAXB NT, not the half-length bound of
+    // the class lists (with the longest ones, or at twice their length, they made the
+    // one-map ring phase 5 and 16 us slower).
     std::vector<int32_t> bl[2];
     int bl_len[2] = {4, 4};
     for (int q : lists[0][0]) {
       const int k = pairs[q].bl_M == lens[0][0] ? 0 : 1;
       bl[k].push_back(q);
-      bl_len[k] = std::max(bl_len[k], pairs[q].bl_M);
+      bl_len[k] = std::max(bl_len[k], pairs[q].mix ? pairs[q].nphi : class_len(pairs[q]));
     }
     for (int k = 0; k < 2; ++k) {
       int32_t* d = nullptr;

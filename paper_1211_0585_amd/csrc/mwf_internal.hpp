@@ -38,11 +38,31 @@ struct RingPair {
   int32_t log2n;     // log2(nphi) if nphi is a power of two, else -1
   int32_t ph_num;    // longitude of pixel 0 = pi * ph_num / ph_den
   int32_t ph_den;
-  int32_t bl_M;      // Bluestein convolution length (0 for power-of-two rings)
-  int32_t pad_;
-  int64_t bl_off;    // offset (complex entries) of this length's filter in the Bluestein table
+  int32_t bl_M;      // Bluestein convolution length (0 for power-of-two and mixed-radix rings)
+  int32_t mix;       // mixed-radix rings (nphi = 2^a 3^b 5^c 7^d, not a power of two):
+                     // b | c << 4 | d << 8, the odd passes after the radix-2/4/8 ones; else 0
+  int64_t bl_off;    // Bluestein rings: offset (complex entries) of this length's filter in the
+                     // Bluestein table; mixed-radix rings: of exp(-2 pi i t / nphi), t < nphi,
+                     // in the mixed-radix table
   int64_t chirp_off; // offset (complex entries) of this length's chirp exp(-i pi j^2 / n)
 };
+
+// Odd radix passes of an n-point mixed-radix ring transform: n = 2^a o with o > 1 a product
+// of 3, 5 and 7 only (returns the packed counts b | c << 4 | d << 8), else 0 (a power of two,
+// or a prime factor above 7: Bluestein).
+__host__ __device__ inline int32_t mixed_radix_passes(int n) {
+  int o = n;
+  while (o > 1 && (o & 1) == 0) o >>= 1;
+  if (o == 1) return 0;
+  int c[3] = {0, 0, 0};
+  const int r[3] = {3, 5, 7};
+  for (int k = 0; k < 3; ++k)
+    while (o % r[k] == 0) {
+      o /= r[k];
+      c[k] += 1;
+    }
+  return o == 1 ? (c[0] | c[1] << 4 | c[2] << 8) : 0;
+}
 
 // Scaling of the Legendre recurrence: a value is carried as v * 2^(-SCALE_BITS * s)
 // with an integer s >= 0. While s > 0 the value is below 2^(64 - SCALE_BITS)
@@ -124,6 +144,8 @@ struct PlanDev {
   const float2* twiddle32;   // the same three tables rounded to float (FP32 plans)
   const float2* chirp32;
   const float2* bluestein32;
+  const double2* mixtw;      // exp(-2 pi i t / n), t < n, per distinct mixed-radix ring length n
+  const float2* mixtw32;
   int64_t rows_total;        // length of the padded per-m row layout of A / C / bcoef
   const int32_t* row_m;      // [rows_total] m of each padded row
 };
@@ -211,10 +233,10 @@ struct RingClass {
   int32_t fft_len;
 };
 
-// Ring launches: class 0 Bluestein rings and class 1 power-of-two rings (512
-// threads each), class 2 transforms of at most 1024 points (one wave per ring
-// pair; used from RING_SPLIT_MAPS maps on, when classes 0 and 1 hold only the
-// longer transforms).
+// Ring launches: class 0 rings that are not a power of two (Bluestein and mixed radix,
+// 512 threads) and class 1 power-of-two rings (256 threads), class 2 transforms of at
+// most 1024 points (one wave per ring pair; used from RING_SPLIT_MAPS maps on, when
+// classes 0 and 1 hold only the longer transforms).
 constexpr int NRING_CLASSES = 3;
 constexpr int RING_SPLIT_MAPS = 4;
 

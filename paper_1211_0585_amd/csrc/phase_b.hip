@@ -21,13 +21,16 @@
 //
 // Ring lengths are 4 i (polar caps) or 4 nside (belt). Powers of two use an
 // in-place Stockham FFT (radix 8, with radix-4 passes for log2 n not a multiple
-// of 3) whose butterflies are staged in registers between two barriers per pass; other
-// lengths use Bluestein's chirp-z method: chirp, power-of-two FFT of length
+// of 3) whose butterflies are staged in registers between two barriers per pass.
+// Lengths 2^a 3^b 5^c 7^d use the same Stockham FFT with mixed radices: the radix-2/4/8
+// passes over the whole length, then radix-3, 5 and 7 passes. Lengths with a larger
+// prime factor use Bluestein's chirp-z method: chirp, power-of-two FFT of length
 // M >= 2 n - 1, multiply by the plan-time filter spectrum, inverse FFT, chirp.
 // The FFT arithmetic type C is double for FP64 plans and float for plans that
 // store maps and ring coefficients in float. Ring pairs are launched in classes:
-// Bluestein rings and power-of-two rings separately (512 and 256 threads, LDS sized
-// to the class: the Bluestein length is about twice the ring's), and, from 4 maps
+// rings that are not a power of two (mixed radix and Bluestein) and power-of-two rings
+// separately (512 and 256 threads, LDS sized to the class: the Bluestein length is about
+// twice the ring's, and a mixed-radix ring counts twice its length), and, from 4 maps
 // on, transforms of at most 1024 points one wave per ring pair, so short polar
 // rings do not leave most of a large workgroup idle. Each workgroup stages the
 // twiddles of its ring's transform in LDS next to the data, one table per pass
@@ -141,6 +144,63 @@ __device__ __forceinline__ void dft8(V* v, S sd) {
   v[7] = csub(e3, t3);
 }
 
+// cos and sin of 2 pi s / R, s = 1 .. (R - 1) / 2, for the odd radices.
+template <int R>
+struct OddRoots;
+template <>
+struct OddRoots<3> {
+  static constexpr double c[1] = {-0.5};
+  static constexpr double s[1] = {0.866025403784438646764};
+};
+template <>
+struct OddRoots<5> {
+  static constexpr double c[2] = {0.309016994374947424102, -0.809016994374947424102};
+  static constexpr double s[2] = {0.951056516295153572116, 0.587785252292473129169};
+};
+template <>
+struct OddRoots<7> {
+  static constexpr double c[3] = {0.623489801858733530525, -0.222520933956314404289, -0.900968867902419126236};
+  static constexpr double s[3] = {0.781831482468029808708, 0.974927912181823607018, 0.433883739117558120476};
+};
+
+// Radix-R DFT of u[0..R-1] in registers for odd R (sd = -1 forward, +1 inverse), by the
+// symmetric pairs a_r = u_r + u_{R-r}, b_r = u_r - u_{R-r}, r = 1 .. H = (R - 1) / 2:
+//   y_0 = u_0 + sum_r a_r,  y_s, y_{R-s} = u_0 + sum_r a_r cos(2 pi r s / R)
+//                                         +- i sd sum_r b_r sin(2 pi r s / R).
+template <int R, class V, class S>
+__device__ __forceinline__ void dft_odd(V* u, S sd) {
+  constexpr int H = (R - 1) / 2;
+  V a[H], b[H];
+#pragma unroll
+  for (int r = 1; r <= H; ++r) {
+    a[r - 1] = cadd(u[r], u[R - r]);
+    b[r - 1] = csub(u[r], u[R - r]);
+  }
+  V y[R];
+  y[0] = u[0];
+#pragma unroll
+  for (int r = 1; r <= H; ++r) y[0] = cadd(y[0], a[r - 1]);
+#pragma unroll
+  for (int t = 1; t <= H; ++t) {
+    V A = u[0], B = {0, 0};
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+      const int m = (r * t) % R;                       // cos / sin of 2 pi m / R
+      const S c = (S)OddRoots<R>::c[(m <= H ? m : R - m) - 1];
+      const S sn = (S)(m <= H ? OddRoots<R>::s[m - 1] : -OddRoots<R>::s[R - m - 1]);
+      A.x += c * a[r - 1].x;
+      A.y += c * a[r - 1].y;
+      B.x += sn * b[r - 1].x;
+      B.y += sn * b[r - 1].y;
+    }
+    const V iB = cmul_is(B, sd);
+    y[t] = cadd(A, iB);
+    y[R - t] = csub(A, iB);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) u[r] = y[r];
+}
+
 // One radix-R pass (R = 2, 4 or 8) of an in-place Stockham FFT of length L in LDS,
 // after Ns points have been combined: butterfly j (j < L / R, k = j mod Ns) takes
 // input r < R from element j + r L / R, multiplies it by w^r with w = exp(dir 2 pi i
@@ -246,6 +306,100 @@ __device__ __forceinline__ void fft_pow2(typename CT<C>::V* x, int lg, int dir,
   }
 }
 
+// One odd radix-R pass (R = 3, 5 or 7) of a mixed-radix Stockham FFT of length L, the
+// same butterflies, index map and layouts as stockham_pass with k = j mod Ns for any Ns;
+// the powers w^r = exp(dir 2 pi i r k / (R Ns)) are read from T[t] = exp(-2 pi i t / L)
+// at t = r k L / (R Ns) (tstride = L / (R Ns); conjugated for dir = +1).
+template <class C, int NT, int R, int NBF>
+__device__ __forceinline__ void stockham_pass_odd(typename CT<C>::V* x, int L, int Ns, int dir, bool pad_in,
+                                                  bool pad_out, const typename CT<C>::V* __restrict__ T,
+                                                  int tstride) {
+  using V = typename CT<C>::V;
+  const int tid = threadIdx.x;
+  const C sd = (C)dir;
+  const int nb = L / R;
+  auto at = [](int e, bool pad) { return pad ? e + (e >> 4) : e; };
+  V v[R * NBF];
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int j = tid + b * NT;
+    if (j < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[R * b + r] = x[at(j + r * nb, pad_in)];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < NBF; ++b) {
+    const int j = tid + b * NT;
+    if (j < nb) {
+      const int k = j % Ns;
+      V* u = v + R * b;
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        V w = T[r * k * tstride];
+        if (dir > 0) w.y = -w.y;
+        u[r] = cmul(u[r], w);
+      }
+      dft_odd<R>(u, sd);
+      const int idx = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[at(idx + r * Ns, pad_out)] = u[r];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place mixed-radix Stockham FFT of n = 2^a 3^b 5^c 7^d points (mix = b | c << 4 |
+// d << 8) in LDS: the radix-2/4/8 passes of a 2^a-point transform over the whole length
+// (their twiddles, which depend only on R Ns, are wt as for fft_pow2 of a), then b radix-3,
+// c radix-5 and d radix-7 passes (twiddles from T[t] = exp(-2 pi i t / n)). Layouts,
+// direction and synchronisation as fft_pow2; n <= 4 MAXB NT.
+template <class C, int NT, int MAXB>
+__device__ __forceinline__ void fft_mixed(typename CT<C>::V* x, int n, int mix, int dir,
+                                          const typename CT<C>::V* __restrict__ wt,
+                                          const typename CT<C>::V* __restrict__ T) {
+  constexpr int NB8 = (MAXB + 1) / 2;
+  const int lg = __ffs(n) - 1;
+  int n2, n4, n8;
+  fft_schedule(lg, &n2, &n4, &n8);
+  const int n3 = mix & 15, n5 = (mix >> 4) & 15, n7 = (mix >> 8) & 15;
+  const int last = n2 + n4 + n8 + n3 + n5 + n7 - 1;
+  int Ns = 1, p = 0, off = 0;
+  auto next = [&](int R) {
+    off += Ns > 1 ? Ns : 0;
+    Ns *= R;
+    ++p;
+  };
+  if (n2) {
+    stockham_pass<C, NT, 2, 2 * MAXB>(x, n, Ns, dir, p > 0, p < last, wt + off);
+    next(2);
+  }
+  for (int q = 0; q < n4; ++q) {
+    stockham_pass<C, NT, 4, MAXB>(x, n, Ns, dir, p > 0, p < last, wt + off);
+    next(4);
+  }
+  for (int q = 0; q < n8; ++q) {
+    stockham_pass<C, NT, 8, NB8>(x, n, Ns, dir, p > 0, p < last, wt + off);
+    next(8);
+  }
+  for (int q = 0; q < n3; ++q) {
+    stockham_pass_odd<C, NT, 3, (4 * MAXB + 2) / 3>(x, n, Ns, dir, p > 0, p < last, T, n / (3 * Ns));
+    Ns *= 3;
+    ++p;
+  }
+  for (int q = 0; q < n5; ++q) {
+    stockham_pass_odd<C, NT, 5, (4 * MAXB + 4) / 5>(x, n, Ns, dir, p > 0, p < last, T, n / (5 * Ns));
+    Ns *= 5;
+    ++p;
+  }
+  for (int q = 0; q < n7; ++q) {
+    stockham_pass_odd<C, NT, 7, (4 * MAXB + 6) / 7>(x, n, Ns, dir, p > 0, p < last, T, n / (7 * Ns));
+    Ns *= 7;
+    ++p;
+  }
+}
+
 // Plan-table index of entry e of the per-pass twiddle tables of a 2^lg-point
 // transform: for each pass with Ns > 1 (in pass order), entries off + k, k < Ns, hold
 // exp(-2 pi i k / (R Ns)) = glob[k glob_len / (R Ns)] of the plan's table glob[t] =
@@ -342,28 +496,42 @@ struct Tabs<double> {
   __device__ static const double2* tw(const PlanDev& P) { return P.twiddle; }
   __device__ static const double2* chirp(const PlanDev& P) { return P.chirp; }
   __device__ static const double2* blue(const PlanDev& P) { return P.bluestein; }
+  __device__ static const double2* mix(const PlanDev& P) { return P.mixtw; }
 };
 template <>
 struct Tabs<float> {
   __device__ static const float2* tw(const PlanDev& P) { return P.twiddle32; }
   __device__ static const float2* chirp(const PlanDev& P) { return P.chirp32; }
   __device__ static const float2* blue(const PlanDev& P) { return P.bluestein32; }
+  __device__ static const float2* mix(const PlanDev& P) { return P.mixtw32; }
 };
 
-// The ring's transform (n points, or Bluestein over M), with the per-pass twiddles
-// of its length staged in LDS (twl). KIND 0: the launch holds only power-of-two
-// rings, 1: only Bluestein rings, 2: both. The Bluestein chirp and filter spectrum
-// are loaded per transform (held across the workgroup they cost occupancy).
+// The ring's transform (n points, mixed radix over n, or Bluestein over M), with the
+// per-pass twiddles of its power-of-two length (n, the 2^a of a mixed-radix length, or M)
+// staged in LDS (twl). KIND 0: the launch holds only power-of-two rings, 1: only rings
+// that are not (mixed radix and Bluestein, n at most half the class length), 2: any.
+// The Bluestein chirp and filter spectrum are loaded per transform (held across the
+// workgroup they cost occupancy).
 template <class C, int NT, int MAXB, int KIND>
 __device__ __forceinline__ void ring_dft(typename CT<C>::V* buf, const typename CT<C>::V* twl,
                                          const RingPair& rp, int dir, const PlanDev& P) {
-  if (KIND == 0 || (KIND == 2 && rp.log2n >= 0)) {
+  if (KIND != 1 && rp.log2n >= 0) {
     fft_pow2<C, NT, MAXB>(buf, rp.log2n, dir, twl);
+  } else if (KIND != 0 && rp.mix != 0) {
+    fft_mixed<C, NT, MAXB>(buf, rp.nphi, rp.mix, dir, twl, Tabs<C>::mix(P) + rp.bl_off);
   } else {
-    BlueRegs<C, NT, MAXB> br;
-    br.load(rp.nphi, rp.bl_M, Tabs<C>::chirp(P) + rp.chirp_off, Tabs<C>::blue(P) + rp.bl_off);
-    dft_bluestein<C, NT, MAXB>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, br, twl);
+    if constexpr (KIND != 0) {
+      BlueRegs<C, NT, MAXB> br;
+      br.load(rp.nphi, rp.bl_M, Tabs<C>::chirp(P) + rp.chirp_off, Tabs<C>::blue(P) + rp.bl_off);
+      dft_bluestein<C, NT, MAXB>(buf, rp.nphi, rp.bl_M, __ffs(rp.bl_M) - 1, dir, br, twl);
+    }
   }
+}
+
+// log2 of the power-of-two transform whose per-pass twiddles a ring stages: n, the 2^a
+// of a mixed-radix n, or the Bluestein length M.
+__device__ __forceinline__ int ring_twiddle_lg(const RingPair& rp) {
+  return rp.log2n >= 0 ? rp.log2n : (rp.bl_M > 0 ? __ffs(rp.bl_M) - 1 : __ffs(rp.nphi) - 1);
 }
 
 // Kind of transforms in a ring launch class (see ring_dft).
@@ -617,7 +785,7 @@ __device__ __forceinline__ void phase_b_body(const PlanDev& P, const PhaseBArgs&
   V* twl = buf + fft_padded(buf_elems);
   constexpr int TWP = (2 * MAXB + 2) / 3;
   static_assert(TWP <= 3, "twiddle prefetch holds at most three entries per thread");
-  const int tw_lg = rp.log2n >= 0 ? rp.log2n : __ffs(rp.bl_M) - 1;
+  const int tw_lg = ring_twiddle_lg(rp);
   const int tw_n = fft_twiddle_entries(tw_lg);
   const V* __restrict__ twg = Tabs<C>::tw(P);
   auto tw_load = [&](int e) { return e < tw_n ? twg[twiddle_glob_index(tw_lg, e, P.tw_len)] : CT<C>::make(0, 0); };
@@ -764,7 +932,7 @@ __device__ __forceinline__ void phase_b_pol_body(const PlanDev& P, const PolRing
   const int64_t mbase = (int64_t)map * 3 * P.npix;
 
   V* twl = buf + fft_padded(buf_elems);
-  const int tw_lg = rp.log2n >= 0 ? rp.log2n : __ffs(rp.bl_M) - 1;
+  const int tw_lg = ring_twiddle_lg(rp);
   const int tw_n = fft_twiddle_entries(tw_lg);
   const V* __restrict__ twg = Tabs<C>::tw(P);
   auto stage_twiddles = [&]() {

@@ -372,6 +372,8 @@ int wf_pol_plan(wf_pol_plan_t* out, int32_t nside, int32_t lmax, const double* c
   D.twiddle32 = g.tw32;
   D.chirp32 = g.chirp32;
   D.bluestein32 = g.blue32;
+  D.mixtw = g.mixtw;
+  D.mixtw32 = g.mixtw32;
   D.rows_total = g.rows_total;
   *out = p;
   return WF_OK;

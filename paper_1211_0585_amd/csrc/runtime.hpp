@@ -84,6 +84,8 @@ struct Geometry {
   float2* tw32 = nullptr;
   float2* chirp32 = nullptr;
   float2* blue32 = nullptr;
+  double2* mixtw = nullptr;            // mixed-radix ring tables exp(-2 pi i t / n)
+  float2* mixtw32 = nullptr;
   // work lists, longest first
   WorkItem* items_ana = nullptr;       // FP64 analysis (ring_block_ana), packed into bins
   WorkItem* items_syn = nullptr;       // FP64 synthesis (ring_block_syn), packed into bins
