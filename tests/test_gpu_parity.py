@@ -63,6 +63,30 @@ def test_sht_pair_parity(torch_dev, nside, lmax):
         assert e2 <= SHT_TOL
 
 
+@pytest.mark.parametrize("nside,lmax,nmaps", [(32, 48, 5), (256, 64, 4)])
+def test_sht_pair_parity_batched_ring_classes(torch_dev, nside, lmax, nmaps):
+    """From 4 maps on the ring transforms run in the batched launch classes (one wave per
+    ring pair up to 1024 points, the other classes beyond): every map of such a batch
+    against the oracle, both directions. At Nside 256 the mixed-radix rings of more than 512
+    points (e.g. 540 = 4 * 135) run in the class of the long rings, the shorter ones and the
+    Bluestein rings of up to 1024 points one wave per pair."""
+    torch = torch_dev
+    _log("sht batched classes", nside, lmax, nmaps)
+    rs = np.random.default_rng(nside + 11 * nmaps)
+    f = rs.standard_normal((nmaps, 12 * nside * nside))
+    a = np.stack([random_alm(lmax, 100 * nside + k) for k in range(nmaps)])
+    with _plan(nside, lmax, max_batch=nmaps) as p:
+        g_alm = p.map2alm(torch.from_numpy(f).cuda()).cpu().numpy()
+        g_map = p.alm2map(torch.from_numpy(a).cuda()).cpu().numpy()
+        p.sync()
+    for k in range(nmaps):
+        e1 = alm_rel_l2(g_alm[k], sht.map2alm(f[k], nside, lmax), lmax)
+        e2 = rel_l2(g_map[k], sht.alm2map(a[k], nside, lmax))
+        _log("  map", k, "map2alm err", e1, "alm2map err", e2)
+        assert e1 <= SHT_TOL
+        assert e2 <= SHT_TOL
+
+
 def test_sht_batch_matches_single(torch_dev):
     torch = torch_dev
     nside, lmax = 32, 64
