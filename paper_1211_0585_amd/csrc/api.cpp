@@ -268,7 +268,18 @@ int run_phase_b(wf_plan_s* p, hipStream_t s, int mode, int nmaps, double lam, co
   const int split = nmaps >= RING_SPLIT_MAPS ? 1 : 0;
   const RingClass* cls = g.ring_cls[split];
   const bool fp32 = p->dtype != WF_F64;
-  if (split || cls[0].count == 0 || cls[1].count == 0) {
+  if (split) {
+    // the rings of the longest transforms, the other long ones that are not a power of two
+    // at their own lengths, the long power-of-two rings, the short ones one wave per pair
+    TIMED(0, {
+      MWF_HIP(launch_phase_b_class(p->dev, a, g.long_split[0], 0, fp32, s));
+      MWF_HIP(launch_phase_b_class(p->dev, a, g.long_split[1], 0, fp32, s));
+      MWF_HIP(launch_phase_b_class(p->dev, a, cls[1], 1, fp32, s));
+      MWF_HIP(launch_phase_b_class(p->dev, a, cls[2], 2, fp32, s));
+    });
+    return WF_OK;
+  }
+  if (cls[0].count == 0 || cls[1].count == 0) {
     TIMED(0, MWF_HIP(launch_phase_b(p->dev, a, cls, fp32, s)));
     return WF_OK;
   }

@@ -264,6 +264,20 @@ int build_geometry(Geometry& g) {
       if ((rc = M.upload(&d, bl[k]))) return rc;
       g.blue_split[k] = RingClass{d, (int32_t)bl[k].size(), bl_len[k]};
     }
+    // the same split of the batched class 0: at 64 maps the 2048-point Bluestein rings and
+    // the long mixed-radix rings ran in the launch sized for the 4096-point ones
+    std::vector<int32_t> ls[2];
+    int ls_len[2] = {4, 4};
+    for (int q : lists[1][0]) {
+      const int k = pairs[q].bl_M == lens[1][0] ? 0 : 1;
+      ls[k].push_back(q);
+      ls_len[k] = std::max(ls_len[k], pairs[q].mix ? pairs[q].nphi : class_len(pairs[q]));
+    }
+    for (int k = 0; k < 2; ++k) {
+      int32_t* d = nullptr;
+      if ((rc = M.upload(&d, ls[k]))) return rc;
+      g.long_split[k] = RingClass{d, (int32_t)ls[k].size(), ls_len[k]};
+    }
   }
 
   // ---- polar skip: ring pairs whose lambda_lm never leaves the negligible range

@@ -103,6 +103,10 @@ struct Geometry {
   // few-maps plan launches: the Bluestein rings split by transform length, [0] those
   // of the longest M, [1] the rest (each launch's LDS sized to its own length)
   RingClass blue_split[2]{};
+  // the batched class 0 (rings that are not a power of two, longer than SMALL_FFT) split the
+  // same way for a plan's own launches: [0] the longest transforms, [1] the others at their
+  // own lengths (mixed radix at n, not 2 n)
+  RingClass long_split[2]{};
   DevMem mem;
 };
 
