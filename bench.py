@@ -74,8 +74,8 @@ def parse():
     ap.add_argument("--pol-sweeps", type=int, default=40,
                     help="timed sweeps of the polarised (T, Q, U) FP64 workload at Nside 512; 0 skips it")
     ap.add_argument("--cpu-full", type=int, default=0,
-                    help="1: time the oracle on the plan of the baseline notes (>= 3 sweeps on all "
-                         "cores, 1 sweep on one core, the small-band 140-sweep solve); minutes of CPU")
+                    help="1: time the oracle more fully (>= 3 sweeps on all cores, 1 sweep on one "
+                         "core, the small-band 140-sweep solve); minutes of CPU")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run N plain 512 MiB device copies (reference for HBM byte counters)")
     return ap.parse_args()
@@ -89,7 +89,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
-              "layout is a design note, not part of this build.", file=sys.stderr)
+              "layout is a design note; the library runs on one GPU.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -55,7 +55,7 @@ enum {
   WF_EINVAL = -1,       /* invalid argument (message in wf_last_error)          */
   WF_ENOMEM = -2,       /* device or host allocation failed / over budget        */
   WF_EDEVICE = -3,      /* HIP runtime error                                      */
-  WF_EUNSUPPORTED = -4, /* valid request this build does not handle               */
+  WF_EUNSUPPORTED = -4, /* valid request the library does not handle              */
   WF_EBUSY = -5,        /* no free slot (serving)                                 */
   WF_ENOTREADY = -6     /* result not finished yet (serving)                      */
 };

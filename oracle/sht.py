@@ -11,8 +11,8 @@ is, on the sphere, the spherical-harmonic transform pair:
   analysis    a_lm = Omega sum_p conj(Y_lm(theta_p, phi_p)) f_p,  Omega = 4 pi / npix
 
 The analysis is the pixel-area-weighted adjoint of the synthesis (no ring
-weights, no iterative refinement): it is the reading this build adopts for the
-transform the paper leaves unspecified.
+weights, no iterative refinement): the reading adopted here for the transform
+the paper leaves unspecified.
 
 Both are split into a ring part (a discrete Fourier sum along each iso-latitude
 ring) and a Legendre part (a sum over rings / over l for each m). The ring
