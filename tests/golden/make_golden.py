@@ -6,7 +6,8 @@ then the oracle messenger solve for the first 2 sweeps and for the full
 80-sweep schedule. Stores the norm, first entries and seeded random projections
 of d (so a test can check an input it builds itself), sampled outputs (seeded
 pixel and alm indices), the norms of the full outputs and their projections on
-seeded random vectors.
+seeded random vectors, and per ring and per m the norm and the projection on one
+seeded random vector.
 
 Run from the repository root:  python tests/golden/make_golden.py
 (about an hour on 8 CPU cores).
@@ -21,7 +22,9 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 from oracle import healpix, messenger, sht  # noqa: E402
+from oracle.legendre import alm_index  # noqa: E402
 from paper_1211_0585_amd import synth  # noqa: E402
+from make_golden_1024 import m_norms, ring_norms  # noqa: E402  (same directory)
 
 NSIDE, LMAX = 512, 1024
 OUT = os.path.join(ROOT, "tests", "golden", "nside512_satellite.npz")
@@ -40,6 +43,19 @@ def summarize(prefix, s_map, s_alm, store):
     store[prefix + "alm_norm"] = np.sqrt(np.sum(w * np.abs(s_alm) ** 2))
     proj = np.random.default_rng(77).standard_normal((4, s_map.size))
     store[prefix + "map_proj"] = proj @ s_map
+    # per ring and per m: norms, and the projection on one seeded random vector (a local
+    # error changes it by about its own size, whatever the sign)
+    store[prefix + "ring_norm"] = ring_norms(s_map, NSIDE)
+    store[prefix + "m_norm"] = m_norms(s_alm, LMAX)
+    v = np.random.default_rng(99).standard_normal(s_map.size)
+    g = healpix.ring_info(NSIDE)
+    store[prefix + "ring_proj"] = np.array([np.dot(v[a:a + n], s_map[a:a + n]) for a, n in zip(g["start"], g["nphi"])])
+    u = np.random.default_rng(98).standard_normal(s_alm.size) + 1j * np.random.default_rng(97).standard_normal(s_alm.size)
+    mp = np.empty(LMAX + 1, dtype=np.complex128)
+    for m in range(LMAX + 1):
+        i0 = alm_index(LMAX, m, m)
+        mp[m] = np.sum(u[i0:i0 + LMAX - m + 1] * s_alm[i0:i0 + LMAX - m + 1])
+    store[prefix + "m_proj"] = mp
 
 
 def main():
