@@ -1,6 +1,7 @@
 // Plan-time tables shared by every plan of a given (device, nside, lmax):
 // HEALPix ring geometry (Gorski et al. 2005), the rescaled Legendre recurrence
-// coefficients, FFT twiddles and Bluestein tables, and the polar-skip work lists.
+// coefficients, FFT twiddles, mixed-radix and Bluestein tables, and the polar-skip work
+// lists.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,9 +18,9 @@ namespace mwf {
 namespace {
 
 constexpr long double PI_L = 3.141592653589793238462643383279502884L;
-// Ring pairs whose transform (n, or the Bluestein length M) has at most this many
-// points run one wave per pair when batched; longer ones a larger workgroup (512
-// threads for Bluestein rings, 256 for power-of-two rings).
+// Ring pairs whose class length (n; twice n for mixed radix; the Bluestein length M) is at
+// most this many points run one wave per pair when batched; longer ones a larger workgroup
+// (512 threads for rings that are not a power of two, 256 for power-of-two rings).
 constexpr int SMALL_FFT = 1024;
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }

@@ -226,7 +226,8 @@ __device__ __forceinline__ void block_sum_add(double v, double* dst) {
 }
 
 // Ring pairs launched together: a device list of pair indices and the largest
-// FFT length (power-of-two n, or the Bluestein M) among them.
+// transform length among them (power-of-two n, the Bluestein M, or a mixed-radix n, which
+// counts twice in the class lists and once in the split launches of a plan).
 struct RingClass {
   const int32_t* q;
   int32_t count;
